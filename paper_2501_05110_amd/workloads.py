@@ -1,0 +1,288 @@
+"""Seeded synthetic workloads shaped like the paper's examples.
+
+This module holds inputs only -- grids, background-field profiles, source
+shapes, scattering rates and seeded random states -- and none of the
+discretisation's arithmetic.  Both the HIP library (through its Python
+binding) and the CPU oracle draw their inputs from here, so that the two see
+identical data.
+
+Units are the code units of Table 1 (q = m = c = 1 for protons), so that
+gamma = sqrt(1 + p^2), V = p / gamma.
+
+Field callables take spatial points X of shape (3, N) (axes that a run does not
+simulate are zero) and return arrays over N:
+
+* flow(X) -> (U (3,N), dU (3,3,N) with dU[a,b] = dU_b/dx^a, dUdt (3,N))
+* magnetic(X) -> B (3,N)
+* source(X, p) -> isotropic source s (N,)   (the s of eq. monoenergetic-point-source)
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+SEED_BASE = 20250110
+
+# term names, matching the term switches of eq. vfp-terms-names
+ADVECTION, MOMENTUM, ROTATION, COLLISION, SOURCE = (
+    "advection", "momentum", "rotation", "collision", "source")
+
+# boundary kinds (Sec. 3.3 and eq. continuous-bc)
+PERIODIC, ZERO_INFLOW, CONTINUOUS = "periodic", "zero_inflow", "continuous"
+
+
+def rng(config_index: int, extra: int = 0) -> np.random.Generator:
+    return np.random.default_rng(SEED_BASE + config_index + 1000 * extra)
+
+
+# ---------------------------------------------------------------- fields --
+
+def zero_flow(X):
+    N = X.shape[1]
+    return np.zeros((3, N)), np.zeros((3, 3, N)), np.zeros((3, N))
+
+
+def uniform_flow(U):
+    U = np.asarray(U, dtype=float)
+
+    def flow(X):
+        N = X.shape[1]
+        return (np.repeat(U[:, None], N, axis=1), np.zeros((3, 3, N)),
+                np.zeros((3, N)))
+    return flow
+
+
+def shock_profile(x, U0, r, w):
+    """Planar tanh shock U(x) = U0[(r+1)/2 - (r-1)/2 tanh(x/w)] along x.
+
+    Returns (U, dU/dx, dU/dt).  The flow is steady, so its material
+    derivative is dU/dt = U dU/dx.  U0 is the downstream speed; the upstream
+    speed is r U0.
+    """
+    t = np.tanh(x / w)
+    U = U0 * ((r + 1) / 2 - (r - 1) / 2 * t)
+    dU = -U0 * (r - 1) / (2 * w) * (1 - t * t)
+    return U, dU, U * dU
+
+
+def shock_flow(U0, r, w):
+    def flow(X):
+        N = X.shape[1]
+        Ux, dUx, aUx = shock_profile(X[0], U0, r, w)
+        U = np.zeros((3, N))
+        dU = np.zeros((3, 3, N))
+        a = np.zeros((3, N))
+        U[0], dU[0, 0], a[0] = Ux, dUx, aUx
+        return U, dU, a
+    return flow
+
+
+def uniform_field(B):
+    B = np.asarray(B, dtype=float)
+    return lambda X: np.repeat(B[:, None], X.shape[1], axis=1)
+
+
+@dataclass
+class FourierField:
+    """B = B0 + sum over axes a and modes n of A_{a,n} cos(2 pi n x_a / L + phi_{a,n}).
+
+    Each A_{a,n} is perpendicular to e_a, so div B = 0.
+    """
+    B0: np.ndarray
+    amp: np.ndarray      # (3 axes, nmodes, 3 components)
+    phase: np.ndarray    # (3, nmodes)
+    length: float
+
+    def __call__(self, X):
+        B = np.repeat(np.asarray(self.B0, float)[:, None], X.shape[1], axis=1)
+        nm = self.amp.shape[1]
+        for a in range(3):
+            for k in range(nm):
+                c = np.cos(2 * math.pi * (k + 1) * X[a] / self.length + self.phase[a, k])
+                B += self.amp[a, k][:, None] * c[None, :]
+        return B
+
+
+def random_fourier_field(seed, B0=(0.0, 0.0, 1.0), nmodes=8, length=20.0,
+                         rms=0.5, box=(-10.0, 10.0), grid=48):
+    g = np.random.default_rng(seed)
+    amp = g.standard_normal((3, nmodes, 3))
+    for a in range(3):
+        amp[a, :, a] = 0.0
+    phase = g.uniform(0, 2 * math.pi, (3, nmodes))
+    fld = FourierField(np.zeros(3), amp, phase, length)
+    # rescale so that the rms of |delta B| over the cell centres is `rms`
+    h = (box[1] - box[0]) / grid
+    c = box[0] + h * (np.arange(grid) + 0.5)
+    X = np.stack([m.ravel() for m in np.meshgrid(c, c, c, indexing="ij")])
+    dB = fld(X)
+    scale = rms / math.sqrt(np.mean(np.sum(dB * dB, axis=0)))
+    return FourierField(np.asarray(B0, float), amp * scale, phase, length)
+
+
+def gaussian_source(Q, x0, lnp0, sigma_x, sigma_lnp):
+    """Isotropic injection: a Gaussian in (x, ln p) with total rate Q."""
+    def source(X, p):
+        lp = np.log(p)
+        return (Q / (2 * math.pi * sigma_x * sigma_lnp)
+                * np.exp(-(X[0] - x0) ** 2 / (2 * sigma_x ** 2))
+                * np.exp(-(lp - lnp0) ** 2 / (2 * sigma_lnp ** 2)))
+    return source
+
+
+# ------------------------------------------------------------- workloads --
+
+@dataclass
+class Workload:
+    """One run: grid, discretisation, physics switches and input fields."""
+    name: str
+    lmax: int
+    k: int
+    axes: tuple                 # e.g. ("x",), ("x","lnp"), ("x","y","z")
+    nodes: tuple                # per-axis cell boundaries (monotone arrays)
+    bc: tuple                   # per-axis (lo, hi) boundary kinds
+    terms: frozenset
+    p_fixed: float = None       # momentum magnitude if there is no ln p axis
+    flow: object = zero_flow
+    magnetic: object = None
+    nu: object = 0.0            # float or per-cell array (len = ncells)
+    source: object = None
+    mass: float = 1.0
+    charge: float = 1.0
+    steps: int = 0
+    courant: float = 0.2
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def ncells_axis(self):
+        return tuple(len(n) - 1 for n in self.nodes)
+
+    @property
+    def ncells(self):
+        return int(np.prod(self.ncells_axis))
+
+    @property
+    def n_lms(self):
+        return (self.lmax + 1) ** 2
+
+    @property
+    def n_basis(self):
+        return (self.k + 1) ** len(self.axes)
+
+    @property
+    def ndofs(self):
+        return self.ncells * self.n_basis * self.n_lms
+
+    @property
+    def shape(self):
+        return (self.ncells, self.n_basis, self.n_lms)
+
+
+def uniform_nodes(lo, hi, n):
+    return np.linspace(lo, hi, n + 1)
+
+
+def equidistant_node_coords(wl: Workload, axis: int):
+    """Coordinates of the k+1 equidistant nodes of every cell along `axis`,
+    shape (ncells_axis, k+1).  Used to sample initial data at nodes."""
+    nd = wl.nodes[axis]
+    t = np.linspace(0.0, 1.0, wl.k + 1)
+    return nd[:-1, None] + (nd[1:] - nd[:-1])[:, None] * t[None, :]
+
+
+def nodal_state(wl: Workload, func):
+    """State vector [cell][basis][lms] holding func at the equidistant nodes.
+
+    func(coords: dict axis->array (M,)) -> (n_lms, M) values.
+    """
+    K1 = wl.k + 1
+    naxis = wl.ncells_axis
+    grids = [equidistant_node_coords(wl, a) for a in range(len(wl.axes))]
+    # multi-index over (cells..., nodes...) flattened in [cell][basis] order
+    coords = {}
+    d = len(wl.axes)
+    cell_idx = np.indices(naxis[::-1]).reshape(d, -1)[::-1]     # axis0 fastest
+    node_idx = np.indices((K1,) * d).reshape(d, -1)[::-1]
+    for a, name in enumerate(wl.axes):
+        c = grids[a][cell_idx[a][:, None], node_idx[a][None, :]]
+        coords[name] = c.ravel()
+    vals = func(coords)                       # (n_lms, ncells*nb)
+    return np.ascontiguousarray(vals.T.reshape(wl.shape))
+
+
+def random_state(wl: Workload, seed: int, scale: float = 1.0):
+    return scale * np.random.default_rng(seed).standard_normal(wl.shape)
+
+
+# C1: 1-D x, fixed p, periodic, k=1, l_max=3, gamma=2, U=0, B=e_z, nu=1
+def config1(ncells=64):
+    p = math.sqrt(3.0)                     # gamma = 2
+    wl = Workload(
+        name="1d_x_lmax3_k1", lmax=3, k=1, axes=("x",),
+        nodes=(uniform_nodes(-0.5, 0.5, ncells),),
+        bc=((PERIODIC, PERIODIC),),
+        terms=frozenset({ADVECTION, ROTATION, COLLISION}),
+        p_fixed=p, flow=zero_flow, magnetic=uniform_field((0.0, 0.0, 1.0)),
+        nu=1.0, steps=100)
+    c = rng(1).standard_normal(wl.n_lms)
+    wl.meta["init"] = nodal_state(
+        wl, lambda X: c[:, None] * np.exp(-X["x"] ** 2 / (2 * 0.1 ** 2))[None, :])
+    return wl
+
+
+def shock_workload(name, nx, np_, k, lmax, U0=0.1, r=4.0, L=10.0, w_frac=0.01,
+                   nu0=1.0, lnp=(0.0, 10.0), seed=2, steps=2000, Q=0.1,
+                   lnp_inj=0.5, sigma_lnp=1.0 / 8):
+    w = w_frac * L
+    xn = uniform_nodes(-L, L, nx)
+    pn = uniform_nodes(lnp[0], lnp[1], np_)
+    pc = np.exp(0.5 * (pn[:-1] + pn[1:]))
+    nu_cell = np.repeat((nu0 * pc ** (-1.0 / 3.0))[:, None], nx, axis=1).ravel()
+    wl = Workload(
+        name=name, lmax=lmax, k=k, axes=("x", "lnp"), nodes=(xn, pn),
+        bc=((ZERO_INFLOW, CONTINUOUS), (ZERO_INFLOW, ZERO_INFLOW)),
+        terms=frozenset({ADVECTION, MOMENTUM, ROTATION, COLLISION, SOURCE}),
+        flow=shock_flow(U0, r, w), magnetic=uniform_field((1.0, 0.0, 0.0)),
+        nu=nu_cell, source=gaussian_source(Q, 0.0, lnp_inj, w, sigma_lnp),
+        steps=steps,
+        meta={"U0": U0, "r": r, "w": w, "L": L, "nu0": nu0})
+    wl.meta["init"] = random_state(wl, SEED_BASE + seed, 1e-3)
+    return wl
+
+
+# C2: 2-D (x, ln p) parallel shock, 1024 x 128, k=2, l_max=3
+def config2(nx=1024, np_=128, steps=2000):
+    return shock_workload("shock2d_x_lnp_1024x128_k2_lmax3", nx, np_, 2, 3,
+                          steps=steps, seed=2)
+
+
+# C3: 3-D x,y,z periodic, 48^3, k=2, l_max=5, fixed p (gamma=2)
+def config3(ncell=48, steps=500):
+    p = math.sqrt(3.0)
+    nodes = tuple(uniform_nodes(-10.0, 10.0, ncell) for _ in range(3))
+    B = random_fourier_field(SEED_BASE + 3)
+    wl = Workload(
+        name=f"3d_xyz_{ncell}cube_k2_lmax5", lmax=5, k=2, axes=("x", "y", "z"),
+        nodes=nodes, bc=((PERIODIC, PERIODIC),) * 3,
+        terms=frozenset({ADVECTION, ROTATION, COLLISION}),
+        p_fixed=p, flow=zero_flow, magnetic=B, nu=0.1, steps=steps)
+    xc = np.random.default_rng(SEED_BASE + 3 + 7).uniform(-10, 10, 3)
+    n = wl.n_lms
+
+    def f0(X):
+        r2 = (X["x"] - xc[0]) ** 2 + (X["y"] - xc[1]) ** 2 + (X["z"] - xc[2]) ** 2
+        out = np.zeros((n, r2.shape[0]))
+        out[0] = np.exp(-r2 / (2 * 1.5 ** 2))
+        return out
+    wl.meta["init_func"] = f0
+    wl.meta["B_field"] = B
+    return wl
+
+
+# C5: adjoint case, C2 physics on 512 x 64 cells
+def config5(nx=512, np_=64, steps=1000):
+    return shock_workload("shock2d_x_lnp_512x64_k2_lmax3", nx, np_, 2, 3,
+                          steps=steps, seed=5)

@@ -1,0 +1,20 @@
+import os
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (runs the HIP library)")
+    config.addinivalue_line("markers", "slow: CPU test that takes more than ~10 s")
+
+
+@pytest.fixture(scope="session")
+def lib():
+    """The HIP library binding (loaded, never built, by tests)."""
+    from paper_2501_05110_amd import vfp
+    return vfp.load()
