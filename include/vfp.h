@@ -1,0 +1,182 @@
+/*
+ * vfp.h -- C ABI of the MI355X library that applies and time-steps the
+ * discontinuous-Galerkin discretisation of the spherical-harmonic expanded
+ * Vlasov-Fokker-Planck system (Schween, Schulze & Reville, arXiv 2501.05110).
+ *
+ * The operator.  For the coefficient vector zeta of f_h (eq.
+ * dg-discrete-representation-solution) the library evaluates
+ *
+ *     L(zeta) = M^{-1} ( h - D zeta )                 (eq. matrix-formulation-system-odes)
+ *
+ * with M, D, h as in eq. definition-mass-and-dg-matrix: volume terms
+ * phi.(R - div beta) f - (grad phi . beta) f, upwind interior fluxes
+ * (eq. definition-upwind-flux), weak boundary fluxes (zero inflow,
+ * eq. definition-boundary-flux; "continuous", eq. continuous-bc; or periodic),
+ * advection matrices beta and reaction matrix R of
+ * eq. definitions-advection-reaction-eq built from the real spherical-harmonic
+ * matrices A^a, Omega^a, C of Sec. 2.1 (products formed at l_max+1, then
+ * truncated).  Integrals use Gauss-Legendre quadrature with k+1 points per
+ * axis; the basis is the tensor Lagrange basis on Gauss-Lobatto nodes
+ * (eq. lagrange-polynomial).  The momentum axis, when present, is ln p, with
+ * beta^{ln p} = beta^p / p.
+ *
+ * Units: the code units of Table 1 (c = 1); gamma = sqrt(1 + (p/m)^2),
+ * V = p/(gamma m), omega_a = q B_a / (gamma m).
+ *
+ * State layout (device, FP64, contiguous): zeta[cell][basis][lms] with
+ *   cell  = i0 + N0 (i1 + N1 i2)          (axis 0 fastest)
+ *   basis = j0 + (k+1)(j1 + (k+1) j2)      (j = Gauss-Lobatto node index per axis)
+ *   lms   = l(l+1) + (-1)^(s+1) m          (eq. ordering-expansion-coefficients)
+ *
+ * Conventions.
+ *   - Every function returns 0 on success or a negative VFP_E* code; the
+ *     message of the last failure on the calling thread is vfp_last_error().
+ *     Nothing is thrown across the ABI and nothing exits the process.
+ *   - Set-up calls (vfp_create .. vfp_set_*) take HOST arrays, copy them, and
+ *     are synchronous.  The library owns only its own tables and copies;
+ *     vfp_destroy frees them.
+ *   - Compute calls take DEVICE pointers owned by the caller and a stream
+ *     (a hipStream_t passed as void*; NULL = the default stream).  They only
+ *     enqueue work and never synchronise.
+ *   - Pointers to state vectors must not alias unless a call says so.
+ */
+#ifndef VFP_H
+#define VFP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define VFP_OK            0
+#define VFP_EINVAL       -1   /* bad argument */
+#define VFP_ENOMEM       -2   /* allocation failed */
+#define VFP_EDEVICE      -3   /* HIP runtime error */
+#define VFP_ESTATE       -4   /* call out of order (e.g. apply before set_mesh) */
+#define VFP_EUNSUPPORTED -5   /* valid request this build does not handle */
+
+/* axis kinds (reduced phase space xi, Sec. 2.2) */
+#define VFP_AXIS_X   0
+#define VFP_AXIS_Y   1
+#define VFP_AXIS_Z   2
+#define VFP_AXIS_LNP 3        /* logarithmic momentum; must be the last axis */
+
+/* term switches (eq. vfp-terms-names) */
+#define VFP_TERM_ADVECTION 1u  /* (U^a 1 + V A^a) d_a f                       */
+#define VFP_TERM_MOMENTUM  2u  /* momentum derivative and the dU terms of R    */
+#define VFP_TERM_ROTATION  4u  /* -omega_a Omega^a f                           */
+#define VFP_TERM_COLLISION 8u  /* nu C f                                       */
+#define VFP_TERM_SOURCE   16u  /* s                                            */
+
+/* boundary kinds per axis end */
+#define VFP_BC_PERIODIC    0
+#define VFP_BC_ZERO_INFLOW 1   /* eq. definition-boundary-flux */
+#define VFP_BC_CONTINUOUS  2   /* eq. continuous-bc            */
+
+/* point sets reported by vfp_query_points (1-D coordinates along one axis) */
+#define VFP_PTS_VOLUME 0      /* N_a (k+1) Gauss points, cell-major       */
+#define VFP_PTS_FACE   1      /* N_a + 1 cell faces                       */
+#define VFP_PTS_NODE   2      /* N_a (k+1) Gauss-Lobatto nodes, cell-major */
+
+typedef struct vfp_ctx vfp_ctx;
+
+/* Message of the last failed call on this thread ("" if none).  The string
+ * stays valid until the next failing call on the same thread. */
+const char* vfp_last_error(void);
+
+/* Create a context.
+ *   lmax       expansion degree l_max, 1..7 (n = (l_max+1)^2 coefficients)
+ *   k          DG degree, 1 or 2
+ *   naxes      1..3 axes of the reduced phase space (Sec. 4 term list: at most
+ *              three; with VFP_AXIS_LNP at most two spatial axes)
+ *   axis_kinds naxes kinds; spatial axes in x, y, z order, VFP_AXIS_LNP last
+ *   term_mask  OR of VFP_TERM_*
+ *   mass, charge  particle mass m > 0 and charge q in code units
+ * Errors: VFP_EINVAL for any value outside these ranges. */
+int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
+               unsigned term_mask, double mass, double charge);
+
+/* Free the context and every table it owns.  NULL is accepted. */
+void vfp_destroy(vfp_ctx* ctx);
+
+/* Rectilinear tensor mesh (Sec. 3.1: lines, rectangles or cuboids).
+ *   ncells[a]  cells along axis a (>= 1)
+ *   nodes[a]   host array of ncells[a]+1 strictly increasing cell boundaries
+ *              (for VFP_AXIS_LNP the boundaries are values of ln p)
+ *   bc_lo[a], bc_hi[a]  VFP_BC_* ; periodic must be set on both ends
+ * Resets all fields to zero. */
+int vfp_set_mesh(vfp_ctx* ctx, const int* ncells, const double* const* nodes,
+                 const int* bc_lo, const int* bc_hi);
+
+/* Momentum magnitude p > 0 for contexts without a ln p axis (mono-energetic
+ * runs, Sec. 4.1-4.3). */
+int vfp_set_momentum(vfp_ctx* ctx, double p);
+
+/* 1-D coordinates of a point set along one axis (see VFP_PTS_*).  If coords
+ * is NULL only *count is written.  Volume points of a cell (i0,i1,i2) and
+ * point index q = q0 + (k+1)(q1 + (k+1) q2) sit at coordinates
+ * VOLUME[a][i_a (k+1) + q_a]. */
+int vfp_query_points(const vfp_ctx* ctx, int which, int axis, double* coords,
+                     int64_t* count);
+
+/* Uniform background flow U (3 components, c = 1 units): grad U = 0 and
+ * dU/dt = 0. */
+int vfp_set_flow_uniform(vfp_ctx* ctx, const double* U);
+
+/* Planar flow U = U_x(x) e_x along axis 0 (which must be VFP_AXIS_X), given
+ * at the axis-0 VOLUME points (u, dudx, dudt: N0(k+1) values each; dudt is
+ * the material derivative dU_x/dt of eq. real-system-of-equations) and at the
+ * axis-0 FACE points (u_face: N0+1 values). */
+int vfp_set_flow_planar(vfp_ctx* ctx, const double* u, const double* dudx,
+                        const double* dudt, const double* u_face);
+
+/* Uniform magnetic field B (3 components). */
+int vfp_set_magnetic_uniform(vfp_ctx* ctx, const double* B);
+
+/* Magnetic field at every volume point: host array [cell][q][3]
+ * (ncells (k+1)^naxes 3 values).  Only for contexts without a ln p axis. */
+int vfp_set_magnetic_points(vfp_ctx* ctx, const double* B);
+
+/* Scattering frequency nu of the collision term: nu_cell (host, one value
+ * per cell) if not NULL, else the uniform value nu. */
+int vfp_set_scattering(vfp_ctx* ctx, double nu, const double* nu_cell);
+
+/* Isotropic source s (the s of eq. monoenergetic-point-source, so that
+ * s_000 = sqrt(4 pi) s) at every volume point: host array [cell][q]. */
+int vfp_set_source_points(vfp_ctx* ctx, const double* s);
+
+/* Number of degrees of freedom N = cells n (k+1)^naxes (Sec. 3.1). */
+int vfp_ndofs(const vfp_ctx* ctx, int64_t* n);
+
+/* Stable explicit step dt = courant / sum_a (beta_a,max / dxi_a,min), where
+ * beta_a,max bounds the spectral radius of beta^a over the mesh (the CFL rule
+ * of the convergence study, Sec. 4.1, summed over axes). */
+int vfp_cfl_dt(const vfp_ctx* ctx, double courant, double* dt);
+
+/* out = M^{-1}( h [with_source] - D in ).  in, out: device, ndofs doubles,
+ * must not alias. */
+int vfp_apply(vfp_ctx* ctx, const double* in, double* out, int with_source,
+              void* stream);
+
+/* One fused Runge-Kutta stage: w_out = u + cdt * L(w_in).
+ * w_in may equal u; w_out may equal u (then each cell's u is read before it
+ * is overwritten) but must not equal w_in unless w_in == u is not also
+ * needed by other cells -- i.e. w_out == w_in is rejected. */
+int vfp_stage(vfp_ctx* ctx, const double* w_in, const double* u, double* w_out,
+              double cdt, void* stream);
+
+/* Advance u by nsteps explicit fourth-order Runge-Kutta steps of size dt
+ * (the four-stage form w_i = u + c_i dt L(w_{i-1}), c = 1/4, 1/3, 1/2, 1,
+ * whose step map on this linear, autonomous system is the degree-4 Taylor
+ * polynomial of exp(dt L), as for classical RK4).  work: device scratch of
+ * 2*ndofs doubles.  u is updated in place. */
+int vfp_advance(vfp_ctx* ctx, double* u, double dt, int64_t nsteps,
+                double* work, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VFP_H */

@@ -1,0 +1,103 @@
+// Kernel argument blocks shared by the host library and the HIP kernels.
+#pragma once
+#include <cstdint>
+
+namespace vfp {
+
+constexpr int kMaxLmax = 7;
+constexpr int kMaxN = (kMaxLmax + 1) * (kMaxLmax + 1);
+constexpr int kMaxK = 2;
+constexpr int kMaxUniSlots = 24;   // max non-zeros per row of a uniform-axis face matrix
+
+// One-dimensional basis data for degree K on the reference interval [-1,1]:
+// Gauss-Lobatto Lagrange basis l_j, (K+1)-point Gauss rule (g_q, w_q), and
+// the 1-D mass matrix M1_ij = sum_q w_q l_i(g_q) l_j(g_q) (exact).
+struct Basis1D {
+  double phi[3][3];    // phi[q][j]  = l_j(g_q)
+  double tst[3][3];    // tst[i][q]  = sum_j (M1^{-1})_ij l_j(g_q) w_q
+  double dtst[3][3];   // dtst[i][q] = sum_j (M1^{-1})_ij l_j'(g_q) w_q
+  double lift[2][3];   // lift[side][i] = (M1^{-1})_{i, 0 or K}
+};
+
+// Per-row (lms) sparse rows of the spherical-harmonic matrices, stored
+// structure-of-arrays: field[slot * n + row].  Missing entries point at the
+// row itself with value 0.
+struct RowTables {
+  const int* ax_col;    // 2 slots: (l+1,m,s), (l-1,m,s)            A^x
+  const double* ax_val;
+  const double* g1_val; // same columns: (A^y Om^z - A^z Om^y)_t
+  const int* axx_col;   // 2 slots: (l+2,m,s), (l-2,m,s)            (A^x A^x)_t
+  const double* axx_val;// 3 slots: l+2, self, l-2
+  const double* g2_val; // same columns: (A^x (A^y Om^z - A^z Om^y))_t
+  const int* om_col;    // 3 matrices x 2 slots: Omega^x, Omega^y, Omega^z
+  const double* om_val;
+  const int* ayz_col;   // 2 matrices x 4 slots: A^y, A^z
+  const double* ayz_val;
+  const double* c_val;  // l(l+1)/2
+  // eigen data of A^x restricted to the (m,s) block of each row
+  const int* blk_mem;   // (lmax+1) slots: lms indices of the block members
+  const double* w_row;  // (lmax+1) slots: W[row][i]
+  const double* w_col;  // (lmax+1) slots: W[member j][pos(row)]
+  const double* lam;    // eigenvalue of characteristic pos(row)
+  // uniform-axis face matrices beta^a and |beta^a| (per spatial axis)
+  const int* fb_col[3];
+  const double* fb_val[3];
+  const int* fa_col[3];
+  const double* fa_val[3];
+  int nfb[3];
+  int nfa[3];
+};
+
+struct FieldArgs {
+  // planar flow along x (profile) -- used when the kernel is built with XPROF
+  const double* u_vol;   // [N0 (k+1)]
+  const double* du_vol;
+  const double* a_vol;
+  const double* u_face;  // [N0 + 1]
+  double U[3];           // uniform flow components (y, z always; x if !XPROF)
+  // momentum axis profiles (ln p): at volume points [Np (k+1)] and faces [Np+1]
+  const double* V_vol;
+  const double* iV_vol;   // 1/V
+  const double* idiv_vol; // m/(gamma p)
+  const double* ig_vol;   // q/(gamma m)
+  const double* iV_face;  // 1/V at p faces
+  double V0, iV0, ig0;    // fixed-momentum values
+  // p-face upwind data: code per (x point, p face): -1 beta>=0, -2 beta<=0,
+  // >= 0 index into pf_tab ([code][n][lmax+1] rows of beta_+ in the block)
+  const int* pf_code;
+  const double* pf_tab;
+  // magnetic field
+  double B[3];            // uniform B
+  const double* B_pts;    // [cell][q][3] or null
+  // scattering and source
+  double nu0;
+  const double* nu_cell;  // [cell] or null
+  const double* src;      // [cell][nb] = M^{-1} h (000 component) or null
+  // term multipliers (0 or 1)
+  double t_adv, t_mom, t_rot, t_col;
+};
+
+struct MeshArgs {
+  int n[3];               // cells per axis (1 for unused axes)
+  int ncells;
+  int bc_lo[3], bc_hi[3];
+  const double* s2h[3];   // 2 / h per cell along each axis
+};
+
+struct StageArgs {
+  const double* w_in;
+  const double* u;        // may be null when alpha == 0
+  double* w_out;
+  double alpha;           // w_out = alpha u + beta L(w_in)
+  double beta;
+  int with_source;
+};
+
+struct KernelArgs {
+  MeshArgs mesh;
+  FieldArgs fld;
+  RowTables tab;
+  StageArgs st;
+};
+
+}  // namespace vfp

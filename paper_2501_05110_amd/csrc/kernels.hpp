@@ -1,0 +1,143 @@
+// HIP kernels for the DG x spherical-harmonic operator (gfx950 / CDNA4).
+//
+// Mapping.  One lane owns one (cell, lms) pair and keeps the cell's (k+1)^D
+// nodal values of that coefficient in registers, so every basis contraction
+// (interpolation to the Gauss points, test-function contraction with the
+// inverse mass folded in, face interpolation and lift) is a compile-time
+// sequence of FMAs with no cross-lane traffic.  The lms mixing by the sparse
+// spherical-harmonic matrices needs values of other coefficients of the same
+// cell: those are exchanged through LDS.  A 256-lane workgroup holds
+// 256 / n cells (n = (l_max+1)^2).
+//
+// Operator (per cell, after the inverse mass matrix, which factorises over
+// axes and cancels the Jacobian):
+//   L = -T (G f_q) + sum_a (2/h_a) T'_a (F^a_q) + face lifts + M^{-1} h
+// with f_q the state at the Gauss points, F^a = beta^a f, G = (R - div beta) f,
+// T the tensor product of the 1-D test matrices tst (and dtst along axis a).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "kargs.hpp"
+
+namespace vfp {
+
+extern __constant__ Basis1D c_basis[kMaxK];
+
+template <int B, int E>
+struct IPow { static constexpr int v = B * IPow<B, E - 1>::v; };
+template <int B>
+struct IPow<B, 0> { static constexpr int v = 1; };
+
+// Apply a (K1 x K1) matrix M along axis AX of a D-dimensional tensor with K1
+// points per axis: out[.., q, ..] = sum_j M[q][j] in[.., j, ..].
+template <int D, int K1, int AX>
+__device__ __forceinline__ void sweep(const double* in, double* out, const double (&M)[3][3]) {
+  constexpr int NB = IPow<K1, D>::v;
+  constexpr int st = IPow<K1, AX>::v;
+#pragma unroll
+  for (int idx = 0; idx < NB; ++idx) {
+    const int q = (idx / st) % K1;
+    const int base = idx - q * st;
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < K1; ++j) acc = fma(M[q][j], in[base + j * st], acc);
+    out[idx] = acc;
+  }
+}
+
+// Contract a quadrature-point tensor with the test matrices: axis DER uses
+// dtst, the others tst (DER < 0: tst everywhere).  out += scale * result.
+template <int D, int K, int DER>
+__device__ __forceinline__ void contract_add(const double* g, double* out, double scale) {
+  constexpr int K1 = K + 1;
+  constexpr int NB = IPow<K1, D>::v;
+  const Basis1D& bs = c_basis[K - 1];
+  double t0[NB], t1[NB];
+  sweep<D, K1, 0>(g, t0, DER == 0 ? bs.dtst : bs.tst);
+  if constexpr (D == 1) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) out[i] = fma(scale, t0[i], out[i]);
+  } else if constexpr (D == 2) {
+    sweep<D, K1, 1>(t0, t1, DER == 1 ? bs.dtst : bs.tst);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) out[i] = fma(scale, t1[i], out[i]);
+  } else {
+    sweep<D, K1, 1>(t0, t1, DER == 1 ? bs.dtst : bs.tst);
+    sweep<D, K1, 2>(t1, t0, DER == 2 ? bs.dtst : bs.tst);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) out[i] = fma(scale, t0[i], out[i]);
+  }
+}
+
+// Interpolate nodal values to the Gauss points (all axes).
+template <int D, int K>
+__device__ __forceinline__ void interp(const double* w, double* f) {
+  constexpr int K1 = K + 1;
+  constexpr int NB = IPow<K1, D>::v;
+  const Basis1D& bs = c_basis[K - 1];
+  if constexpr (D == 1) {
+    sweep<1, K1, 0>(w, f, bs.phi);
+  } else if constexpr (D == 2) {
+    double t[NB];
+    sweep<2, K1, 0>(w, t, bs.phi);
+    sweep<2, K1, 1>(t, f, bs.phi);
+  } else {
+    double t[NB];
+    sweep<3, K1, 0>(w, f, bs.phi);
+    sweep<3, K1, 1>(f, t, bs.phi);
+    sweep<3, K1, 2>(t, f, bs.phi);
+  }
+}
+
+// Face helpers: a face normal to axis AX has (K+1)^(D-1) points; face index
+// fi enumerates the remaining axes in increasing order, lowest fastest.
+template <int D, int K, int AX>
+__device__ __forceinline__ int face_node_to_cell_node(int fi, int jn) {
+  constexpr int K1 = K + 1;
+  int idx = 0, st = 1, rem = fi;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int j;
+    if (a == AX) {
+      j = jn;
+    } else {
+      j = rem % K1;
+      rem /= K1;
+    }
+    idx += j * st;
+    st *= K1;
+  }
+  return idx;
+}
+
+template <int D, int K>
+__device__ __forceinline__ void face_interp(const double* nod, double* pts) {
+  constexpr int K1 = K + 1;
+  const Basis1D& bs = c_basis[K - 1];
+  if constexpr (D == 1) {
+    pts[0] = nod[0];
+  } else if constexpr (D == 2) {
+    sweep<1, K1, 0>(nod, pts, bs.phi);
+  } else {
+    double t[K1 * K1];
+    sweep<2, K1, 0>(nod, t, bs.phi);
+    sweep<2, K1, 1>(t, pts, bs.phi);
+  }
+}
+
+template <int D, int K>
+__device__ __forceinline__ void face_test(const double* pts, double* nod) {
+  constexpr int K1 = K + 1;
+  const Basis1D& bs = c_basis[K - 1];
+  if constexpr (D == 1) {
+    nod[0] = pts[0];
+  } else if constexpr (D == 2) {
+    sweep<1, K1, 0>(pts, nod, bs.tst);
+  } else {
+    double t[K1 * K1];
+    sweep<2, K1, 0>(pts, t, bs.tst);
+    sweep<2, K1, 1>(t, nod, bs.tst);
+  }
+}
+
+}  // namespace vfp

@@ -1,0 +1,926 @@
+// Host side of the C ABI in include/vfp.h: argument checking, set-up of the
+// spherical-harmonic tables and field data, and kernel launches.
+#include "vfp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "kargs.hpp"
+#include "launch.hpp"
+#include "shtab.hpp"
+
+using namespace vfp;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                            \
+  do {                                                                           \
+    hipError_t e_ = (expr);                                                      \
+    if (e_ != hipSuccess) return fail(VFP_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+// Owned device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+int upload(DevBuf& b, const void* host, size_t bytes) {
+  b.release();
+  if (bytes == 0) return VFP_OK;
+  if (std::getenv("VFP_FAIL_ALLOC")) return fail(VFP_ENOMEM, "allocation of %zu bytes refused (VFP_FAIL_ALLOC)", bytes);
+  hipError_t e = hipMalloc(&b.p, bytes);
+  if (e != hipSuccess) {
+    b.p = nullptr;
+    return fail(VFP_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  HIP_TRY(hipMemcpy(b.p, host, bytes, hipMemcpyHostToDevice));
+  return VFP_OK;
+}
+
+template <class T>
+int upload_vec(DevBuf& b, const std::vector<T>& v) { return upload(b, v.data(), v.size() * sizeof(T)); }
+
+// 1-D basis data for degree k (Gauss-Lobatto Lagrange basis, (k+1)-point
+// Gauss rule) computed in double precision.
+Basis1D make_basis(int k) {
+  Basis1D B;
+  std::memset(&B, 0, sizeof B);
+  const int K1 = k + 1;
+  std::vector<double> nodes, g, w;
+  if (k == 1) {
+    nodes = {-1.0, 1.0};
+    g = {-1.0 / std::sqrt(3.0), 1.0 / std::sqrt(3.0)};
+    w = {1.0, 1.0};
+  } else {
+    nodes = {-1.0, 0.0, 1.0};
+    g = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)};
+    w = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
+  }
+  auto lag = [&](int j, double x) {
+    double v = 1.0;
+    for (int m = 0; m < K1; ++m)
+      if (m != j) v *= (x - nodes[m]) / (nodes[j] - nodes[m]);
+    return v;
+  };
+  auto dlag = [&](int j, double x) {
+    double d = 0.0;
+    for (int m = 0; m < K1; ++m) {
+      if (m == j) continue;
+      double t = 1.0 / (nodes[j] - nodes[m]);
+      for (int i = 0; i < K1; ++i)
+        if (i != j && i != m) t *= (x - nodes[i]) / (nodes[j] - nodes[i]);
+      d += t;
+    }
+    return d;
+  };
+  double M1[3][3] = {}, Mi[3][3] = {};
+  for (int i = 0; i < K1; ++i)
+    for (int j = 0; j < K1; ++j)
+      for (int q = 0; q < K1; ++q) M1[i][j] += w[q] * lag(i, g[q]) * lag(j, g[q]);
+  // invert the small SPD matrix by Gauss-Jordan
+  double a[3][6] = {};
+  for (int i = 0; i < K1; ++i) {
+    for (int j = 0; j < K1; ++j) a[i][j] = M1[i][j];
+    a[i][K1 + i] = 1.0;
+  }
+  for (int c = 0; c < K1; ++c) {
+    double piv = a[c][c];
+    for (int j = 0; j < 2 * K1; ++j) a[c][j] /= piv;
+    for (int r = 0; r < K1; ++r)
+      if (r != c) {
+        double f = a[r][c];
+        for (int j = 0; j < 2 * K1; ++j) a[r][j] -= f * a[c][j];
+      }
+  }
+  for (int i = 0; i < K1; ++i)
+    for (int j = 0; j < K1; ++j) Mi[i][j] = a[i][K1 + j];
+  for (int q = 0; q < K1; ++q)
+    for (int j = 0; j < K1; ++j) B.phi[q][j] = lag(j, g[q]);
+  for (int i = 0; i < K1; ++i)
+    for (int q = 0; q < K1; ++q) {
+      double t = 0.0, dt = 0.0;
+      for (int j = 0; j < K1; ++j) {
+        t += Mi[i][j] * lag(j, g[q]);
+        dt += Mi[i][j] * dlag(j, g[q]);
+      }
+      B.tst[i][q] = t * w[q];
+      B.dtst[i][q] = dt * w[q];
+    }
+  for (int i = 0; i < K1; ++i) {
+    B.lift[0][i] = Mi[i][0];
+    B.lift[1][i] = Mi[i][k];
+  }
+  return B;
+}
+
+std::vector<double> gauss_points(int k) {
+  if (k == 1) return {-1.0 / std::sqrt(3.0), 1.0 / std::sqrt(3.0)};
+  return {-std::sqrt(0.6), 0.0, std::sqrt(0.6)};
+}
+
+bool g_basis_ready[64] = {};
+
+}  // namespace
+
+struct vfp_ctx {
+  int lmax = 0, k = 0, naxes = 0, n = 0, nb = 0, K1 = 0;
+  int axes[3] = {0, 0, 0};
+  unsigned terms = 0;
+  double mass = 1.0, charge = 1.0;
+  bool mom = false;
+  int nspace = 0;
+  int device = -1;
+  ShMatrices S;
+
+  bool mesh_set = false;
+  int ncell[3] = {1, 1, 1};
+  int ncells = 0;
+  std::vector<double> nodes[3];
+  int bc_lo[3] = {0, 0, 0}, bc_hi[3] = {0, 0, 0};
+  double p_fixed = std::numeric_limits<double>::quiet_NaN();
+
+  bool planar = false;
+  double U[3] = {0, 0, 0};
+  std::vector<double> u_vol, du_vol, a_vol, u_face;
+  double B[3] = {0, 0, 0};
+  bool have_Bpts = false;
+  double nu0 = 0.0;
+  bool have_nu_cell = false;
+  bool have_src = false;
+
+  // device data
+  DevBuf d_s2h[3], d_u_vol, d_du_vol, d_a_vol, d_u_face;
+  DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face;
+  DevBuf d_pf_code, d_pf_tab, d_Bpts, d_nu, d_src;
+  DevBuf d_itab, d_dtab;
+  RowTables tab{};
+  FieldArgs fld{};
+  MeshArgs meshargs{};
+  StageLauncher launcher = nullptr;
+  double beta_pmax = 0.0;   // spectral-radius bound of beta^{ln p} over p faces
+  double vmax = 0.0;
+  double lam_max = 0.0;     // largest eigenvalue of A^x
+};
+
+namespace {
+
+double momentum_V(const vfp_ctx* c, double p) {
+  double g = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
+  return p / (g * c->mass);
+}
+
+// -------------------------------------------------------- row tables --
+
+int build_row_tables(vfp_ctx* c) {
+  const int n = c->n, L = c->lmax;
+  const ShMatrices& S = c->S;
+  auto lms = [&](int r, int& l, int& m, int& s) {
+    l = (int)std::floor(std::sqrt((double)r) + 1e-9);
+    int d = r - l * (l + 1);
+    m = std::abs(d);
+    s = d > 0 ? 1 : 0;
+  };
+  std::vector<int> iv;
+  std::vector<double> dv;
+  // offsets into iv / dv
+  auto ialloc = [&](size_t cnt) { size_t o = iv.size(); iv.resize(o + cnt, 0); return o; };
+  auto dalloc = [&](size_t cnt) { size_t o = dv.size(); dv.resize(o + cnt, 0.0); return o; };
+  size_t o_axc = ialloc(2 * n), o_axv = dalloc(2 * n), o_g1v = dalloc(2 * n);
+  size_t o_axxc = ialloc(2 * n), o_axxv = dalloc(3 * n), o_g2v = dalloc(3 * n);
+  size_t o_omc = ialloc(6 * n), o_omv = dalloc(6 * n);
+  size_t o_ayzc = ialloc(8 * n), o_ayzv = dalloc(8 * n);
+  size_t o_cv = dalloc(n);
+  size_t o_mem = ialloc((L + 1) * n), o_wrow = dalloc((L + 1) * n), o_wcol = dalloc((L + 1) * n);
+  size_t o_lam = dalloc(n);
+
+  auto check_covered = [&](const Mat& A, int r, std::initializer_list<int> cols, const char* name) -> int {
+    for (int j = 0; j < n; ++j) {
+      if (A(r, j) == 0.0) continue;
+      bool ok = false;
+      for (int cc : cols) ok |= (cc == j);
+      if (!ok) return fail(VFP_EDEVICE, "internal: %s row %d has an entry outside its stencil", name, r);
+    }
+    return VFP_OK;
+  };
+
+  for (int r = 0; r < n; ++r) {
+    int l, m, s;
+    lms(r, l, m, s);
+    int cp = (l + 1 <= L) ? lms_index(l + 1, m, s) : r;
+    int cm = (l - 1 >= m) ? lms_index(l - 1, m, s) : r;
+    iv[o_axc + r] = cp;
+    iv[o_axc + n + r] = cm;
+    dv[o_axv + r] = (cp != r) ? S.A[0](r, cp) : 0.0;
+    dv[o_axv + n + r] = (cm != r) ? S.A[0](r, cm) : 0.0;
+    dv[o_g1v + r] = (cp != r) ? S.G1(r, cp) : 0.0;
+    dv[o_g1v + n + r] = (cm != r) ? S.G1(r, cm) : 0.0;
+    if (int e = check_covered(S.A[0], r, {cp, cm}, "A^x")) return e;
+    if (int e = check_covered(S.G1, r, {cp, cm}, "G1")) return e;
+    int cpp = (l + 2 <= L) ? lms_index(l + 2, m, s) : r;
+    int cmm = (l - 2 >= m) ? lms_index(l - 2, m, s) : r;
+    iv[o_axxc + r] = cpp;
+    iv[o_axxc + n + r] = cmm;
+    dv[o_axxv + r] = (cpp != r) ? S.AXX(r, cpp) : 0.0;
+    dv[o_axxv + n + r] = S.AXX(r, r);
+    dv[o_axxv + 2 * n + r] = (cmm != r) ? S.AXX(r, cmm) : 0.0;
+    dv[o_g2v + r] = (cpp != r) ? S.G2(r, cpp) : 0.0;
+    dv[o_g2v + n + r] = S.G2(r, r);
+    dv[o_g2v + 2 * n + r] = (cmm != r) ? S.G2(r, cmm) : 0.0;
+    if (int e = check_covered(S.AXX, r, {cpp, r, cmm}, "(AxAx)_t")) return e;
+    if (int e = check_covered(S.G2, r, {cpp, r, cmm}, "G2")) return e;
+    for (int cc = 0; cc < 3; ++cc) {
+      int slot = 0;
+      for (int j = 0; j < n; ++j) {
+        if (S.Om[cc](r, j) == 0.0) continue;
+        if (slot >= 2) return fail(VFP_EDEVICE, "internal: Omega row %d has more than 2 entries", r);
+        iv[o_omc + (cc * 2 + slot) * n + r] = j;
+        dv[o_omv + (cc * 2 + slot) * n + r] = S.Om[cc](r, j);
+        ++slot;
+      }
+      for (; slot < 2; ++slot) iv[o_omc + (cc * 2 + slot) * n + r] = r;
+    }
+    for (int cc = 0; cc < 2; ++cc) {
+      int slot = 0;
+      for (int j = 0; j < n; ++j) {
+        if (S.A[cc + 1](r, j) == 0.0) continue;
+        if (slot >= 4) return fail(VFP_EDEVICE, "internal: A^y/A^z row %d has more than 4 entries", r);
+        iv[o_ayzc + (cc * 4 + slot) * n + r] = j;
+        dv[o_ayzv + (cc * 4 + slot) * n + r] = S.A[cc + 1](r, j);
+        ++slot;
+      }
+      for (; slot < 4; ++slot) iv[o_ayzc + (cc * 4 + slot) * n + r] = r;
+    }
+    dv[o_cv + r] = S.C[r];
+    // (m,s) block of A^x: l' = m..L
+    const int bsz = L - m + 1;
+    Mat blk(bsz);
+    for (int i = 0; i < bsz; ++i)
+      for (int j = 0; j < bsz; ++j) blk(i, j) = S.A[0](lms_index(m + i, m, s), lms_index(m + j, m, s));
+    std::vector<double> lam;
+    Mat W;
+    jacobi_eigh(blk, lam, W);
+    const int pos = l - m;
+    for (int i = 0; i <= L; ++i) {
+      if (i < bsz) {
+        iv[o_mem + i * n + r] = lms_index(m + i, m, s);
+        dv[o_wrow + i * n + r] = W(pos, i);
+        dv[o_wcol + i * n + r] = W(i, pos);
+      } else {
+        iv[o_mem + i * n + r] = r;
+      }
+    }
+    dv[o_lam + r] = lam[pos];
+  }
+
+  // uniform-axis face matrices beta^a = U_a + V A^a and |beta^a| (no ln p axis)
+  size_t o_fb[3] = {0, 0, 0}, o_fa[3] = {0, 0, 0}, o_fbv[3] = {0, 0, 0}, o_fav[3] = {0, 0, 0};
+  int nfb[3] = {0, 0, 0}, nfa[3] = {0, 0, 0};
+  const bool adv = c->terms & VFP_TERM_ADVECTION;
+  for (int ax = 0; ax < c->nspace; ++ax) {
+    if (ax == 0 && c->planar) continue;
+    if (c->mom) break;  // with a ln p axis only the profiled x axis is spatial
+    const int comp = c->axes[ax];
+    const double V = momentum_V(c, c->p_fixed);
+    Mat Bm(n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) Bm(i, j) = adv ? V * S.A[comp](i, j) : 0.0;
+    for (int i = 0; i < n; ++i) Bm(i, i) += adv ? c->U[comp] : 0.0;
+    std::vector<double> lam;
+    Mat W;
+    jacobi_eigh(Bm, lam, W);
+    Mat Ab(n);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double acc = 0.0;
+        for (int e = 0; e < n; ++e) acc += W(i, e) * std::fabs(lam[e]) * W(j, e);
+        Ab(i, j) = std::fabs(acc) < 1e-14 ? 0.0 : acc;
+      }
+    auto pack = [&](const Mat& Mx, size_t& oc, size_t& ov, int& cnt) -> int {
+      cnt = 0;
+      for (int i = 0; i < n; ++i) {
+        int nz = 0;
+        for (int j = 0; j < n; ++j) nz += (Mx(i, j) != 0.0);
+        cnt = std::max(cnt, nz);
+      }
+      if (cnt > kMaxUniSlots) return fail(VFP_EUNSUPPORTED, "face matrix row has %d > %d entries", cnt, kMaxUniSlots);
+      oc = ialloc(size_t(cnt) * n);
+      ov = dalloc(size_t(cnt) * n);
+      for (int i = 0; i < n; ++i) {
+        int slot = 0;
+        for (int j = 0; j < n; ++j)
+          if (Mx(i, j) != 0.0) {
+            iv[oc + size_t(slot) * n + i] = j;
+            dv[ov + size_t(slot) * n + i] = Mx(i, j);
+            ++slot;
+          }
+        for (; slot < cnt; ++slot) iv[oc + size_t(slot) * n + i] = i;
+      }
+      return VFP_OK;
+    };
+    if (int e = pack(Bm, o_fb[ax], o_fbv[ax], nfb[ax])) return e;
+    if (int e = pack(Ab, o_fa[ax], o_fav[ax], nfa[ax])) return e;
+  }
+
+  if (int e = upload_vec(c->d_itab, iv)) return e;
+  if (int e = upload_vec(c->d_dtab, dv)) return e;
+  const int* ib = c->d_itab.as<int>();
+  const double* db = c->d_dtab.as<double>();
+  RowTables& T = c->tab;
+  T = RowTables{};
+  T.ax_col = ib + o_axc;
+  T.ax_val = db + o_axv;
+  T.g1_val = db + o_g1v;
+  T.axx_col = ib + o_axxc;
+  T.axx_val = db + o_axxv;
+  T.g2_val = db + o_g2v;
+  T.om_col = ib + o_omc;
+  T.om_val = db + o_omv;
+  T.ayz_col = ib + o_ayzc;
+  T.ayz_val = db + o_ayzv;
+  T.c_val = db + o_cv;
+  T.blk_mem = ib + o_mem;
+  T.w_row = db + o_wrow;
+  T.w_col = db + o_wcol;
+  T.lam = db + o_lam;
+  for (int ax = 0; ax < 3; ++ax) {
+    T.nfb[ax] = nfb[ax];
+    T.nfa[ax] = nfa[ax];
+    T.fb_col[ax] = nfb[ax] ? ib + o_fb[ax] : nullptr;
+    T.fb_val[ax] = nfb[ax] ? db + o_fbv[ax] : nullptr;
+    T.fa_col[ax] = nfa[ax] ? ib + o_fa[ax] : nullptr;
+    T.fa_val[ax] = nfa[ax] ? db + o_fav[ax] : nullptr;
+  }
+  return VFP_OK;
+}
+
+// ------------------------------------------------- momentum-axis data --
+
+int build_momentum_data(vfp_ctx* c) {
+  if (!c->mom || !c->mesh_set) return VFP_OK;
+  const int pa = c->naxes - 1, K1 = c->K1;
+  const int np = c->ncell[pa];
+  const std::vector<double>& nd = c->nodes[pa];
+  std::vector<double> g = gauss_points(c->k);
+  std::vector<double> V(np * K1), iV(np * K1), idiv(np * K1), ig(np * K1), iVf(np + 1);
+  c->vmax = 0.0;
+  for (int i = 0; i < np; ++i)
+    for (int q = 0; q < K1; ++q) {
+      double lp = nd[i] + (1.0 + g[q]) * 0.5 * (nd[i + 1] - nd[i]);
+      double p = std::exp(lp);
+      double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
+      V[i * K1 + q] = p / (gam * c->mass);
+      iV[i * K1 + q] = gam * c->mass / p;
+      idiv[i * K1 + q] = c->mass / (gam * p);
+      ig[i * K1 + q] = c->charge / (gam * c->mass);
+      c->vmax = std::max(c->vmax, V[i * K1 + q]);
+    }
+  for (int f = 0; f <= np; ++f) {
+    double p = std::exp(nd[f]);
+    double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
+    iVf[f] = gam * c->mass / p;
+    c->vmax = std::max(c->vmax, p / (gam * c->mass));
+  }
+  if (int e = upload_vec(c->d_V_vol, V)) return e;
+  if (int e = upload_vec(c->d_iV_vol, iV)) return e;
+  if (int e = upload_vec(c->d_idiv_vol, idiv)) return e;
+  if (int e = upload_vec(c->d_ig_vol, ig)) return e;
+  if (int e = upload_vec(c->d_iV_face, iVf)) return e;
+  return VFP_OK;
+}
+
+// p-face upwind data: beta^{ln p} = a1 A^x + a2 (A^x A^x)_t at each (x point,
+// p face); it keeps the (m,s) blocks of A^x, so each block is diagonalised.
+int build_pface_data(vfp_ctx* c) {
+  if (!c->mom || !c->mesh_set) return VFP_OK;
+  const int pa = c->naxes - 1, K1 = c->K1, n = c->n, L = c->lmax;
+  const int nxp = c->ncell[0] * K1, npf = c->ncell[pa] + 1;
+  const std::vector<double>& nd = c->nodes[pa];
+  const double tm = (c->terms & VFP_TERM_MOMENTUM) ? 1.0 : 0.0;
+  std::vector<int> code((size_t)nxp * npf, -1);
+  std::vector<double> tab;
+  c->beta_pmax = 0.0;
+  std::vector<double> Bp_rows((size_t)n * (L + 1));
+  for (int ix = 0; ix < nxp; ++ix) {
+    const double a = c->planar ? c->a_vol[ix] : 0.0;
+    const double du = c->planar ? c->du_vol[ix] : 0.0;
+    for (int f = 0; f < npf; ++f) {
+      double p = std::exp(nd[f]);
+      double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
+      const double a1 = -tm * a * gam * c->mass / p, a2 = -tm * du;
+      bool anypos = false, anyneg = false;
+      double bnorm = 0.0;
+      std::fill(Bp_rows.begin(), Bp_rows.end(), 0.0);
+      for (int m = 0; m <= L; ++m) {
+        const int bsz = L - m + 1;
+        Mat blk(bsz);
+        for (int i = 0; i < bsz; ++i)
+          for (int j = 0; j < bsz; ++j) {
+            int ri = lms_index(m + i, m, 0), rj = lms_index(m + j, m, 0);
+            blk(i, j) = a1 * c->S.A[0](ri, rj) + a2 * c->S.AXX(ri, rj);
+          }
+        std::vector<double> lam;
+        Mat W;
+        jacobi_eigh(blk, lam, W);
+        for (double l : lam) bnorm = std::max(bnorm, std::fabs(l));
+        for (int i = 0; i < bsz; ++i) {
+          if (lam[i] > 0) anypos = true;
+          if (lam[i] < 0) anyneg = true;
+        }
+        // beta_+ rows of this block, for s = 0 and s = 1 rows alike
+        for (int i = 0; i < bsz; ++i)
+          for (int j = 0; j < bsz; ++j) {
+            double acc = 0.0;
+            for (int e = 0; e < bsz; ++e) acc += W(i, e) * std::max(lam[e], 0.0) * W(j, e);
+            for (int s = 0; s <= (m ? 1 : 0); ++s)
+              Bp_rows[(size_t)lms_index(m + i, m, s) * (L + 1) + j] = acc;
+          }
+      }
+      c->beta_pmax = std::max(c->beta_pmax, bnorm);
+      // treat eigenvalues within rounding of zero as zero
+      const double tol = 1e-14 * bnorm;
+      anypos = anyneg = false;
+      for (int m = 0; m <= L; ++m) {
+        const int bsz = L - m + 1;
+        Mat blk(bsz);
+        for (int i = 0; i < bsz; ++i)
+          for (int j = 0; j < bsz; ++j) {
+            int ri = lms_index(m + i, m, 0), rj = lms_index(m + j, m, 0);
+            blk(i, j) = a1 * c->S.A[0](ri, rj) + a2 * c->S.AXX(ri, rj);
+          }
+        std::vector<double> lam;
+        Mat W;
+        jacobi_eigh(blk, lam, W);
+        for (double l : lam) {
+          if (l > tol) anypos = true;
+          if (l < -tol) anyneg = true;
+        }
+      }
+      int cd;
+      if (!anyneg) cd = -1;
+      else if (!anypos) cd = -2;
+      else {
+        cd = (int)(tab.size() / ((size_t)n * (L + 1)));
+        tab.insert(tab.end(), Bp_rows.begin(), Bp_rows.end());
+      }
+      code[(size_t)ix * npf + f] = cd;
+    }
+  }
+  if (int e = upload_vec(c->d_pf_code, code)) return e;
+  if (tab.empty()) tab.assign((size_t)n * (L + 1), 0.0);
+  if (int e = upload_vec(c->d_pf_tab, tab)) return e;
+  return VFP_OK;
+}
+
+// Binds the context to the current device on first use and uploads the
+// 1-D basis tables to that device once per process.
+int ensure_device(vfp_ctx* c) {
+  if (c->device >= 0) return VFP_OK;
+  int cnt = 0;
+  hipError_t e = hipGetDeviceCount(&cnt);
+  if (e != hipSuccess || cnt <= 0) return fail(VFP_EDEVICE, "no HIP device available");
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(VFP_EDEVICE, "device ordinal %d", dev);
+  if (!g_basis_ready[dev]) {
+    Basis1D b[kMaxK] = {make_basis(1), make_basis(2)};
+    HIP_TRY(upload_basis(b));
+    g_basis_ready[dev] = true;
+  }
+  c->device = dev;
+  return VFP_OK;
+}
+
+int refresh(vfp_ctx* c) {
+  if (!c->mesh_set) return VFP_OK;
+  if (int e = ensure_device(c)) return e;
+  if (int e = build_row_tables(c)) return e;
+  if (int e = build_momentum_data(c)) return e;
+  if (int e = build_pface_data(c)) return e;
+  FieldArgs& F = c->fld;
+  F = FieldArgs{};
+  F.u_vol = c->d_u_vol.as<double>();
+  F.du_vol = c->d_du_vol.as<double>();
+  F.a_vol = c->d_a_vol.as<double>();
+  F.u_face = c->d_u_face.as<double>();
+  for (int i = 0; i < 3; ++i) F.U[i] = c->U[i];
+  F.V_vol = c->d_V_vol.as<double>();
+  F.iV_vol = c->d_iV_vol.as<double>();
+  F.idiv_vol = c->d_idiv_vol.as<double>();
+  F.ig_vol = c->d_ig_vol.as<double>();
+  F.iV_face = c->d_iV_face.as<double>();
+  if (!c->mom) {
+    double p = c->p_fixed;
+    double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
+    F.V0 = p / (gam * c->mass);
+    F.iV0 = gam * c->mass / p;
+    F.ig0 = c->charge / (gam * c->mass);
+    c->vmax = F.V0;
+  }
+  F.pf_code = c->d_pf_code.as<int>();
+  F.pf_tab = c->d_pf_tab.as<double>();
+  for (int i = 0; i < 3; ++i) F.B[i] = c->B[i];
+  F.B_pts = c->have_Bpts ? c->d_Bpts.as<double>() : nullptr;
+  F.nu0 = c->nu0;
+  F.nu_cell = c->have_nu_cell ? c->d_nu.as<double>() : nullptr;
+  F.src = c->have_src ? c->d_src.as<double>() : nullptr;
+  F.t_adv = (c->terms & VFP_TERM_ADVECTION) ? 1.0 : 0.0;
+  F.t_mom = (c->terms & VFP_TERM_MOMENTUM) ? 1.0 : 0.0;
+  F.t_rot = (c->terms & VFP_TERM_ROTATION) ? 1.0 : 0.0;
+  F.t_col = (c->terms & VFP_TERM_COLLISION) ? 1.0 : 0.0;
+  if (c->mom && !c->planar) {
+    // a momentum axis needs the x profile arrays; a uniform flow is stored as
+    // a constant profile
+    return VFP_OK;
+  }
+  c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
+  return VFP_OK;
+}
+
+int check_ready(const vfp_ctx* c) {
+  if (!c) return fail(VFP_EINVAL, "null context");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  if (!c->mom && !(c->p_fixed > 0)) return fail(VFP_ESTATE, "vfp_set_momentum has not been called");
+  if (c->mom && !c->planar) return fail(VFP_ESTATE, "a ln p axis needs vfp_set_flow_planar (a constant profile for uniform flow)");
+  if (!c->launcher) return fail(VFP_EUNSUPPORTED, "no kernel built for naxes=%d k=%d lmax=%d lnp=%d planar=%d",
+                                c->naxes, c->k, c->lmax, (int)c->mom, (int)c->planar);
+  return VFP_OK;
+}
+
+}  // namespace
+
+// ===================================================================== ABI
+
+extern "C" {
+
+const char* vfp_last_error(void) { return g_err.c_str(); }
+
+int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds, unsigned term_mask,
+               double mass, double charge) {
+  if (!out) return fail(VFP_EINVAL, "out is null");
+  *out = nullptr;
+  if (lmax < 1 || lmax > kMaxLmax) return fail(VFP_EINVAL, "lmax=%d outside [1,%d]", lmax, kMaxLmax);
+  if (k < 1 || k > kMaxK) return fail(VFP_EINVAL, "k=%d outside [1,%d]", k, kMaxK);
+  if (naxes < 1 || naxes > 3) return fail(VFP_EINVAL, "naxes=%d outside [1,3]", naxes);
+  if (!axis_kinds) return fail(VFP_EINVAL, "axis_kinds is null");
+  if (!(mass > 0) || !std::isfinite(mass) || !std::isfinite(charge)) return fail(VFP_EINVAL, "bad mass/charge");
+  if (term_mask & ~31u) return fail(VFP_EINVAL, "unknown term bits 0x%x", term_mask);
+  int nsp = 0;
+  bool mom = false;
+  for (int a = 0; a < naxes; ++a) {
+    int kd = axis_kinds[a];
+    if (kd == VFP_AXIS_LNP) {
+      if (a != naxes - 1) return fail(VFP_EINVAL, "the ln p axis must be the last axis");
+      mom = true;
+    } else if (kd >= VFP_AXIS_X && kd <= VFP_AXIS_Z) {
+      if (kd != a) return fail(VFP_EINVAL, "spatial axes must be x, y, z in order");
+      ++nsp;
+    } else {
+      return fail(VFP_EINVAL, "axis kind %d unknown", kd);
+    }
+  }
+  if (mom && nsp > 2) return fail(VFP_EINVAL, "at most two spatial axes with a ln p axis");
+  if (nsp == 0) return fail(VFP_EINVAL, "at least one spatial axis is required");
+  vfp_ctx* c = new (std::nothrow) vfp_ctx();
+  if (!c) return fail(VFP_ENOMEM, "context allocation");
+  c->lmax = lmax;
+  c->k = k;
+  c->naxes = naxes;
+  c->n = (lmax + 1) * (lmax + 1);
+  c->K1 = k + 1;
+  c->nb = 1;
+  for (int a = 0; a < naxes; ++a) {
+    c->nb *= c->K1;
+    c->axes[a] = axis_kinds[a];
+  }
+  c->terms = term_mask;
+  c->mass = mass;
+  c->charge = charge;
+  c->mom = mom;
+  c->nspace = nsp;
+  c->S = build_sh_matrices(lmax);
+  {
+    std::vector<double> lam;
+    Mat W;
+    jacobi_eigh(c->S.A[0], lam, W);
+    c->lam_max = *std::max_element(lam.begin(), lam.end());
+  }
+  *out = c;
+  return VFP_OK;
+}
+
+void vfp_destroy(vfp_ctx* c) { delete c; }
+
+int vfp_set_mesh(vfp_ctx* c, const int* ncells, const double* const* nodes, const int* bc_lo,
+                 const int* bc_hi) {
+  if (!c || !ncells || !nodes || !bc_lo || !bc_hi) return fail(VFP_EINVAL, "null argument");
+  long long tot = 1;
+  for (int a = 0; a < c->naxes; ++a) {
+    if (ncells[a] < 1) return fail(VFP_EINVAL, "ncells[%d]=%d", a, ncells[a]);
+    if (!nodes[a]) return fail(VFP_EINVAL, "nodes[%d] is null", a);
+    for (int i = 0; i < ncells[a]; ++i)
+      if (!(nodes[a][i + 1] > nodes[a][i]) || !std::isfinite(nodes[a][i + 1]))
+        return fail(VFP_EINVAL, "nodes[%d] not strictly increasing at %d", a, i);
+    for (int lohi = 0; lohi < 2; ++lohi) {
+      int b = lohi ? bc_hi[a] : bc_lo[a];
+      if (b < 0 || b > 2) return fail(VFP_EINVAL, "bc kind %d unknown", b);
+    }
+    if ((bc_lo[a] == VFP_BC_PERIODIC) != (bc_hi[a] == VFP_BC_PERIODIC))
+      return fail(VFP_EINVAL, "axis %d: periodic must be set on both ends", a);
+    tot *= ncells[a];
+  }
+  if (tot > (1LL << 31) / 64) return fail(VFP_EINVAL, "too many cells (%lld)", tot);
+  c->ncells = (int)tot;
+  for (int a = 0; a < 3; ++a) {
+    c->ncell[a] = a < c->naxes ? ncells[a] : 1;
+    c->bc_lo[a] = a < c->naxes ? bc_lo[a] : 0;
+    c->bc_hi[a] = a < c->naxes ? bc_hi[a] : 0;
+    c->nodes[a].clear();
+    if (a < c->naxes) c->nodes[a].assign(nodes[a], nodes[a] + ncells[a] + 1);
+  }
+  // reset fields
+  c->planar = false;
+  for (int i = 0; i < 3; ++i) c->U[i] = c->B[i] = 0.0;
+  c->have_Bpts = c->have_nu_cell = c->have_src = false;
+  c->nu0 = 0.0;
+  c->u_vol.assign(c->ncell[0] * c->K1, 0.0);
+  c->du_vol = c->a_vol = c->u_vol;
+  c->u_face.assign(c->ncell[0] + 1, 0.0);
+  c->mesh_set = true;
+  for (int a = 0; a < 3; ++a) {
+    c->meshargs.n[a] = c->ncell[a];
+    c->meshargs.bc_lo[a] = c->bc_lo[a];
+    c->meshargs.bc_hi[a] = c->bc_hi[a];
+  }
+  c->meshargs.ncells = c->ncells;
+  if (c->mom) c->planar = true;   // a ln p axis always uses the x-profile kernels (U = 0 to start)
+  if (int e = ensure_device(c)) return e;
+  for (int a = 0; a < 3; ++a) {
+    std::vector<double> s2h(c->ncell[a], 0.0);
+    if (a < c->naxes)
+      for (int i = 0; i < c->ncell[a]; ++i) s2h[i] = 2.0 / (c->nodes[a][i + 1] - c->nodes[a][i]);
+    if (int e = upload_vec(c->d_s2h[a], s2h)) return e;
+    c->meshargs.s2h[a] = c->d_s2h[a].as<double>();
+  }
+  if (c->mom) {
+    if (int e = upload_vec(c->d_u_vol, c->u_vol)) return e;
+    if (int e = upload_vec(c->d_du_vol, c->du_vol)) return e;
+    if (int e = upload_vec(c->d_a_vol, c->a_vol)) return e;
+    if (int e = upload_vec(c->d_u_face, c->u_face)) return e;
+  }
+  if (!c->mom && !(c->p_fixed > 0)) return VFP_OK;
+  return refresh(c);
+}
+
+int vfp_set_momentum(vfp_ctx* c, double p) {
+  if (!c) return fail(VFP_EINVAL, "null context");
+  if (c->mom) return fail(VFP_EINVAL, "context has a ln p axis; momentum is a coordinate");
+  if (!(p > 0) || !std::isfinite(p)) return fail(VFP_EINVAL, "p=%g must be positive", p);
+  c->p_fixed = p;
+  return refresh(c);
+}
+
+int vfp_query_points(const vfp_ctx* c, int which, int axis, double* coords, int64_t* count) {
+  if (!c || !count) return fail(VFP_EINVAL, "null argument");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  if (axis < 0 || axis >= c->naxes) return fail(VFP_EINVAL, "axis %d", axis);
+  const int na = c->ncell[axis], K1 = c->K1;
+  const std::vector<double>& nd = c->nodes[axis];
+  if (which == VFP_PTS_FACE) {
+    *count = na + 1;
+    if (coords) std::copy(nd.begin(), nd.end(), coords);
+    return VFP_OK;
+  }
+  if (which != VFP_PTS_VOLUME && which != VFP_PTS_NODE) return fail(VFP_EINVAL, "point set %d", which);
+  *count = (int64_t)na * K1;
+  if (!coords) return VFP_OK;
+  std::vector<double> ref = (which == VFP_PTS_VOLUME) ? gauss_points(c->k)
+                                                      : (c->k == 1 ? std::vector<double>{-1.0, 1.0}
+                                                                   : std::vector<double>{-1.0, 0.0, 1.0});
+  for (int i = 0; i < na; ++i)
+    for (int q = 0; q < K1; ++q) coords[i * K1 + q] = nd[i] + (1.0 + ref[q]) * 0.5 * (nd[i + 1] - nd[i]);
+  return VFP_OK;
+}
+
+int vfp_set_flow_uniform(vfp_ctx* c, const double* U) {
+  if (!c || !U) return fail(VFP_EINVAL, "null argument");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  for (int i = 0; i < 3; ++i)
+    if (!std::isfinite(U[i])) return fail(VFP_EINVAL, "U not finite");
+  for (int i = 0; i < 3; ++i) c->U[i] = U[i];
+  if (c->mom) {
+    // stored as a constant x profile (grad U = 0, dU/dt = 0)
+    std::fill(c->u_vol.begin(), c->u_vol.end(), U[0]);
+    std::fill(c->u_face.begin(), c->u_face.end(), U[0]);
+    std::fill(c->du_vol.begin(), c->du_vol.end(), 0.0);
+    std::fill(c->a_vol.begin(), c->a_vol.end(), 0.0);
+    if (int e = upload_vec(c->d_u_vol, c->u_vol)) return e;
+    if (int e = upload_vec(c->d_du_vol, c->du_vol)) return e;
+    if (int e = upload_vec(c->d_a_vol, c->a_vol)) return e;
+    if (int e = upload_vec(c->d_u_face, c->u_face)) return e;
+  } else {
+    c->planar = false;
+  }
+  return refresh(c);
+}
+
+int vfp_set_flow_planar(vfp_ctx* c, const double* u, const double* dudx, const double* dudt,
+                        const double* u_face) {
+  if (!c || !u || !dudx || !dudt || !u_face) return fail(VFP_EINVAL, "null argument");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  if (c->axes[0] != VFP_AXIS_X) return fail(VFP_EINVAL, "planar flow needs axis 0 = x");
+  const int nq = c->ncell[0] * c->K1;
+  for (int i = 0; i < nq; ++i)
+    if (!std::isfinite(u[i]) || !std::isfinite(dudx[i]) || !std::isfinite(dudt[i]))
+      return fail(VFP_EINVAL, "flow profile not finite at %d", i);
+  c->u_vol.assign(u, u + nq);
+  c->du_vol.assign(dudx, dudx + nq);
+  c->a_vol.assign(dudt, dudt + nq);
+  c->u_face.assign(u_face, u_face + c->ncell[0] + 1);
+  c->U[0] = 0.0;
+  c->planar = true;
+  if (int e = upload_vec(c->d_u_vol, c->u_vol)) return e;
+  if (int e = upload_vec(c->d_du_vol, c->du_vol)) return e;
+  if (int e = upload_vec(c->d_a_vol, c->a_vol)) return e;
+  if (int e = upload_vec(c->d_u_face, c->u_face)) return e;
+  return refresh(c);
+}
+
+int vfp_set_magnetic_uniform(vfp_ctx* c, const double* B) {
+  if (!c || !B) return fail(VFP_EINVAL, "null argument");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  for (int i = 0; i < 3; ++i) c->B[i] = B[i];
+  c->have_Bpts = false;
+  return refresh(c);
+}
+
+int vfp_set_magnetic_points(vfp_ctx* c, const double* B) {
+  if (!c || !B) return fail(VFP_EINVAL, "null argument");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  if (c->mom) return fail(VFP_EUNSUPPORTED, "point-wise B with a ln p axis");
+  if (int e = upload(c->d_Bpts, B, (size_t)c->ncells * c->nb * 3 * sizeof(double))) return e;
+  c->have_Bpts = true;
+  for (int i = 0; i < 3; ++i) c->B[i] = 0.0;
+  return refresh(c);
+}
+
+int vfp_set_scattering(vfp_ctx* c, double nu, const double* nu_cell) {
+  if (!c) return fail(VFP_EINVAL, "null context");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  if (nu_cell) {
+    if (int e = upload(c->d_nu, nu_cell, (size_t)c->ncells * sizeof(double))) return e;
+    c->have_nu_cell = true;
+  } else {
+    if (!std::isfinite(nu)) return fail(VFP_EINVAL, "nu not finite");
+    c->nu0 = nu;
+    c->have_nu_cell = false;
+  }
+  return refresh(c);
+}
+
+int vfp_set_source_points(vfp_ctx* c, const double* s) {
+  if (!c || !s) return fail(VFP_EINVAL, "null argument");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  // M^{-1} h per cell: the 000 component of the test contraction of
+  // s_000 = sqrt(4 pi) s (the Jacobian cancels against M^{-1})
+  Basis1D b = make_basis(c->k);
+  const int nb = c->nb, K1 = c->K1, D = c->naxes;
+  std::vector<double> out((size_t)c->ncells * nb, 0.0);
+  const double s4 = std::sqrt(4.0 * M_PI);
+  for (int cell = 0; cell < c->ncells; ++cell) {
+    const double* sc = s + (size_t)cell * nb;
+    for (int i = 0; i < nb; ++i) {
+      double acc = 0.0;
+      for (int q = 0; q < nb; ++q) {
+        double t = 1.0;
+        int ii = i, qq = q;
+        for (int a = 0; a < D; ++a) {
+          t *= b.tst[ii % K1][qq % K1];
+          ii /= K1;
+          qq /= K1;
+        }
+        acc += t * sc[q];
+      }
+      out[(size_t)cell * nb + i] = s4 * acc;
+    }
+  }
+  if (int e = upload_vec(c->d_src, out)) return e;
+  c->have_src = true;
+  return refresh(c);
+}
+
+int vfp_ndofs(const vfp_ctx* c, int64_t* n) {
+  if (!c || !n) return fail(VFP_EINVAL, "null argument");
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  *n = (int64_t)c->ncells * c->nb * c->n;
+  return VFP_OK;
+}
+
+int vfp_cfl_dt(const vfp_ctx* c, double courant, double* dt) {
+  if (int e = check_ready(c)) return e;
+  if (!dt || !(courant > 0)) return fail(VFP_EINVAL, "bad courant / dt pointer");
+  double sum = 0.0;
+  const bool adv = c->terms & VFP_TERM_ADVECTION;
+  for (int a = 0; a < c->naxes; ++a) {
+    double hmin = 1e300;
+    for (int i = 0; i < c->ncell[a]; ++i) hmin = std::min(hmin, c->nodes[a][i + 1] - c->nodes[a][i]);
+    double bmax = 0.0;
+    if (c->mom && a == c->naxes - 1) {
+      bmax = c->beta_pmax;
+    } else if (adv) {
+      double umax = std::fabs(c->U[c->axes[a]]);
+      if (a == 0 && c->planar) {
+        for (double v : c->u_vol) umax = std::max(umax, std::fabs(v));
+        for (double v : c->u_face) umax = std::max(umax, std::fabs(v));
+      }
+      bmax = umax + c->lam_max * c->vmax;
+    }
+    sum += bmax / hmin;
+  }
+  if (!(sum > 0)) return fail(VFP_EINVAL, "no advection: the CFL step is unbounded");
+  *dt = courant / sum;
+  return VFP_OK;
+}
+
+static int launch(vfp_ctx* c, const double* w_in, const double* u, double* w_out, double alpha, double beta,
+                  int with_source, void* stream) {
+  KernelArgs a;
+  a.mesh = c->meshargs;
+  a.fld = c->fld;
+  a.tab = c->tab;
+  a.st.w_in = w_in;
+  a.st.u = u;
+  a.st.w_out = w_out;
+  a.st.alpha = alpha;
+  a.st.beta = beta;
+  a.st.with_source = with_source && (c->terms & VFP_TERM_SOURCE);
+  c->launcher(a, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return VFP_OK;
+}
+
+int vfp_apply(vfp_ctx* c, const double* in, double* out, int with_source, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!in || !out) return fail(VFP_EINVAL, "null state pointer");
+  if (in == out) return fail(VFP_EINVAL, "in and out must not alias");
+  return launch(c, in, nullptr, out, 0.0, 1.0, with_source, stream);
+}
+
+int vfp_stage(vfp_ctx* c, const double* w_in, const double* u, double* w_out, double cdt, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!w_in || !u || !w_out) return fail(VFP_EINVAL, "null state pointer");
+  if (w_out == w_in) return fail(VFP_EINVAL, "w_out must differ from w_in");
+  if (!std::isfinite(cdt)) return fail(VFP_EINVAL, "cdt not finite");
+  return launch(c, w_in, u, w_out, 1.0, cdt, 1, stream);
+}
+
+int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!u || !work) return fail(VFP_EINVAL, "null state pointer");
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  double* wa = work;
+  double* wb = work + N;
+  if ((u >= work && u < work + 2 * N) || (work >= u && work < u + N))
+    return fail(VFP_EINVAL, "work overlaps u");
+  for (int64_t s = 0; s < nsteps; ++s) {
+    if (int e = launch(c, u, u, wa, 1.0, 0.25 * dt, 1, stream)) return e;
+    if (int e = launch(c, wa, u, wb, 1.0, dt / 3.0, 1, stream)) return e;
+    if (int e = launch(c, wb, u, wa, 1.0, 0.5 * dt, 1, stream)) return e;
+    if (int e = launch(c, wa, u, u, 1.0, dt, 1, stream)) return e;
+  }
+  return VFP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,241 @@
+"""Thin ctypes binding of libvfp.so (include/vfp.h).
+
+Argument marshalling only: every step of the operator runs in the HIP
+kernels of the library.  PyTorch supplies device memory and streams.  The
+binding fails loudly if the library is missing -- there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvfp.so")
+
+AXIS = {"x": 0, "y": 1, "z": 2, "lnp": 3}
+TERM = {"advection": 1, "momentum": 2, "rotation": 4, "collision": 8, "source": 16}
+BC = {"periodic": 0, "zero_inflow": 1, "continuous": 2}
+PTS_VOLUME, PTS_FACE, PTS_NODE = 0, 1, 2
+
+_lib = None
+
+
+class VFPError(RuntimeError):
+    pass
+
+
+def load(path: str = LIB_PATH):
+    """Load the built library (never builds it)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise VFPError(f"{path} is missing: build it with `python -m paper_2501_05110_amd.build`")
+    # torch's bundled HIP runtime carries the same SONAME as the one libvfp
+    # links against; loading torch first makes the process use one runtime.
+    import torch  # noqa: F401
+    lib = C.CDLL(path)
+    P, I, D, U, L = C.c_void_p, C.c_int, C.c_double, C.c_uint, C.c_int64
+    dp = C.POINTER(C.c_double)
+    sig = {
+        "vfp_last_error": (C.c_char_p, []),
+        "vfp_create": (I, [C.POINTER(P), I, I, I, C.POINTER(I), U, D, D]),
+        "vfp_destroy": (None, [P]),
+        "vfp_set_mesh": (I, [P, C.POINTER(I), C.POINTER(dp), C.POINTER(I), C.POINTER(I)]),
+        "vfp_set_momentum": (I, [P, D]),
+        "vfp_query_points": (I, [P, I, I, dp, C.POINTER(L)]),
+        "vfp_set_flow_uniform": (I, [P, dp]),
+        "vfp_set_flow_planar": (I, [P, dp, dp, dp, dp]),
+        "vfp_set_magnetic_uniform": (I, [P, dp]),
+        "vfp_set_magnetic_points": (I, [P, dp]),
+        "vfp_set_scattering": (I, [P, D, dp]),
+        "vfp_set_source_points": (I, [P, dp]),
+        "vfp_ndofs": (I, [P, C.POINTER(L)]),
+        "vfp_cfl_dt": (I, [P, D, dp]),
+        "vfp_apply": (I, [P, P, P, I, P]),
+        "vfp_stage": (I, [P, P, P, P, D, P]),
+        "vfp_advance": (I, [P, P, D, L, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["vfp_last_error", "vfp_create", "vfp_destroy", "vfp_set_mesh", "vfp_set_momentum",
+            "vfp_query_points", "vfp_set_flow_uniform", "vfp_set_flow_planar",
+            "vfp_set_magnetic_uniform", "vfp_set_magnetic_points", "vfp_set_scattering",
+            "vfp_set_source_points", "vfp_ndofs", "vfp_cfl_dt", "vfp_apply", "vfp_stage",
+            "vfp_advance"]
+
+
+def _check(rc):
+    if rc != 0:
+        msg = _lib.vfp_last_error().decode()
+        raise VFPError(f"vfp error {rc}: {msg}")
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _stream_handle(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+class Operator:
+    """The DG operator of one run (a context of the C library)."""
+
+    def __init__(self, wl):
+        lib = load()
+        self.wl = wl
+        self._ctx = C.c_void_p()
+        kinds = (C.c_int * len(wl.axes))(*[AXIS[a] for a in wl.axes])
+        mask = 0
+        for t in wl.terms:
+            mask |= TERM[t]
+        _check(lib.vfp_create(C.byref(self._ctx), wl.lmax, wl.k, len(wl.axes), kinds, mask,
+                              float(wl.mass), float(wl.charge)))
+        d = len(wl.axes)
+        self._nodes = [_f64(n) for n in wl.nodes]
+        nc = (C.c_int * d)(*[len(n) - 1 for n in self._nodes])
+        nptr = (C.POINTER(C.c_double) * d)(*[_dptr(n) for n in self._nodes])
+        lo = (C.c_int * d)(*[BC[b[0]] for b in wl.bc])
+        hi = (C.c_int * d)(*[BC[b[1]] for b in wl.bc])
+        _check(lib.vfp_set_mesh(self._ctx, nc, nptr, lo, hi))
+        self.mom = "lnp" in wl.axes
+        if not self.mom:
+            _check(lib.vfp_set_momentum(self._ctx, float(wl.p_fixed)))
+        self._set_fields()
+        n = C.c_int64()
+        _check(lib.vfp_ndofs(self._ctx, C.byref(n)))
+        self.ndofs = n.value
+        self.shape = wl.shape
+
+    # -- field sampling at the points the library reports ----------------
+    def points(self, which, axis):
+        cnt = C.c_int64()
+        _check(_lib.vfp_query_points(self._ctx, which, axis, None, C.byref(cnt)))
+        out = np.zeros(cnt.value)
+        _check(_lib.vfp_query_points(self._ctx, which, axis, _dptr(out), C.byref(cnt)))
+        return out
+
+    def volume_points(self):
+        """Spatial coordinates X (3, ncells*nb) and momenta p of every volume
+        point, ordered [cell][q]."""
+        wl = self.wl
+        d = len(wl.axes)
+        K1 = wl.k + 1
+        ncx = wl.ncells_axis
+        coords = [self.points(PTS_VOLUME, a).reshape(ncx[a], K1) for a in range(d)]
+        cell_idx = np.indices(ncx[::-1]).reshape(d, -1)[::-1]
+        q_idx = np.indices((K1,) * d).reshape(d, -1)[::-1]
+        X = np.zeros((3, wl.ncells * wl.n_basis))
+        p = np.full(X.shape[1], np.nan if wl.p_fixed is None else float(wl.p_fixed))
+        for a, name in enumerate(wl.axes):
+            v = coords[a][cell_idx[a][:, None], q_idx[a][None, :]].ravel()
+            if name == "lnp":
+                p = np.exp(v)
+            else:
+                X[AXIS[name]] = v
+        return X, p
+
+    def _set_fields(self):
+        wl, lib, ctx = self.wl, _lib, self._ctx
+        kind = getattr(wl.flow, "kind", None)
+        if kind is None:
+            raise VFPError("flow callable has no .kind (uniform or planar_x)")
+        if kind[0] == "uniform":
+            _check(lib.vfp_set_flow_uniform(ctx, _dptr(_f64(kind[1]))))
+        elif kind[0] == "planar_x":
+            xv = self.points(PTS_VOLUME, 0)
+            xf = self.points(PTS_FACE, 0)
+
+            def sample(x):
+                X = np.zeros((3, x.shape[0]))
+                X[0] = x
+                U, dU, a = wl.flow(X)
+                return _f64(U[0]), _f64(dU[0, 0]), _f64(a[0])
+            u, du, a = sample(xv)
+            uf = sample(xf)[0]
+            _check(lib.vfp_set_flow_planar(ctx, _dptr(u), _dptr(du), _dptr(a), _dptr(uf)))
+        else:
+            raise VFPError(f"flow kind {kind}")
+        if wl.magnetic is not None:
+            mk = getattr(wl.magnetic, "kind", ("points",))
+            if mk[0] == "uniform":
+                _check(lib.vfp_set_magnetic_uniform(ctx, _dptr(_f64(mk[1]))))
+            else:
+                X, _ = self.volume_points()
+                B = _f64(wl.magnetic(X).T)          # [cell*q][3]
+                _check(lib.vfp_set_magnetic_points(ctx, _dptr(B)))
+        if np.isscalar(wl.nu):
+            _check(lib.vfp_set_scattering(ctx, float(wl.nu), None))
+        else:
+            nu = _f64(wl.nu)
+            if nu.shape != (wl.ncells,):
+                raise VFPError("nu must be a scalar or one value per cell")
+            _check(lib.vfp_set_scattering(ctx, 0.0, _dptr(nu)))
+        if wl.source is not None and "source" in wl.terms:
+            X, p = self.volume_points()
+            s = _f64(wl.source(X, p))
+            _check(lib.vfp_set_source_points(ctx, _dptr(s)))
+
+    def set_scattering(self, nu):
+        if np.isscalar(nu):
+            _check(_lib.vfp_set_scattering(self._ctx, float(nu), None))
+        else:
+            _check(_lib.vfp_set_scattering(self._ctx, 0.0, _dptr(_f64(nu))))
+
+    # -- compute ------------------------------------------------------------
+    def _t(self, x, name):
+        import torch
+        if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64 \
+                or not x.is_contiguous() or x.numel() < self.ndofs:
+            raise VFPError(f"{name} must be a contiguous float64 CUDA tensor of >= {self.ndofs} elements")
+        return C.c_void_p(x.data_ptr())
+
+    def apply(self, zin, zout, with_source=True, stream=None):
+        _check(_lib.vfp_apply(self._ctx, self._t(zin, "in"), self._t(zout, "out"),
+                              int(bool(with_source)), _stream_handle(stream)))
+
+    def stage(self, w_in, u, w_out, cdt, stream=None):
+        _check(_lib.vfp_stage(self._ctx, self._t(w_in, "w_in"), self._t(u, "u"),
+                              self._t(w_out, "w_out"), float(cdt), _stream_handle(stream)))
+
+    def advance(self, u, dt, nsteps, work, stream=None):
+        import torch
+        if work.numel() < 2 * self.ndofs:
+            raise VFPError("work needs 2*ndofs doubles")
+        _check(_lib.vfp_advance(self._ctx, self._t(u, "u"), float(dt), int(nsteps),
+                                self._t(work, "work"), _stream_handle(stream)))
+
+    def cfl_dt(self, courant=None):
+        c = self.wl.courant if courant is None else courant
+        dt = C.c_double()
+        _check(_lib.vfp_cfl_dt(self._ctx, float(c), C.byref(dt)))
+        return dt.value
+
+    def close(self):
+        if self._ctx:
+            _lib.vfp_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -45,6 +45,9 @@ def zero_flow(X):
     return np.zeros((3, N)), np.zeros((3, 3, N)), np.zeros((3, N))
 
 
+zero_flow.kind = ("uniform", np.zeros(3))
+
+
 def uniform_flow(U):
     U = np.asarray(U, dtype=float)
 
@@ -52,6 +55,7 @@ def uniform_flow(U):
         N = X.shape[1]
         return (np.repeat(U[:, None], N, axis=1), np.zeros((3, 3, N)),
                 np.zeros((3, N)))
+    flow.kind = ("uniform", U)
     return flow
 
 
@@ -77,12 +81,17 @@ def shock_flow(U0, r, w):
         a = np.zeros((3, N))
         U[0], dU[0, 0], a[0] = Ux, dUx, aUx
         return U, dU, a
+    flow.kind = ("planar_x",)
     return flow
 
 
 def uniform_field(B):
     B = np.asarray(B, dtype=float)
-    return lambda X: np.repeat(B[:, None], X.shape[1], axis=1)
+
+    def field(X):
+        return np.repeat(B[:, None], X.shape[1], axis=1)
+    field.kind = ("uniform", B)
+    return field
 
 
 @dataclass
@@ -95,6 +104,7 @@ class FourierField:
     amp: np.ndarray      # (3 axes, nmodes, 3 components)
     phase: np.ndarray    # (3, nmodes)
     length: float
+    kind = ("points",)
 
     def __call__(self, X):
         B = np.repeat(np.asarray(self.B0, float)[:, None], X.shape[1], axis=1)
@@ -260,12 +270,13 @@ def config2(nx=1024, np_=128, steps=2000):
 
 
 # C3: 3-D x,y,z periodic, 48^3, k=2, l_max=5, fixed p (gamma=2)
-def config3(ncell=48, steps=500):
+def config3(ncell=48, steps=500, lmax=5, k=2):
     p = math.sqrt(3.0)
-    nodes = tuple(uniform_nodes(-10.0, 10.0, ncell) for _ in range(3))
+    nc = (ncell,) * 3 if np.isscalar(ncell) else tuple(ncell)
+    nodes = tuple(uniform_nodes(-10.0, 10.0, m) for m in nc)
     B = random_fourier_field(SEED_BASE + 3)
     wl = Workload(
-        name=f"3d_xyz_{ncell}cube_k2_lmax5", lmax=5, k=2, axes=("x", "y", "z"),
+        name=f"3d_xyz_{'x'.join(map(str, nc))}_k{k}_lmax{lmax}", lmax=lmax, k=k, axes=("x", "y", "z"),
         nodes=nodes, bc=((PERIODIC, PERIODIC),) * 3,
         terms=frozenset({ADVECTION, ROTATION, COLLISION}),
         p_fixed=p, flow=zero_flow, magnetic=B, nu=0.1, steps=steps)

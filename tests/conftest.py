@@ -15,6 +15,18 @@ def pytest_configure(config):
 
 @pytest.fixture(scope="session")
 def lib():
-    """The HIP library binding (loaded, never built, by tests)."""
+    """The HIP library binding.  Tests load what is built and build only if
+    nothing is."""
     from paper_2501_05110_amd import vfp
+    if not os.path.exists(vfp.LIB_PATH):
+        from paper_2501_05110_amd import build
+        build.build(verbose=False)
     return vfp.load()
+
+
+@pytest.fixture(scope="session")
+def cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch.device("cuda:0")

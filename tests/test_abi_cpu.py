@@ -1,0 +1,96 @@
+"""Host-side checks of the C ABI that need no GPU: every function declared in
+include/vfp.h is exported, and argument validation reports errors through
+status codes and vfp_last_error()."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2501_05110_amd import vfp
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "vfp.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(vfp_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_binding_functions(lib):
+    assert sorted(vfp.exported_symbols()) == declared_functions()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def _create(lib, lmax=3, k=2, axes=(0, 3), mask=31, mass=1.0, charge=1.0):
+    ctx = C.c_void_p()
+    kinds = (C.c_int * len(axes))(*axes)
+    rc = lib.vfp_create(C.byref(ctx), lmax, k, len(axes), kinds, mask, mass, charge)
+    return rc, ctx
+
+
+@pytest.mark.parametrize("kw,needle", [
+    (dict(lmax=0), "lmax"), (dict(lmax=8), "lmax"), (dict(k=0), "k="), (dict(k=3), "k="),
+    (dict(axes=()), "naxes"), (dict(axes=(0, 1, 2, 3)), "naxes"), (dict(axes=(3, 0)), "ln p"),
+    (dict(axes=(1,)), "x, y, z"), (dict(axes=(0, 1, 2, 3)[:3] + ()), None),
+    (dict(mass=0.0), "mass"), (dict(mask=64), "term"), (dict(axes=(3,)), "spatial"),
+])
+def test_create_validation(lib, kw, needle):
+    rc, ctx = _create(lib, **kw)
+    if needle is None:
+        assert rc == 0
+        lib.vfp_destroy(ctx)
+        return
+    assert rc == -1
+    assert needle in lib.vfp_last_error().decode()
+
+
+def test_calls_out_of_order(lib):
+    rc, ctx = _create(lib)
+    assert rc == 0
+    U = (C.c_double * 3)(0.1, 0, 0)
+    assert lib.vfp_set_flow_uniform(ctx, U) == -4
+    assert "set_mesh" in lib.vfp_last_error().decode()
+    n = C.c_int64()
+    assert lib.vfp_ndofs(ctx, C.byref(n)) == -4
+    assert lib.vfp_apply(ctx, None, None, 1, None) == -4
+    assert lib.vfp_set_momentum(ctx, 1.0) == -1       # ln p axis: momentum is a coordinate
+    lib.vfp_destroy(ctx)
+    lib.vfp_destroy(None)
+
+
+def test_mesh_validation_and_points(lib):
+    rc, ctx = _create(lib, lmax=1, k=2, axes=(0,))
+    assert rc == 0
+    bad = np.array([0.0, 1.0, 0.5])
+    arr = (C.POINTER(C.c_double) * 1)(bad.ctypes.data_as(C.POINTER(C.c_double)))
+    nc = (C.c_int * 1)(2)
+    per = (C.c_int * 1)(0)
+    zin = (C.c_int * 1)(1)
+    assert lib.vfp_set_mesh(ctx, nc, arr, per, per) == -1
+    assert "increasing" in lib.vfp_last_error().decode()
+    good = np.array([0.0, 1.0, 3.0])
+    arr = (C.POINTER(C.c_double) * 1)(good.ctypes.data_as(C.POINTER(C.c_double)))
+    assert lib.vfp_set_mesh(ctx, nc, arr, per, zin) == -1      # periodic on one end only
+    rc = lib.vfp_set_mesh(ctx, nc, arr, zin, zin)
+    assert rc in (0, -3)          # -3 (EDEVICE) on a machine without a GPU
+    n = C.c_int64()
+    assert lib.vfp_ndofs(ctx, C.byref(n)) == 0 and n.value == 2 * 3 * 4
+    cnt = C.c_int64()
+    assert lib.vfp_query_points(ctx, 0, 0, None, C.byref(cnt)) == 0 and cnt.value == 6
+    pts = np.zeros(6)
+    assert lib.vfp_query_points(ctx, 0, 0, pts.ctypes.data_as(C.POINTER(C.c_double)), C.byref(cnt)) == 0
+    g = np.sqrt(0.6)
+    want = np.concatenate([0.5 + 0.5 * np.array([-g, 0, g]), 2.0 + np.array([-g, 0, g])])
+    np.testing.assert_allclose(pts, want, atol=1e-15)
+    assert lib.vfp_query_points(ctx, 1, 0, pts.ctypes.data_as(C.POINTER(C.c_double)), C.byref(cnt)) == 0
+    np.testing.assert_allclose(pts[:3], good)
+    assert lib.vfp_query_points(ctx, 0, 1, None, C.byref(cnt)) == -1
+    lib.vfp_destroy(ctx)
