@@ -1,0 +1,167 @@
+"""Benchmark: explicit time stepping of the DG x spherical-harmonic operator.
+
+Workload: the 2-D (x, ln p) parallel shock -- 1024 x 128 cells, DG degree 2,
+l_max = 3 (18,874,368 FP64 degrees of freedom), tanh flow profile with r = 4,
+B along x, nu ~ p^(-1/3) per cell, Gaussian injection -- advanced with the
+four-stage fourth-order Runge-Kutta scheme at Courant number 0.2.  A step is
+one full Runge-Kutta step (four fused stage launches over all cells).
+
+Prints one JSON line: DoF-updates/s over the timed steps, the stage kernel's
+HBM roofline fraction (algorithmic bytes / measured launch time, against
+8 TB/s), and the CPU oracle's rate on a bounded sample of the same workload.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--copy-probe]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(budget_s=12.0):
+    """The oracle (assembled CSR + classical RK4) on a reduced grid with the
+    same per-cell structure: 64 x 8 cells of the same shock, k=2, l_max=3.
+    SciPy's CSR product runs on one thread."""
+    import numpy as np
+    from oracle import dg
+    from paper_2501_05110_amd import workloads as W
+
+    wl = W.config2(nx=64, np_=8)
+    t0 = time.perf_counter()
+    S = dg.assemble(wl)
+    t_asm = time.perf_counter() - t0
+    z = wl.meta["init"].ravel().copy()
+    # dt as the GPU run would use it on this grid is irrelevant for the rate
+    dt = 1e-3
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        z = dg.rk4(S, z, dt, 1)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s:
+            break
+    rate = wl.ndofs * steps / el
+    return {"value": rate, "unit": "DoF-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"same shock on 64x8 cells ({wl.ndofs} DoF), {steps} classical RK4 steps "
+                      f"in {el:.1f} s after {t_asm:.1f} s assembly; per-DoF rate of the "
+                      f"1024x128 workload's structure",
+            "cpu_model": cpu_model(), "os_cpu_count": os.cpu_count(),
+            "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              f"the multi-GPU decomposition is a design note, not a measured path.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2501_05110_amd import vfp, workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    wl = W.config2()
+    op = vfp.Operator(wl)
+    N = op.ndofs
+    dt = op.cfl_dt(wl.courant)
+    u = torch.from_numpy(np.ascontiguousarray(wl.meta["init"]).ravel()).to(dev)
+    work = torch.empty(2 * N, dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    op.advance(u, dt, args.warmup, work)
+    torch.cuda.synchronize()
+
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    op.advance(u, dt, args.steps, work)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    if not torch.isfinite(u).all():
+        print("state is not finite after the timed steps", file=sys.stderr)
+        sys.exit(1)
+
+    secs = gpu_ms / 1e3
+    launches = 4 * args.steps
+    per_launch_s = secs / launches
+    ncells = wl.ncells
+    nb = wl.n_basis
+    # algorithmic bytes per stage launch: stage 1 reads u and writes w (16 B/DoF),
+    # stages 2-4 read w_in and u and write w_out (24 B/DoF); plus the input
+    # fields at the resolution they cross the ABI (nu per cell, s at the volume
+    # points, the 1-D profiles)
+    field_bytes = 8 * ncells + 8 * ncells * nb + 8 * (1024 * 3 * 4 + 1025 + 128 * 3 * 4 + 129)
+    bytes_per_launch = N * (16 + 24 * 3) / 4 + field_bytes
+    achieved = bytes_per_launch / per_launch_s / 1e9
+    out = {
+        "metric": "DG-SH operator DoF-updates/s (FP64)",
+        "value": N * args.steps / secs,
+        "unit": "DoF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": gpu_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "cells": list(wl.ncells_axis), "k": wl.k,
+                   "lmax": wl.lmax, "ndofs": N, "dt": dt, "courant": wl.courant,
+                   "stage_launches": launches, "wall_s": wall},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "stage_kernel<2,2,3,true,true>",
+                     "bytes_per_launch": bytes_per_launch, "us_per_launch": per_launch_s * 1e6},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -8,6 +8,7 @@ constexpr int kMaxLmax = 7;
 constexpr int kMaxN = (kMaxLmax + 1) * (kMaxLmax + 1);
 constexpr int kMaxK = 2;
 constexpr int kMaxUniSlots = 24;   // max non-zeros per row of a uniform-axis face matrix
+constexpr int kRec = 16;           // doubles per packed x / p scalar record
 
 // One-dimensional basis data for degree K on the reference interval [-1,1]:
 // Gauss-Lobatto Lagrange basis l_j, (K+1)-point Gauss rule (g_q, w_q), and
@@ -39,6 +40,10 @@ struct RowTables {
   const double* w_row;  // (lmax+1) slots: W[row][i]
   const double* w_col;  // (lmax+1) slots: W[member j][pos(row)]
   const double* lam;    // eigenvalue of characteristic pos(row)
+  // rotation row (B . Omega) for a uniform B, padded to nrot slots
+  const int* rot_col;
+  const double* rot_val;
+  int nrot;
   // uniform-axis face matrices beta^a and |beta^a| (per spatial axis)
   const int* fb_col[3];
   const double* fb_val[3];
@@ -62,10 +67,18 @@ struct FieldArgs {
   const double* ig_vol;   // q/(gamma m)
   const double* iV_face;  // 1/V at p faces
   double V0, iV0, ig0;    // fixed-momentum values
-  // p-face upwind data: code per (x point, p face): -1 beta>=0, -2 beta<=0,
-  // >= 0 index into pf_tab ([code][n][lmax+1] rows of beta_+ in the block)
+  // p-face upwind data: code per (p face, x point) stored [pf][x point]:
+  // -1 beta>=0, -2 beta<=0, >= 0 index into pf_tab ([code][n][lmax+1] rows of
+  // beta_+ in the block)
   const int* pf_code;
   const double* pf_tab;
+  // packed per-cell-row scalars for the (x, ln p) kernel (kRec doubles each):
+  // xrec[ix]: t_adv (2/h_x) U(x_q) [3], U'(x_q) [3], t_mom dU/dt(x_q) [3],
+  //           t_adv U at the lo / hi face [2], 2/h_x
+  // prec[ip]: V(p_q) [3], 1/V [3], m/(gamma p) [3], t_rot q/(gamma m) [3],
+  //           t_mom / V at the lo / hi face [2], 2/h_p
+  const double* xrec;
+  const double* prec;
   // magnetic field
   double B[3];            // uniform B
   const double* B_pts;    // [cell][q][3] or null

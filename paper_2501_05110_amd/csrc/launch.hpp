@@ -12,6 +12,10 @@ using StageLauncher = void (*)(const KernelArgs&, hipStream_t);
 // profile), or nullptr if that combination is not built.
 StageLauncher find_stage_launcher(int D, int k, int lmax, bool mom, bool xprof);
 
+// Specialised kernel for two axes (x, ln p) with a planar x flow and a
+// uniform B; nrot = padded non-zeros per row of B.Omega (1 or 5).
+StageLauncher find_shock_launcher(int k, int lmax, int nrot);
+
 hipError_t upload_basis(const Basis1D* b);
 
 int stage_cells_per_block(int lmax);

@@ -229,7 +229,7 @@ __device__ __forceinline__ void face_axis(const KernelArgs& A, const LaneRows<LM
         const int ix = ic[0] * K1 + fi % K1;
         const double a1 = -F.t_mom * F.a_vol[ix] * iVf;
         const double a2 = -F.t_mom * F.du_vol[ix];
-        const int code = F.pf_code[(size_t)ix * npf + pf];
+        const int code = F.pf_code[(size_t)pf * (M.n[0] * K1) + ix];
         const double* P1 = shc + fi * N;
         const double* P2 = shc + (NF + fi) * N;
         const double* Pu = (code == -1) ? P1 : P2;

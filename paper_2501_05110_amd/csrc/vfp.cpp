@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <new>
@@ -183,7 +184,7 @@ struct vfp_ctx {
   DevBuf d_s2h[3], d_u_vol, d_du_vol, d_a_vol, d_u_face;
   DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face;
   DevBuf d_pf_code, d_pf_tab, d_Bpts, d_nu, d_src;
-  DevBuf d_itab, d_dtab;
+  DevBuf d_itab, d_dtab, d_xrec, d_prec;
   RowTables tab{};
   FieldArgs fld{};
   MeshArgs meshargs{};
@@ -191,6 +192,8 @@ struct vfp_ctx {
   double beta_pmax = 0.0;   // spectral-radius bound of beta^{ln p} over p faces
   double vmax = 0.0;
   double lam_max = 0.0;     // largest eigenvalue of A^x
+  size_t o_rot[2] = {0, 0};
+  bool force_general = false;
 };
 
 namespace {
@@ -352,6 +355,33 @@ int build_row_tables(vfp_ctx* c) {
     if (int e = pack(Ab, o_fa[ax], o_fav[ax], nfa[ax])) return e;
   }
 
+  // B . Omega rows for a uniform B (the kernel multiplies by q/(gamma m))
+  int nrot = 0;
+  {
+    Mat RB(n);
+    for (int cc = 0; cc < 3; ++cc)
+      for (size_t i = 0; i < RB.a.size(); ++i) RB.a[i] += c->B[cc] * S.Om[cc].a[i];
+    for (int i = 0; i < n; ++i) {
+      int nz = 0;
+      for (int j = 0; j < n; ++j) nz += (RB(i, j) != 0.0);
+      nrot = std::max(nrot, nz);
+    }
+    if (nrot > 5) return fail(VFP_EDEVICE, "internal: B.Omega row with %d entries", nrot);
+    nrot = (nrot <= 1) ? 1 : 5;
+    size_t oc = ialloc(size_t(nrot) * n), ov = dalloc(size_t(nrot) * n);
+    for (int i = 0; i < n; ++i) {
+      int slot = 0;
+      for (int j = 0; j < n; ++j)
+        if (RB(i, j) != 0.0) {
+          iv[oc + size_t(slot) * n + i] = j;
+          dv[ov + size_t(slot) * n + i] = RB(i, j);
+          ++slot;
+        }
+      for (; slot < nrot; ++slot) iv[oc + size_t(slot) * n + i] = i;
+    }
+    c->o_rot[0] = oc;
+    c->o_rot[1] = ov;
+  }
   if (int e = upload_vec(c->d_itab, iv)) return e;
   if (int e = upload_vec(c->d_dtab, dv)) return e;
   const int* ib = c->d_itab.as<int>();
@@ -373,6 +403,9 @@ int build_row_tables(vfp_ctx* c) {
   T.w_row = db + o_wrow;
   T.w_col = db + o_wcol;
   T.lam = db + o_lam;
+  T.rot_col = ib + c->o_rot[0];
+  T.rot_val = db + c->o_rot[1];
+  T.nrot = nrot;
   for (int ax = 0; ax < 3; ++ax) {
     T.nfb[ax] = nfb[ax];
     T.nfa[ax] = nfa[ax];
@@ -493,7 +526,7 @@ int build_pface_data(vfp_ctx* c) {
         cd = (int)(tab.size() / ((size_t)n * (L + 1)));
         tab.insert(tab.end(), Bp_rows.begin(), Bp_rows.end());
       }
-      code[(size_t)ix * npf + f] = cd;
+      code[(size_t)f * nxp + ix] = cd;
     }
   }
   if (int e = upload_vec(c->d_pf_code, code)) return e;
@@ -521,12 +554,57 @@ int ensure_device(vfp_ctx* c) {
   return VFP_OK;
 }
 
+// Packed per-x-cell and per-p-cell scalar records (see FieldArgs::xrec).
+int build_records(vfp_ctx* c) {
+  if (!c->mom || !c->mesh_set) return VFP_OK;
+  const int K1 = c->K1, nxc = c->ncell[0], pa = c->naxes - 1, npc = c->ncell[pa];
+  const double ta = (c->terms & VFP_TERM_ADVECTION) ? 1.0 : 0.0;
+  const double tm = (c->terms & VFP_TERM_MOMENTUM) ? 1.0 : 0.0;
+  const double tr = (c->terms & VFP_TERM_ROTATION) ? 1.0 : 0.0;
+  std::vector<double> xr((size_t)nxc * kRec, 0.0), pr((size_t)npc * kRec, 0.0);
+  for (int i = 0; i < nxc; ++i) {
+    const double s2h = 2.0 / (c->nodes[0][i + 1] - c->nodes[0][i]);
+    double* x = &xr[(size_t)i * kRec];
+    for (int q = 0; q < K1; ++q) {
+      x[0 + q] = ta * s2h * c->u_vol[i * K1 + q];
+      x[3 + q] = c->du_vol[i * K1 + q];
+      x[6 + q] = tm * c->a_vol[i * K1 + q];
+    }
+    x[9] = ta * c->u_face[i];
+    x[10] = ta * c->u_face[i + 1];
+    x[11] = s2h;
+  }
+  const std::vector<double>& nd = c->nodes[pa];
+  std::vector<double> g = gauss_points(c->k);
+  for (int j = 0; j < npc; ++j) {
+    double* p = &pr[(size_t)j * kRec];
+    for (int q = 0; q < K1; ++q) {
+      const double pp = std::exp(nd[j] + (1.0 + g[q]) * 0.5 * (nd[j + 1] - nd[j]));
+      const double gam = std::sqrt(1.0 + (pp / c->mass) * (pp / c->mass));
+      p[0 + q] = pp / (gam * c->mass);
+      p[3 + q] = gam * c->mass / pp;
+      p[6 + q] = c->mass / (gam * pp);
+      p[9 + q] = tr * c->charge / (gam * c->mass);
+    }
+    for (int s = 0; s < 2; ++s) {
+      const double pp = std::exp(nd[j + s]);
+      const double gam = std::sqrt(1.0 + (pp / c->mass) * (pp / c->mass));
+      p[12 + s] = tm * gam * c->mass / pp;
+    }
+    p[14] = 2.0 / (nd[j + 1] - nd[j]);
+  }
+  if (int e = upload_vec(c->d_xrec, xr)) return e;
+  if (int e = upload_vec(c->d_prec, pr)) return e;
+  return VFP_OK;
+}
+
 int refresh(vfp_ctx* c) {
   if (!c->mesh_set) return VFP_OK;
   if (int e = ensure_device(c)) return e;
   if (int e = build_row_tables(c)) return e;
   if (int e = build_momentum_data(c)) return e;
   if (int e = build_pface_data(c)) return e;
+  if (int e = build_records(c)) return e;
   FieldArgs& F = c->fld;
   F = FieldArgs{};
   F.u_vol = c->d_u_vol.as<double>();
@@ -548,6 +626,8 @@ int refresh(vfp_ctx* c) {
     c->vmax = F.V0;
   }
   F.pf_code = c->d_pf_code.as<int>();
+  F.xrec = c->d_xrec.as<double>();
+  F.prec = c->d_prec.as<double>();
   F.pf_tab = c->d_pf_tab.as<double>();
   for (int i = 0; i < 3; ++i) F.B[i] = c->B[i];
   F.B_pts = c->have_Bpts ? c->d_Bpts.as<double>() : nullptr;
@@ -563,7 +643,10 @@ int refresh(vfp_ctx* c) {
     // a constant profile
     return VFP_OK;
   }
-  c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
+  c->launcher = nullptr;
+  if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general)
+    c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot);
+  if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
   return VFP_OK;
 }
 
@@ -628,6 +711,10 @@ int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
   c->charge = charge;
   c->mom = mom;
   c->nspace = nsp;
+  {
+    const char* kv = std::getenv("VFP_KERNEL");
+    c->force_general = kv && std::strcmp(kv, "general") == 0;
+  }
   c->S = build_sh_matrices(lmax);
   {
     std::vector<double> lam;

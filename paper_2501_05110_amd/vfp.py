@@ -28,11 +28,12 @@ class VFPError(RuntimeError):
     pass
 
 
-def load(path: str = LIB_PATH):
+def load(path: str = None):
     """Load the built library (never builds it)."""
     global _lib
     if _lib is not None:
         return _lib
+    path = path or os.environ.get("VFP_LIB") or LIB_PATH
     if not os.path.exists(path):
         raise VFPError(f"{path} is missing: build it with `python -m paper_2501_05110_amd.build`")
     # torch's bundled HIP runtime carries the same SONAME as the one libvfp
