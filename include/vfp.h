@@ -160,10 +160,11 @@ int vfp_cfl_dt(const vfp_ctx* ctx, double courant, double* dt);
 int vfp_apply(vfp_ctx* ctx, const double* in, double* out, int with_source,
               void* stream);
 
-/* One fused Runge-Kutta stage: w_out = u + cdt * L(w_in).
- * w_in may equal u; w_out may equal u (then each cell's u is read before it
- * is overwritten) but must not equal w_in unless w_in == u is not also
- * needed by other cells -- i.e. w_out == w_in is rejected. */
+/* One fused Runge-Kutta stage: w_out = u + cdt * L(w_in) (with the source).
+ * All three are device arrays of ndofs doubles.  w_in may equal u.  w_out may
+ * equal u (each lane reads its own u before writing w_out), but w_out must
+ * not equal w_in, because neighbouring cells still read w_in: that case is
+ * rejected with VFP_EINVAL. */
 int vfp_stage(vfp_ctx* ctx, const double* w_in, const double* u, double* w_out,
               double cdt, void* stream);
 

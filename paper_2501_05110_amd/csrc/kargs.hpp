@@ -71,6 +71,7 @@ struct FieldArgs {
   // -1 beta>=0, -2 beta<=0, >= 0 index into pf_tab ([code][n][lmax+1] rows of
   // beta_+ in the block)
   const int* pf_code;
+  const double* pf_coded;   // the same codes as doubles (staged into LDS as is)
   const double* pf_tab;
   // packed per-cell-row scalars for the (x, ln p) kernel (kRec doubles each):
   // xrec[ix]: t_adv (2/h_x) U(x_q) [3], U'(x_q) [3], t_mom dU/dt(x_q) [3],

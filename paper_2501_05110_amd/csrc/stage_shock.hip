@@ -6,7 +6,8 @@
 //
 // Lane = (cell, lms); the cell's (k+1)^2 nodal values of that coefficient stay
 // in registers.  Per Gauss point the lane needs the coefficients
-// (l+-1, m, s), (l+-2, m, s) and the rotation row of its own cell from LDS:
+// (l+-1, m, s), (l+-2, m, s) and the rotation row of its own cell, which are
+// exchanged through LDS:
 //   F^x = U f + V A^x f                                 (advection, x)
 //   F^p = -(dU/dt / V) A^x f - U' (A^x A^x)_t f         (beta^{ln p} f)
 //   G   = (dU/dt / V) G1 f + U' (G2 f - f) - dU/dt m/(gamma p) A^x f
@@ -15,10 +16,12 @@
 //   L = -T(G) + (2/h_x) T'_x(F^x) + (2/h_p) T'_p(F^p) + face lifts + M^{-1} h
 // is contracted row by row of Gauss points (sum factorisation).
 //
-// Latency: every global load (own state, the four neighbour traces and the
-// per-cell field scalars) is issued at the start.  The per-cell scalars are
-// staged once in LDS and read by broadcast.  Faces are processed before the
-// volume so that the nodal state is dead once it has been interpolated.
+// Scheduling.  All global loads (own state, the four neighbour traces, the
+// per-cell field scalars) are issued at the start; the scalars go to LDS.
+// Each face side, and each row of Gauss points, then passes through one small
+// LDS exchange area of 2(k+1) rows per cell, so that few values are live at
+// once.  When a cell's n lanes never straddle a wavefront (n divides 64) the
+// workgroup is one wavefront and the exchanges need no workgroup barrier.
 #include "basis.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -26,9 +29,8 @@
 namespace vfp {
 namespace {
 
-constexpr int kThreads = 256;
 #ifndef VFP_SHOCK_WAVES
-#define VFP_SHOCK_WAVES 3
+#define VFP_SHOCK_WAVES 1
 #endif
 
 // per-cell scalar record in LDS (doubles): the packed x record of the cell's
@@ -51,19 +53,38 @@ enum : int {
 };
 static_assert(kRec == 16, "record layout");
 
+template <int N>
+struct Launch {
+  static constexpr bool kWave = (64 % N) == 0;
+  static constexpr int kThreads = kWave ? 64 : 256;
+  static constexpr int kCells = (kThreads / N) > 0 ? kThreads / N : 1;
+};
+
+// Orders the LDS exchange between the lanes of one cell.  LDS operations of
+// one wavefront complete in order, so within a wavefront a compiler-level
+// fence suffices; otherwise the workgroup synchronises.
+template <int N>
+__device__ __forceinline__ void cell_sync() {
+  if constexpr (Launch<N>::kWave) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 template <int K, int LMAX, int NROT>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(VFP_SHOCK_WAVES)))
+__global__ __launch_bounds__(Launch<(LMAX + 1) * (LMAX + 1)>::kThreads) __attribute__((amdgpu_waves_per_eu(VFP_SHOCK_WAVES)))
 void shock_kernel(KernelArgs A) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
   constexpr int NB = K1 * K1;
-  constexpr int CPB = (kThreads / N) > 0 ? kThreads / N : 1;
-  constexpr int FV = NB;              // volume exchange rows per cell
-  constexpr int FF = 4 * K1;          // face exchange rows per cell
+  constexpr int CPB = Launch<N>::kCells;
+  constexpr int XR = 2 * K1;          // exchange rows per cell
   using CB = CBasis<K>;
   static_assert(K1 <= 3, "basis tables");
-  __shared__ double shv[CPB * FV * N];
-  __shared__ double shf[CPB * FF * N];
+  __shared__ double shx[CPB * XR * N];
   __shared__ double shs[CPB * S_STRIDE];
 
   const int tid = threadIdx.x;
@@ -79,251 +100,213 @@ void shock_kernel(KernelArgs A) {
   const int nx = M.n[0], np = M.n[1];
   const int ix = cell % nx, ip = cell / nx;
   const int clc = in_grp ? cl : 0;
-  double* vol = shv + clc * FV * N;
-  double* fac = shf + clc * FF * N;
+  double* X = shx + clc * XR * N;
   double* sc = shs + clc * S_STRIDE;
 
-  // ---- issue every global load --------------------------------------------
+  // ---- issue every global load, in order of first use ------------------------
+  constexpr int NREC = (kRec + N - 1) / N;
+  constexpr int NCODE = (2 * K1 + N - 1) / N;
+  double rx[NREC], rp[NREC], rcode[NCODE], rnu = 0.0;
+#pragma unroll
+  for (int it = 0; it < NREC; ++it) {
+    const int e = r + it * N;
+    rx[it] = (in_grp && e < kRec) ? F.xrec[(size_t)ix * kRec + e] : 0.0;
+    rp[it] = (in_grp && e < kRec) ? F.prec[(size_t)ip * kRec + e] : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < NCODE; ++it) {
+    const int e = r + it * N;
+    rcode[it] = (in_grp && e < 2 * K1) ? F.pf_coded[(size_t)(ip + e / K1) * (nx * K1) + ix * K1 + e % K1]
+                                       : 0.0;
+  }
+  if (in_grp && r == 0) rnu = F.t_col * (F.nu_cell ? F.nu_cell[cell] : F.nu0);
+
   const size_t cbase = (size_t)cell * NB * N + r;
   const double* win = A.st.w_in + cbase;
   double w[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) w[b] = act ? win[(size_t)b * N] : 0.0;
 
-  // neighbour traces: tnx[side][j] (x faces, nodes along p) and tnp[side][j]
-  // (p faces, nodes along x)
-  double tnx[2][K1], tnp[2][K1];
-  bool use_nx[2], use_np[2];
+  // neighbour traces: tn[axis][side][j]; x faces carry nodes along p, p faces
+  // nodes along x.  Boundary sides are resolved to 0 (zero inflow) or the own
+  // trace (continuous) below.
+  double tn[2][2][K1];
+  bool use_n[2][2];
 #pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    int ni = side ? ix + 1 : ix - 1;
-    const int bc = side ? M.bc_hi[0] : M.bc_lo[0];
-    use_nx[side] = (ni >= 0 && ni < nx) || bc == 0;
-    ni = (ni + nx) % nx;
-    const double* nb0 = A.st.w_in + (size_t)(cell + (ni - ix)) * NB * N + r;
-    const int jn = side ? 0 : K;
+  for (int ax = 0; ax < 2; ++ax)
 #pragma unroll
-    for (int j = 0; j < K1; ++j) tnx[side][j] = (act && use_nx[side]) ? nb0[(size_t)(jn + K1 * j) * N] : 0.0;
-  }
+    for (int side = 0; side < 2; ++side) {
+      const int ia = ax ? ip : ix, na = ax ? np : nx, st = ax ? nx : 1;
+      int ni = side ? ia + 1 : ia - 1;
+      const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
+      use_n[ax][side] = (ni >= 0 && ni < na) || bc == 0;
+      ni = (ni + na) % na;
+      const double* nb0 = A.st.w_in + (size_t)(cell + (ni - ia) * st) * NB * N + r;
+      const int jn = side ? 0 : K;
 #pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    int ni = side ? ip + 1 : ip - 1;
-    const int bc = side ? M.bc_hi[1] : M.bc_lo[1];
-    use_np[side] = (ni >= 0 && ni < np) || bc == 0;
-    ni = (ni + np) % np;
-    const double* nb0 = A.st.w_in + (size_t)(cell + (ni - ip) * nx) * NB * N + r;
-    const int jn = side ? 0 : K;
-#pragma unroll
-    for (int j = 0; j < K1; ++j) tnp[side][j] = (act && use_np[side]) ? nb0[(size_t)(j + K1 * jn) * N] : 0.0;
-  }
-
-  // per-cell scalars: lanes of a cell share the record
-  if (in_grp) {
-    for (int e = r; e < kRec; e += N) {
-      sc[e] = F.xrec[(size_t)ix * kRec + e];
-      sc[kRec + e] = F.prec[(size_t)ip * kRec + e];
+      for (int j = 0; j < K1; ++j) {
+        const int node = ax ? (j + K1 * jn) : (jn + K1 * j);
+        tn[ax][side][j] = (act && use_n[ax][side]) ? nb0[(size_t)node * N] : 0.0;
+      }
     }
-    for (int e = r; e < 2 * K1; e += N)
-      sc[C_CODE + e] = (double)F.pf_code[(size_t)(ip + e / K1) * (nx * K1) + ix * K1 + e % K1];
-    if (r == 0) sc[C_NU] = F.t_col * (F.nu_cell ? F.nu_cell[cell] : F.nu0);
-  }
 
-  // lms rows used by the x faces
+  // rows for the x faces
   int mem[LMAX + 1];
-  double wcol[LMAX + 1];
+  double wcol[LMAX + 1], wrow[LMAX + 1];
 #pragma unroll
   for (int i = 0; i <= LMAX; ++i) {
     mem[i] = T.blk_mem[i * N + r];
     wcol[i] = T.w_col[i * N + r];
+    wrow[i] = T.w_row[i * N + r];
   }
   const double lam = T.lam[r];
 
-  // ---- interpolation: volume points and face points -----------------------
-  {
-    double t[NB];
+  if (in_grp) {
 #pragma unroll
-    for (int j1 = 0; j1 < K1; ++j1)
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        double acc = 0.0;
-#pragma unroll
-        for (int j0 = 0; j0 < K1; ++j0) acc = fma(CB::phi[q0][j0], w[j0 + K1 * j1], acc);
-        t[q0 + K1 * j1] = acc;
+    for (int it = 0; it < NREC; ++it) {
+      const int e = r + it * N;
+      if (e < kRec) {
+        sc[e] = rx[it];
+        sc[kRec + e] = rp[it];
       }
-    if (in_grp) {
-#pragma unroll
-      for (int q1 = 0; q1 < K1; ++q1)
-#pragma unroll
-        for (int q0 = 0; q0 < K1; ++q0) {
-          double acc = 0.0;
-#pragma unroll
-          for (int j1 = 0; j1 < K1; ++j1) acc = fma(CB::phi[q1][j1], t[q0 + K1 * j1], acc);
-          vol[(q0 + K1 * q1) * N + r] = acc;
-        }
     }
+#pragma unroll
+    for (int it = 0; it < NCODE; ++it) {
+      const int e = r + it * N;
+      if (e < 2 * K1) sc[C_CODE + e] = rcode[it];
+    }
+    if (r == 0) sc[C_NU] = rnu;
   }
-  // x faces: LDS rows (side*2 + which)*K1 + q, which 0 = lower cell, 1 = upper
-  {
-    const int bclo = M.bc_lo[0], bchi = M.bc_hi[0];
-    double tr[2][2][K1];
-#pragma unroll
-    for (int j = 0; j < K1; ++j) {
-      tr[0][1][j] = w[0 + K1 * j];
-      tr[1][0][j] = w[K + K1 * j];
-      tr[0][0][j] = use_nx[0] ? tnx[0][j] : (bclo == 1 ? 0.0 : tr[0][1][j]);
-      tr[1][1][j] = use_nx[1] ? tnx[1][j] : (bchi == 1 ? 0.0 : tr[1][0][j]);
-    }
-    if (in_grp) {
-#pragma unroll
-      for (int side = 0; side < 2; ++side)
-#pragma unroll
-        for (int which = 0; which < 2; ++which)
-#pragma unroll
-          for (int q = 0; q < K1; ++q) {
-            double acc = 0.0;
-#pragma unroll
-            for (int j = 0; j < K1; ++j) acc = fma(CB::phi[q][j], tr[side][which][j], acc);
-            fac[((side * 2 + which) * K1 + q) * N + r] = acc;
-          }
-    }
-  }
-  // p-face traces are interpolated now, while w is live, and kept in registers
-  double Fp[2][2][K1];
-  {
-    const int bclo = M.bc_lo[1], bchi = M.bc_hi[1];
-    double tr[2][2][K1];
-#pragma unroll
-    for (int j = 0; j < K1; ++j) {
-      tr[0][1][j] = w[j];
-      tr[1][0][j] = w[j + K1 * K];
-      tr[0][0][j] = use_np[0] ? tnp[0][j] : (bclo == 1 ? 0.0 : tr[0][1][j]);
-      tr[1][1][j] = use_np[1] ? tnp[1][j] : (bchi == 1 ? 0.0 : tr[1][0][j]);
-    }
-#pragma unroll
-    for (int side = 0; side < 2; ++side)
-#pragma unroll
-      for (int which = 0; which < 2; ++which)
-#pragma unroll
-        for (int q = 0; q < K1; ++q) {
-          double acc = 0.0;
-#pragma unroll
-          for (int j = 0; j < K1; ++j) acc = fma(CB::phi[q][j], tr[side][which][j], acc);
-          Fp[side][which][q] = acc;
-        }
-  }
-  __syncthreads();
 
   double res[NB];
 #pragma unroll
   for (int b = 0; b < NB; ++b) res[b] = 0.0;
 
   // ---- x faces: characteristic variables of A^x ------------------------------
-  {
-    double Jc[2][K1];
 #pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const double UF = sc[X_UF + side];
+  for (int side = 0; side < 2; ++side) {
+    double own[K1], oth[K1];
+    const int bc = side ? M.bc_hi[0] : M.bc_lo[0];
 #pragma unroll
-      for (int q = 0; q < K1; ++q) {
-        const double* P1 = fac + ((side * 2 + 0) * K1 + q) * N;
-        const double* P2 = fac + ((side * 2 + 1) * K1 + q) * N;
-        double c1 = 0.0, c2 = 0.0;
-#pragma unroll
-        for (int j = 0; j <= LMAX; ++j) {
-          c1 = fma(wcol[j], P1[mem[j]], c1);
-          c2 = fma(wcol[j], P2[mem[j]], c2);
-        }
-        const double mu = fma(F.t_adv * lam, sc[P_V + q], UF);
-        Jc[side][q] = fmax(mu, 0.0) * c1 + fmin(mu, 0.0) * c2;
-      }
+    for (int j = 0; j < K1; ++j) {
+      own[j] = w[(side ? K : 0) + K1 * j];
+      oth[j] = use_n[0][side] ? tn[0][side][j] : (bc == 1 ? 0.0 : own[j]);
     }
-    __syncthreads();
+    // lower cell's trace to rows [0, K1), upper cell's to rows [K1, 2 K1)
     if (in_grp) {
 #pragma unroll
-      for (int side = 0; side < 2; ++side)
-#pragma unroll
-        for (int q = 0; q < K1; ++q) fac[(side * K1 + q) * N + r] = Jc[side][q];
-    }
-    __syncthreads();
-    double wrow[LMAX + 1];
-#pragma unroll
-    for (int i = 0; i <= LMAX; ++i) wrow[i] = T.w_row[i * N + r];
-    const double s2hx = sc[X_S2H];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      double J[K1];
-#pragma unroll
       for (int q = 0; q < K1; ++q) {
-        const double* P = fac + (side * K1 + q) * N;
-        double acc = 0.0;
+        double a = 0.0, b = 0.0;
 #pragma unroll
-        for (int i = 0; i <= LMAX; ++i) acc = fma(wrow[i], P[mem[i]], acc);
-        J[q] = acc;
-      }
-      const double scl = side ? -s2hx : s2hx;
-#pragma unroll
-      for (int i1 = 0; i1 < K1; ++i1) {
-        double jn = 0.0;
-#pragma unroll
-        for (int q = 0; q < K1; ++q)
-          if (CB::tst[i1][q] != 0.0) jn = fma(CB::tst[i1][q], J[q], jn);
-        jn *= scl;
-#pragma unroll
-        for (int i0 = 0; i0 < K1; ++i0) res[i0 + K1 * i1] = fma(CB::lift[side][i0], jn, res[i0 + K1 * i1]);
+        for (int j = 0; j < K1; ++j) {
+          a = fma(CB::phi[q][j], side ? own[j] : oth[j], a);
+          b = fma(CB::phi[q][j], side ? oth[j] : own[j], b);
+        }
+        X[q * N + r] = a;
+        X[(K1 + q) * N + r] = b;
       }
     }
+    cell_sync<N>();
+    double Jc[K1];
+    const double UF = sc[X_UF + side];
+#pragma unroll
+    for (int q = 0; q < K1; ++q) {
+      double c1 = 0.0, c2 = 0.0;
+#pragma unroll
+      for (int j = 0; j <= LMAX; ++j) {
+        c1 = fma(wcol[j], X[q * N + mem[j]], c1);
+        c2 = fma(wcol[j], X[(K1 + q) * N + mem[j]], c2);
+      }
+      const double mu = fma(F.t_adv * lam, sc[P_V + q], UF);
+      Jc[q] = fmax(mu, 0.0) * c1 + fmin(mu, 0.0) * c2;
+    }
+    cell_sync<N>();
+    if (in_grp) {
+#pragma unroll
+      for (int q = 0; q < K1; ++q) X[q * N + r] = Jc[q];
+    }
+    cell_sync<N>();
+    double J[K1];
+#pragma unroll
+    for (int q = 0; q < K1; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int i = 0; i <= LMAX; ++i) acc = fma(wrow[i], X[q * N + mem[i]], acc);
+      J[q] = acc;
+    }
+    const double scl = side ? -sc[X_S2H] : sc[X_S2H];
+#pragma unroll
+    for (int i1 = 0; i1 < K1; ++i1) {
+      double jn = 0.0;
+#pragma unroll
+      for (int q = 0; q < K1; ++q)
+        if (CB::tst[i1][q] != 0.0) jn = fma(CB::tst[i1][q], J[q], jn);
+      jn *= scl;
+#pragma unroll
+      for (int i0 = 0; i0 < K1; ++i0) res[i0 + K1 * i1] = fma(CB::lift[side][i0], jn, res[i0 + K1 * i1]);
+    }
+    cell_sync<N>();
   }
-  __syncthreads();
 
   // ---- ln p faces: beta^{ln p} = a1 A^x + a2 (A^x A^x)_t per point ---------
   const int axc0 = T.ax_col[r], axc1 = T.ax_col[N + r];
   const double axv0 = T.ax_val[r], axv1 = T.ax_val[N + r];
   const int axxc0 = T.axx_col[r], axxc1 = T.axx_col[N + r];
   const double axxv0 = T.axx_val[r], axxv1 = T.axx_val[N + r], axxv2 = T.axx_val[2 * N + r];
-  {
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    double own[K1], oth[K1];
+    const int bc = side ? M.bc_hi[1] : M.bc_lo[1];
+#pragma unroll
+    for (int j = 0; j < K1; ++j) {
+      own[j] = w[j + K1 * (side ? K : 0)];
+      oth[j] = use_n[1][side] ? tn[1][side][j] : (bc == 1 ? 0.0 : own[j]);
+    }
     if (in_grp) {
 #pragma unroll
-      for (int side = 0; side < 2; ++side)
-#pragma unroll
-        for (int which = 0; which < 2; ++which)
-#pragma unroll
-          for (int q = 0; q < K1; ++q) fac[((side * 2 + which) * K1 + q) * N + r] = Fp[side][which][q];
-    }
-    __syncthreads();
-    const double s2hp = sc[P_S2H];
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const double iVf = sc[P_IVF + side];
-      double J[K1];
-#pragma unroll
       for (int q = 0; q < K1; ++q) {
-        const double a1 = -sc[X_A + q] * iVf;
-        const double a2 = -F.t_mom * sc[X_DU + q];
-        const int code = (int)sc[C_CODE + side * K1 + q];
-        const double* P1 = fac + ((side * 2 + 0) * K1 + q) * N;
-        const double* P2 = fac + ((side * 2 + 1) * K1 + q) * N;
-        const double* Pu = (code == -1) ? P1 : P2;
-        double jv = a1 * fma(axv0, Pu[axc0], axv1 * Pu[axc1]) +
-                    a2 * fma(axxv0, Pu[axxc0], fma(axxv1, Pu[r], axxv2 * Pu[axxc1]));
-        if (code >= 0) {
-          const double* tb = F.pf_tab + ((size_t)code * N + r) * (LMAX + 1);
+        double a = 0.0, b = 0.0;
 #pragma unroll
-          for (int i = 0; i <= LMAX; ++i) jv = fma(tb[i], P1[mem[i]] - P2[mem[i]], jv);
+        for (int j = 0; j < K1; ++j) {
+          a = fma(CB::phi[q][j], side ? own[j] : oth[j], a);
+          b = fma(CB::phi[q][j], side ? oth[j] : own[j], b);
         }
-        J[q] = jv;
-      }
-      const double scl = side ? -s2hp : s2hp;
-#pragma unroll
-      for (int i0 = 0; i0 < K1; ++i0) {
-        double jn = 0.0;
-#pragma unroll
-        for (int q = 0; q < K1; ++q)
-          if (CB::tst[i0][q] != 0.0) jn = fma(CB::tst[i0][q], J[q], jn);
-        jn *= scl;
-#pragma unroll
-        for (int i1 = 0; i1 < K1; ++i1) res[i0 + K1 * i1] = fma(CB::lift[side][i1], jn, res[i0 + K1 * i1]);
+        X[q * N + r] = a;
+        X[(K1 + q) * N + r] = b;
       }
     }
+    cell_sync<N>();
+    const double iVf = sc[P_IVF + side];
+    double J[K1];
+#pragma unroll
+    for (int q = 0; q < K1; ++q) {
+      const double a1 = -sc[X_A + q] * iVf;
+      const double a2 = -F.t_mom * sc[X_DU + q];
+      const int code = (int)sc[C_CODE + side * K1 + q];
+      const double* P1 = X + q * N;
+      const double* P2 = X + (K1 + q) * N;
+      const double* Pu = (code == -1) ? P1 : P2;
+      double jv = a1 * fma(axv0, Pu[axc0], axv1 * Pu[axc1]) +
+                  a2 * fma(axxv0, Pu[axxc0], fma(axxv1, Pu[r], axxv2 * Pu[axxc1]));
+      if (code >= 0) {
+        const double* tb = F.pf_tab + ((size_t)code * N + r) * (LMAX + 1);
+#pragma unroll
+        for (int i = 0; i <= LMAX; ++i) jv = fma(tb[i], P1[mem[i]] - P2[mem[i]], jv);
+      }
+      J[q] = jv;
+    }
+    const double scl = side ? -sc[P_S2H] : sc[P_S2H];
+#pragma unroll
+    for (int i0 = 0; i0 < K1; ++i0) {
+      double jn = 0.0;
+#pragma unroll
+      for (int q = 0; q < K1; ++q)
+        if (CB::tst[i0][q] != 0.0) jn = fma(CB::tst[i0][q], J[q], jn);
+      jn *= scl;
+#pragma unroll
+      for (int i1 = 0; i1 < K1; ++i1) res[i0 + K1 * i1] = fma(CB::lift[side][i1], jn, res[i0 + K1 * i1]);
+    }
+    cell_sync<N>();
   }
 
   // u (the stage base) is loaded now so that its latency hides behind the
@@ -334,7 +317,7 @@ void shock_kernel(KernelArgs A) {
 #pragma unroll
   for (int b = 0; b < NB; ++b) uu[b] = (act && use_u) ? A.st.u[cbase + (size_t)b * N] : 0.0;
 
-  // ---- volume -------------------------------------------------------------
+  // ---- volume, one row of Gauss points (fixed q1) at a time -----------------
   {
     const double g1v0 = T.g1_val[r], g1v1 = T.g1_val[N + r];
     const double g2v0 = T.g2_val[r], g2v1 = T.g2_val[N + r], g2v2 = T.g2_val[2 * N + r];
@@ -349,8 +332,30 @@ void shock_kernel(KernelArgs A) {
     const double mom_s2hp = -F.t_mom * sc[P_S2H];
     const double t_adv = F.t_adv, t_mom = F.t_mom;
     const double tas2hx = t_adv * sc[X_S2H];
+    // interpolate along x once: t[q0 + K1 j1]
+    double t[NB];
+#pragma unroll
+    for (int j1 = 0; j1 < K1; ++j1)
+#pragma unroll
+      for (int q0 = 0; q0 < K1; ++q0) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j0 = 0; j0 < K1; ++j0) acc = fma(CB::phi[q0][j0], w[j0 + K1 * j1], acc);
+        t[q0 + K1 * j1] = acc;
+      }
 #pragma unroll
     for (int q1 = 0; q1 < K1; ++q1) {
+      if (in_grp) {
+#pragma unroll
+        for (int q0 = 0; q0 < K1; ++q0) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j1 = 0; j1 < K1; ++j1)
+            if (CB::phi[q1][j1] != 0.0) acc = fma(CB::phi[q1][j1], t[q0 + K1 * j1], acc);
+          X[q0 * N + r] = acc;
+        }
+      }
+      cell_sync<N>();
       const double pV = tas2hx * sc[P_V + q1];
       const double piV = sc[P_IV + q1];
       const double pid = sc[P_ID + q1];
@@ -363,7 +368,7 @@ void shock_kernel(KernelArgs A) {
         const double U = sc[X_U + q0];
         const double dU = sc[X_DU + q0];
         const double a = sc[X_A + q0];
-        const double* P = vol + (q0 + K1 * q1) * N;
+        const double* P = X + q0 * N;
         const double f = P[r];
         const double fxp = P[axc0], fxm = P[axc1];
         const double fpp = P[axxc0], fmm = P[axxc1];
@@ -375,7 +380,7 @@ void shock_kernel(KernelArgs A) {
         const double A2f = fma(axxv0, fpp, fma(axxv1, f, axxv2 * fmm));
         const double G2f = fma(g2v0, fpp, fma(g2v1, f, g2v2 * fmm));
         const double aiV = a * piV;
-        const double X = fma(U, f, pV * Axf);
+        const double Xf = fma(U, f, pV * Axf);
         const double Pp = mom_s2hp * fma(aiV, Axf, dU * A2f);
         double G = fma(aiV, G1f, dU * fma(t_mom, G2f, -t_adv * f));
         G = fma(-a * pid, Axf, G);
@@ -384,7 +389,7 @@ void shock_kernel(KernelArgs A) {
 #pragma unroll
         for (int i = 0; i < K1; ++i) {
           if (CB::tst[i][q0] != 0.0) ac[i] = fma(-CB::tst[i][q0], G, ac[i]);
-          if (CB::dtst[i][q0] != 0.0) ac[i] = fma(CB::dtst[i][q0], X, ac[i]);
+          if (CB::dtst[i][q0] != 0.0) ac[i] = fma(CB::dtst[i][q0], Xf, ac[i]);
           if (CB::tst[i][q0] != 0.0) bc[i] = fma(CB::tst[i][q0], Pp, bc[i]);
         }
       }
@@ -397,13 +402,17 @@ void shock_kernel(KernelArgs A) {
           if (CB::dtst[i1][q1] != 0.0) v = fma(CB::dtst[i1][q1], bc[i0], v);
           res[i0 + K1 * i1] = v;
         }
+      cell_sync<N>();
     }
   }
 
   // ---- source and output ---------------------------------------------------
-  if (A.st.with_source && F.src && r == 0) {
+  if (A.st.with_source && F.src && r == 0 && act) {
+    double src[NB];
 #pragma unroll
-    for (int b = 0; b < NB; ++b) res[b] += F.src[(size_t)cell * NB + b];
+    for (int b = 0; b < NB; ++b) src[b] = F.src[(size_t)cell * NB + b];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) res[b] += src[b];
   }
   if (act) {
     const double al = A.st.alpha, be = A.st.beta;
@@ -415,9 +424,9 @@ void shock_kernel(KernelArgs A) {
 template <int K, int LMAX, int NROT>
 void launch_shock_t(const KernelArgs& a, hipStream_t s) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
-  constexpr int CPB = (kThreads / N) > 0 ? kThreads / N : 1;
-  const int blocks = (a.mesh.ncells + CPB - 1) / CPB;
-  hipLaunchKernelGGL((shock_kernel<K, LMAX, NROT>), dim3(blocks), dim3(kThreads), 0, s, a);
+  using L = Launch<N>;
+  const int blocks = (a.mesh.ncells + L::kCells - 1) / L::kCells;
+  hipLaunchKernelGGL((shock_kernel<K, LMAX, NROT>), dim3(blocks), dim3(L::kThreads), 0, s, a);
 }
 
 template <int K, int NROT>

@@ -183,7 +183,7 @@ struct vfp_ctx {
   // device data
   DevBuf d_s2h[3], d_u_vol, d_du_vol, d_a_vol, d_u_face;
   DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face;
-  DevBuf d_pf_code, d_pf_tab, d_Bpts, d_nu, d_src;
+  DevBuf d_pf_code, d_pf_coded, d_pf_tab, d_Bpts, d_nu, d_src;
   DevBuf d_itab, d_dtab, d_xrec, d_prec;
   RowTables tab{};
   FieldArgs fld{};
@@ -530,6 +530,8 @@ int build_pface_data(vfp_ctx* c) {
     }
   }
   if (int e = upload_vec(c->d_pf_code, code)) return e;
+  std::vector<double> coded(code.begin(), code.end());
+  if (int e = upload_vec(c->d_pf_coded, coded)) return e;
   if (tab.empty()) tab.assign((size_t)n * (L + 1), 0.0);
   if (int e = upload_vec(c->d_pf_tab, tab)) return e;
   return VFP_OK;
@@ -626,6 +628,7 @@ int refresh(vfp_ctx* c) {
     c->vmax = F.V0;
   }
   F.pf_code = c->d_pf_code.as<int>();
+  F.pf_coded = c->d_pf_coded.as<double>();
   F.xrec = c->d_xrec.as<double>();
   F.prec = c->d_prec.as<double>();
   F.pf_tab = c->d_pf_tab.as<double>();
