@@ -176,6 +176,77 @@ int vfp_stage(vfp_ctx* ctx, const double* w_in, const double* u, double* w_out,
 int vfp_advance(vfp_ctx* ctx, double* u, double dt, int64_t nsteps,
                 double* work, void* stream);
 
+/* ------------------------------------------------------------------ adjoint
+ *
+ * The linear part of L is  L_lin = -M^{-1} D  (eq. matrix-formulation-system-odes
+ * without h).  Its Euclidean transpose is  L_lin^T = -D^T M^{-1}  (M is
+ * symmetric).  The reverse-mode calls below run in the variable
+ * mu = M^{-1} lambda, where the transposed operator reads
+ *     K = M^{-1} L_lin^T M = -M^{-1} D^T,
+ * which couples cells through face-node traces only, like the forward
+ * operator.  D^T: volume blocks transposed (beta^a symmetric, R^T with
+ * Omega^T = -Omega), and on a face from T1 to T2 with B = n.beta (eq.
+ * definition-upwind-flux) the blocks B_+ and B_- trade places between the
+ * rows: T1 receives B_+ (mu_1 - mu_2), T2 receives -B_- (mu_1 - mu_2).
+ *
+ * Scattering enters L as -nu_c l(l+1)/2 per coefficient of cell c (the GL(k+1)
+ * mass matrix of the collision term cancels against M^{-1}), so
+ *     d L(w) / d nu_c = -C w  on the degrees of freedom of cell c.
+ */
+
+/* out = M in (inverse = 0) or M^{-1} in (inverse != 0), cell by cell, with M
+ * the DG mass matrix of eq. definition-mass-and-dg-matrix.  in may equal out. */
+int vfp_mass(vfp_ctx* ctx, const double* in, double* out, int inverse, void* stream);
+
+/* out = -D^T M^{-1} in  (the transpose of the linear part of vfp_apply; the
+ * source does not enter).  in, out: device, ndofs doubles, must not alias.
+ * Uses a library-owned scratch vector of ndofs doubles, allocated on the first
+ * call (VFP_ENOMEM if that fails); calls on one context that overlap in time
+ * race on it. */
+int vfp_apply_adjoint(vfp_ctx* ctx, const double* in, double* out, void* stream);
+
+/* One adjoint Runge-Kutta stage in mu variables:
+ *     t = cdt K(mu_in);   t_out = t (if t_out != NULL);   acc_out = acc_in + t.
+ * If grad_nu != NULL (fwd must then be given), also
+ *     grad_nu[c] += -cdt sum_{b, lms in c} (l(l+1)/2) (M mu_in)_{b,lms} fwd_{b,lms}
+ * which is d/dnu_c of <M mu_in, cdt L(fwd)>: fwd is the forward stage input
+ * that this adjoint stage transposes.  acc_in may equal mu_in; acc_out may
+ * equal acc_in; t_out and acc_out must not overlap mu_in, and t_out must not
+ * overlap acc_in or acc_out (VFP_EINVAL). */
+int vfp_adjoint_stage(vfp_ctx* ctx, const double* mu_in, const double* acc_in, const double* fwd,
+                      double cdt, double* t_out, double* acc_out, double* grad_nu, void* stream);
+
+/* Forward steps as vfp_advance, keeping every stage vector: tape holds
+ * 4 nsteps ndofs doubles, step s storing w_1, w_2, w_3 and u_{s+1} in slots
+ * 4s .. 4s+3.  u0 is read only; the final state is slot 4 nsteps - 1. */
+int vfp_advance_tape(vfp_ctx* ctx, const double* u0, double dt, int64_t nsteps, double* tape,
+                     void* stream);
+
+/* Reverse sweep over a taped run of nsteps steps from u0 (the same u0, dt and
+ * tape as vfp_advance_tape).  On entry mu = M^{-1} dJ/du_nsteps; on exit
+ * mu = M^{-1} dJ/du_0.  Because every 4-stage fourth-order scheme has the
+ * step map P(dt L_lin) = 1 + dt L_lin + ... + (dt L_lin)^4/24 on this
+ * linear autonomous system, each step maps mu to P(dt K) mu.
+ * grad_nu (ncells doubles, may be NULL) accumulates dJ/dnu_c.
+ * work: 3 ndofs doubles. */
+int vfp_adjoint_steps(vfp_ctx* ctx, const double* u0, const double* tape, double dt, int64_t nsteps,
+                      double* mu, double* grad_nu, double* work, void* stream);
+
+/* vfp_advance with checkpoints: before each segment of seg steps the current
+ * u is copied into ckpt[j] (ckpt: ceil(nsteps/seg) ndofs doubles).  work:
+ * 2 ndofs doubles. */
+int vfp_forward_checkpoints(vfp_ctx* ctx, double* u, double dt, int64_t nsteps, int64_t seg,
+                            double* ckpt, double* work, void* stream);
+
+/* Reverse pass over a checkpointed run: for each segment, last first, the
+ * forward steps are replayed from its checkpoint into tape
+ * (4 min(seg, nsteps) ndofs doubles) and swept back with vfp_adjoint_steps.
+ * lam: on entry dJ/du_nsteps, on exit dJ/du_0 (Euclidean gradients).
+ * grad_nu (ncells doubles, may be NULL) accumulates dJ/dnu_c.  work: 3 ndofs
+ * doubles.  All buffers must be disjoint. */
+int vfp_adjoint_checkpointed(vfp_ctx* ctx, const double* ckpt, double dt, int64_t nsteps, int64_t seg,
+                             double* tape, double* lam, double* grad_nu, double* work, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -411,6 +411,69 @@ def rk4(sysm: System, zeta, dt, nsteps, with_source=True):
     return z
 
 
+def collision_system(wl) -> System:
+    """The collision part alone with nu = 1 in every cell: its D is
+    sum_c (M_c x C) restricted to cell c, so that d D / d nu_c is that block
+    (the nu C term of R in eq. definitions-advection-reaction-eq, integrated
+    as in eq. definition-mass-and-dg-matrix)."""
+    from dataclasses import replace
+    return assemble(replace(wl, terms=frozenset({"collision"}), nu=1.0, source=None))
+
+
+def rk4_gradient(sysm: System, zeta0, dt, nsteps, dJ_dzN, dsys=None, with_source=True):
+    """Reverse mode of `rk4` for a loss J(zeta_N) with dJ/dzeta_N given.
+
+    Returns (dJ/dzeta_0, dJ/dnu) where dJ/dnu (one value per cell) is formed
+    when `dsys` (from `collision_system`) is given: d apply(x)/d nu_c is
+    -M^{-1} (dD/dnu_c) x.  Each classical RK4 stage is transposed in turn;
+    the forward states are kept for every step.
+    """
+    z = np.asarray(zeta0, float).ravel().copy()
+    states = []
+    for _ in range(nsteps):
+        states.append(z.copy())
+        k1 = apply(sysm, z, with_source)
+        k2 = apply(sysm, z + 0.5 * dt * k1, with_source)
+        k3 = apply(sysm, z + 0.5 * dt * k2, with_source)
+        k4 = apply(sysm, z + dt * k3, with_source)
+        z = z + dt / 6.0 * (k1 + 2 * k2 + 2 * k3 + k4)
+    ncells, nb, n = sysm.shape
+    gnu = np.zeros(ncells) if dsys is not None else None
+
+    def dnu(kbar, x):
+        if gnu is None:
+            return
+        t = -(sysm.Minv @ (dsys.D @ x))
+        gnu[:] += (kbar * t).reshape(ncells, nb * n).sum(axis=1)
+
+    zbar = np.asarray(dJ_dzN, float).ravel().copy()
+    for zs in reversed(states):
+        k1 = apply(sysm, zs, with_source)
+        x2 = zs + 0.5 * dt * k1
+        k2 = apply(sysm, x2, with_source)
+        x3 = zs + 0.5 * dt * k2
+        k3 = apply(sysm, x3, with_source)
+        x4 = zs + dt * k3
+        kb1, kb2, kb3, kb4 = dt / 6.0 * zbar, dt / 3.0 * zbar, dt / 3.0 * zbar, dt / 6.0 * zbar
+        znew = zbar.copy()
+        dnu(kb4, x4)
+        xb4 = apply_adjoint(sysm, kb4)
+        znew += xb4
+        kb3 = kb3 + dt * xb4
+        dnu(kb3, x3)
+        xb3 = apply_adjoint(sysm, kb3)
+        znew += xb3
+        kb2 = kb2 + 0.5 * dt * xb3
+        dnu(kb2, x2)
+        xb2 = apply_adjoint(sysm, kb2)
+        znew += xb2
+        kb1 = kb1 + 0.5 * dt * xb2
+        dnu(kb1, zs)
+        znew += apply_adjoint(sysm, kb1)
+        zbar = znew
+    return zbar, gnu
+
+
 def steady_state(sysm: System):
     """Solve D zeta = h (sparse LU)."""
     return spla.spsolve(sysm.D.tocsc(), sysm.h)

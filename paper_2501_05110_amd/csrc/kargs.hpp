@@ -18,6 +18,9 @@ struct Basis1D {
   double tst[3][3];    // tst[i][q]  = sum_j (M1^{-1})_ij l_j(g_q) w_q
   double dtst[3][3];   // dtst[i][q] = sum_j (M1^{-1})_ij l_j'(g_q) w_q
   double lift[2][3];   // lift[side][i] = (M1^{-1})_{i, 0 or K}
+  double dphi[3][3];   // dphi[q][j] = l_j'(g_q)
+  double mass[3][3];   // M1
+  double imass[3][3];  // M1^{-1}
 };
 
 // Per-row (lms) sparse rows of the spherical-harmonic matrices, stored
@@ -30,6 +33,8 @@ struct RowTables {
   const int* axx_col;   // 2 slots: (l+2,m,s), (l-2,m,s)            (A^x A^x)_t
   const double* axx_val;// 3 slots: l+2, self, l-2
   const double* g2_val; // same columns: (A^x (A^y Om^z - A^z Om^y))_t
+  const double* g1t_val;// transposes of G1 and G2 on the same (symmetric) patterns
+  const double* g2t_val;
   const int* om_col;    // 3 matrices x 2 slots: Omega^x, Omega^y, Omega^z
   const double* om_val;
   const int* ayz_col;   // 2 matrices x 4 slots: A^y, A^z
@@ -107,11 +112,22 @@ struct StageArgs {
   int with_source;
 };
 
+// Extra outputs of the adjoint kernels (operator K = -M^{-1} D^T, acting on
+// mu = M^{-1} lambda).  With st.alpha = 1 the kernel forms t = beta K(w_in),
+// writes t_out (if not null) and w_out = u + t.
+struct AdjArgs {
+  double* t_out;          // may be null
+  const double* fwd;      // forward stage input paired with w_in for d/dnu, or null
+  double* grad_nu;        // [cell] accumulated: -beta t_col sum C (M fwd) . w_in
+  int mass_out;           // 1: multiply the result by the cell mass matrix
+};
+
 struct KernelArgs {
   MeshArgs mesh;
   FieldArgs fld;
   RowTables tab;
   StageArgs st;
+  AdjArgs adj;
 };
 
 }  // namespace vfp

@@ -89,6 +89,59 @@ __device__ __forceinline__ void interp(const double* w, double* f) {
   }
 }
 
+// Interpolate nodal values to the Gauss points with the derivative l_j' along
+// axis DER and l_j along the others (reference coordinates).
+template <int D, int K, int DER>
+__device__ __forceinline__ void interp_deriv(const double* w, double* f) {
+  constexpr int K1 = K + 1;
+  constexpr int NB = IPow<K1, D>::v;
+  const Basis1D& bs = c_basis[K - 1];
+  if constexpr (D == 1) {
+    sweep<1, K1, 0>(w, f, bs.dphi);
+  } else if constexpr (D == 2) {
+    double t[NB];
+    sweep<2, K1, 0>(w, t, DER == 0 ? bs.dphi : bs.phi);
+    sweep<2, K1, 1>(t, f, DER == 1 ? bs.dphi : bs.phi);
+  } else {
+    double t[NB];
+    sweep<3, K1, 0>(w, f, DER == 0 ? bs.dphi : bs.phi);
+    sweep<3, K1, 1>(f, t, DER == 1 ? bs.dphi : bs.phi);
+    sweep<3, K1, 2>(t, f, DER == 2 ? bs.dphi : bs.phi);
+  }
+}
+
+// v <- (M1 x ... x M1) v (INV: the inverse) on the reference cell, in place;
+// the caller supplies the Jacobian factor.
+template <int D, int K, bool INV>
+__device__ __forceinline__ void ref_mass(double* v) {
+  constexpr int K1 = K + 1;
+  constexpr int NB = IPow<K1, D>::v;
+  const Basis1D& bs = c_basis[K - 1];
+  const double(&Mm)[3][3] = INV ? bs.imass : bs.mass;
+  double t[NB];
+  sweep<D, K1, 0>(v, t, Mm);
+  if constexpr (D == 1) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v[i] = t[i];
+  } else if constexpr (D == 2) {
+    sweep<D, K1, 1>(t, v, Mm);
+  } else {
+    sweep<D, K1, 1>(t, v, Mm);
+    sweep<D, K1, 2>(v, t, Mm);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) v[i] = t[i];
+  }
+}
+
+// Jacobian of the affine map of cell ic: prod_a h_a / 2.
+template <int D>
+__device__ __forceinline__ double cell_jacobian(const MeshArgs& M, const int* ic) {
+  double j = 1.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) j /= M.s2h[a][ic[a]];
+  return j;
+}
+
 // Face helpers: a face normal to axis AX has (K+1)^(D-1) points; face index
 // fi enumerates the remaining axes in increasing order, lowest fastest.
 template <int D, int K, int AX>

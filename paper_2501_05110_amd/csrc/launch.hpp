@@ -12,6 +12,13 @@ using StageLauncher = void (*)(const KernelArgs&, hipStream_t);
 // profile), or nullptr if that combination is not built.
 StageLauncher find_stage_launcher(int D, int k, int lmax, bool mom, bool xprof);
 
+// Adjoint kernel (K = -M^{-1} D^T on mu = M^{-1} lambda) for the same families.
+StageLauncher find_adjoint_launcher(int D, int k, int lmax, bool mom, bool xprof);
+
+// out = M in (inv = false) or M^{-1} in per cell, n coefficients per node.
+using MassLauncher = void (*)(const MeshArgs&, int n, const double* in, double* out, bool inv, hipStream_t);
+MassLauncher find_mass_launcher(int D, int k);
+
 // Specialised kernel for two axes (x, ln p) with a planar x flow and a
 // uniform B; nrot = padded non-zeros per row of B.Omega (1 or 5).
 StageLauncher find_shock_launcher(int k, int lmax, int nrot);

@@ -1,5 +1,20 @@
 // Fused operator / Runge-Kutta stage kernel:  w_out = alpha u + beta L(w_in)
 // with L(w) = M^{-1}(h - D w) of eq. definition-mass-and-dg-matrix.
+//
+// The same template with ADJ = true applies the adjoint operator in the
+// variable mu = M^{-1} lambda:  K mu = -M^{-1} D^T mu, so that the Euclidean
+// transpose of the linear part of L is  L^T = M K M^{-1}.  Writing D^T out per
+// cell (transpose of the volume and face blocks of eq.
+// definition-mass-and-dg-matrix with the upwind flux of eq.
+// definition-upwind-flux):
+//   volume:  K mu = -T((R - div beta)^T mu_q) + sum_a (2/h_a) T(beta^a d_a mu_q)
+//            (beta^a symmetric; d_a mu_q the derivative interpolation)
+//   faces :  with B = n.beta on a face from T1 (below) to T2 (above) and
+//            d = mu(own trace) - mu(other trace):
+//            T1 lifts -(2/h) B_+ d,  T2 lifts +(2/h) B_- d,
+//            zero inflow: other trace 0; "continuous": B mu(own trace).
+// The face part is the forward flux routine fed (F1, F2) = (d, 0) on the hi
+// side and (0, d) on the lo side, or (own, own) at a continuous boundary.
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -23,6 +38,7 @@ struct LaneRows {
   double axv[2], g1v[2];
   int axxc[2];
   double axxv[3], g2v[3];
+  double g1tv[2], g2tv[3];
   int omc[3][2];
   double omv[3][2];
   int ayzc[2][4];
@@ -41,12 +57,14 @@ __device__ __forceinline__ void load_rows(const RowTables& T, int r, LaneRows<LM
     R.axc[s] = T.ax_col[s * N + r];
     R.axv[s] = T.ax_val[s * N + r];
     R.g1v[s] = T.g1_val[s * N + r];
+    R.g1tv[s] = T.g1t_val[s * N + r];
     R.axxc[s] = T.axx_col[s * N + r];
   }
 #pragma unroll
   for (int s = 0; s < 3; ++s) {
     R.axxv[s] = T.axx_val[s * N + r];
     R.g2v[s] = T.g2_val[s * N + r];
+    R.g2tv[s] = T.g2t_val[s * N + r];
   }
 #pragma unroll
   for (int c = 0; c < 3; ++c)
@@ -123,7 +141,7 @@ __device__ __forceinline__ PointScalars point_scalars(const FieldArgs& F, const 
   return s;
 }
 
-template <int D, int K, int LMAX, bool MOM, bool XPROF, int AX>
+template <int D, int K, int LMAX, bool MOM, bool XPROF, int AX, bool ADJ>
 __device__ __forceinline__ void face_axis(const KernelArgs& A, const LaneRows<LMAX>& R,
                                           double* shc, const double* w, double* res,
                                           const int* ic, int cell, int r, bool act, bool in_grp) {
@@ -162,6 +180,15 @@ __device__ __forceinline__ void face_axis(const KernelArgs& A, const LaneRows<LM
     } else {
 #pragma unroll
       for (int fi = 0; fi < NF; ++fi) nbr[fi] = own[fi];
+    }
+    if constexpr (ADJ) {
+      if (inside || bc != 2) {
+#pragma unroll
+        for (int fi = 0; fi < NF; ++fi) {
+          own[fi] -= nbr[fi];
+          nbr[fi] = 0.0;
+        }
+      }
     }
     double F1[NF], F2[NF], J[NF];
     face_interp<D, K>(side ? own : nbr, F1);
@@ -287,7 +314,42 @@ __device__ __forceinline__ void face_axis(const KernelArgs& A, const LaneRows<LM
   }
 }
 
-template <int D, int K, int LMAX, bool MOM, bool XPROF>
+// Adjoint volume flux along axis AX: res += (2/h_AX) T(beta^AX d_AX mu).
+// Writes the derivative values to the cell's LDS rows (all lanes of the block
+// take part in the barriers).
+template <int D, int K, int LMAX, bool MOM, bool XPROF, int AX>
+__device__ __forceinline__ void adj_flux_axis(const KernelArgs& A, const LaneRows<LMAX>& R, double* shc,
+                                              const double* w, double* res, const int* ic, int r,
+                                              bool in_grp) {
+  constexpr int N = (LMAX + 1) * (LMAX + 1);
+  constexpr int NB = IPow<K + 1, D>::v;
+  constexpr bool IS_P = MOM && (AX == D - 1);
+  const FieldArgs& F = A.fld;
+  double dq[NB], tmp[NB];
+  interp_deriv<D, K, AX>(w, dq);
+  __syncthreads();
+  if (in_grp) {
+#pragma unroll
+    for (int q = 0; q < NB; ++q) shc[q * N + r] = dq[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const double* P = shc + q * N;
+    const PointScalars s = point_scalars<D, K, MOM, XPROF>(F, ic, q);
+    if constexpr (IS_P) {
+      const double Axf = R.axv[0] * P[R.axc[0]] + R.axv[1] * P[R.axc[1]];
+      const double A2f = R.axxv[0] * P[R.axxc[0]] + R.axxv[1] * dq[q] + R.axxv[2] * P[R.axxc[1]];
+      tmp[q] = -F.t_mom * (s.a * s.iV * Axf + s.dU * A2f);
+    } else {
+      const double Uc = (AX == 0) ? s.U : F.U[AX];
+      tmp[q] = F.t_adv * (Uc * dq[q] + s.V * dir_apply<LMAX>(R, AX, P));
+    }
+  }
+  contract_add<D, K, -1>(tmp, res, A.mesh.s2h[AX][ic[AX]]);
+}
+
+template <int D, int K, int LMAX, bool MOM, bool XPROF, bool ADJ>
 __global__ __launch_bounds__(kThreads) void stage_kernel(KernelArgs A) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
@@ -354,7 +416,13 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(KernelArgs A) {
         const double Axf = R.axv[0] * fxp + R.axv[1] * fxm;
         const double G1f = R.g1v[0] * fxp + R.g1v[1] * fxm;
         const double G2f = R.g2v[0] * fpp + R.g2v[1] * f + R.g2v[2] * fmm;
-        g += F.t_mom * (s.a * s.iV * G1f + s.dU * G2f - s.a * s.idiv * Axf);
+        if constexpr (ADJ) {
+          const double G1t = R.g1tv[0] * fxp + R.g1tv[1] * fxm;
+          const double G2t = R.g2tv[0] * fpp + R.g2tv[1] * f + R.g2tv[2] * fmm;
+          g += F.t_mom * (s.a * s.iV * G1t + s.dU * G2t - s.a * s.idiv * Axf);
+        } else {
+          g += F.t_mom * (s.a * s.iV * G1f + s.dU * G2f - s.a * s.idiv * Axf);
+        }
       }
       if constexpr (XPROF) g -= F.t_adv * s.dU * f;
       if (F.t_rot != 0.0) {
@@ -367,51 +435,87 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(KernelArgs A) {
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c)
-          if (om[c] != 0.0) g -= s.ig * om[c] * om_apply<LMAX>(R, c, P);
+          if (om[c] != 0.0) g += (ADJ ? 1.0 : -1.0) * s.ig * om[c] * om_apply<LMAX>(R, c, P);
       }
       tmp[q] = g;
     }
     contract_add<D, K, -1>(tmp, res, -1.0);
 
-    // F^a = beta^a f for the spatial axes (axis a is the spatial component a)
+    if constexpr (!ADJ) {
+      // F^a = beta^a f for the spatial axes (axis a is the spatial component a)
 #pragma unroll
-    for (int ax = 0; ax < DS; ++ax) {
+      for (int ax = 0; ax < DS; ++ax) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const double* P = shc + q * N;
-        const PointScalars s = point_scalars<D, K, MOM, XPROF>(F, ic, q);
-        const double Uc = (ax == 0) ? s.U : F.U[ax];
-        tmp[q] = F.t_adv * (Uc * fq[q] + s.V * dir_apply<LMAX>(R, ax, P));
+        for (int q = 0; q < NB; ++q) {
+          const double* P = shc + q * N;
+          const PointScalars s = point_scalars<D, K, MOM, XPROF>(F, ic, q);
+          const double Uc = (ax == 0) ? s.U : F.U[ax];
+          tmp[q] = F.t_adv * (Uc * fq[q] + s.V * dir_apply<LMAX>(R, ax, P));
+        }
+        const double sc = M.s2h[ax][ic[ax]];
+        if (ax == 0) contract_add<D, K, 0>(tmp, res, sc);
+        if constexpr (D > 1)
+          if (ax == 1) contract_add<D, K, (D > 1 ? 1 : 0)>(tmp, res, sc);
+        if constexpr (D > 2)
+          if (ax == 2) contract_add<D, K, (D > 2 ? 2 : 0)>(tmp, res, sc);
       }
-      const double sc = M.s2h[ax][ic[ax]];
-      if (ax == 0) contract_add<D, K, 0>(tmp, res, sc);
-      if constexpr (D > 1)
-        if (ax == 1) contract_add<D, K, (D > 1 ? 1 : 0)>(tmp, res, sc);
-      if constexpr (D > 2)
-        if (ax == 2) contract_add<D, K, (D > 2 ? 2 : 0)>(tmp, res, sc);
-    }
-    // F^{ln p} = beta^{ln p} f
-    if constexpr (MOM) {
+      // F^{ln p} = beta^{ln p} f
+      if constexpr (MOM) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const double* P = shc + q * N;
-        const PointScalars s = point_scalars<D, K, MOM, XPROF>(F, ic, q);
-        const double Axf = R.axv[0] * P[R.axc[0]] + R.axv[1] * P[R.axc[1]];
-        const double A2f = R.axxv[0] * P[R.axxc[0]] + R.axxv[1] * fq[q] + R.axxv[2] * P[R.axxc[1]];
-        tmp[q] = -F.t_mom * (s.a * s.iV * Axf + s.dU * A2f);
+        for (int q = 0; q < NB; ++q) {
+          const double* P = shc + q * N;
+          const PointScalars s = point_scalars<D, K, MOM, XPROF>(F, ic, q);
+          const double Axf = R.axv[0] * P[R.axc[0]] + R.axv[1] * P[R.axc[1]];
+          const double A2f = R.axxv[0] * P[R.axxc[0]] + R.axxv[1] * fq[q] + R.axxv[2] * P[R.axxc[1]];
+          tmp[q] = -F.t_mom * (s.a * s.iV * Axf + s.dU * A2f);
+        }
+        contract_add<D, K, D - 1>(tmp, res, M.s2h[D - 1][ic[D - 1]]);
       }
-      contract_add<D, K, D - 1>(tmp, res, M.s2h[D - 1][ic[D - 1]]);
+    } else {
+      // beta^a (d_a mu) at the Gauss points, tested with phi (all axes)
+      adj_flux_axis<D, K, LMAX, MOM, XPROF, 0>(A, R, shc, w, res, ic, r, in_grp);
+      if constexpr (D > 1) adj_flux_axis<D, K, LMAX, MOM, XPROF, (D > 1 ? 1 : 0)>(A, R, shc, w, res, ic, r, in_grp);
+      if constexpr (D > 2) adj_flux_axis<D, K, LMAX, MOM, XPROF, (D > 2 ? 2 : 0)>(A, R, shc, w, res, ic, r, in_grp);
     }
     __syncthreads();
   }
 
   // ---- faces ------------------------------------------------------------
-  face_axis<D, K, LMAX, MOM, XPROF, 0>(A, R, shc, w, res, ic, cell, r, act, in_grp);
-  if constexpr (D > 1) face_axis<D, K, LMAX, MOM, XPROF, (D > 1 ? 1 : 0)>(A, R, shc, w, res, ic, cell, r, act, in_grp);
-  if constexpr (D > 2) face_axis<D, K, LMAX, MOM, XPROF, (D > 2 ? 2 : 0)>(A, R, shc, w, res, ic, cell, r, act, in_grp);
+  face_axis<D, K, LMAX, MOM, XPROF, 0, ADJ>(A, R, shc, w, res, ic, cell, r, act, in_grp);
+  if constexpr (D > 1) face_axis<D, K, LMAX, MOM, XPROF, (D > 1 ? 1 : 0), ADJ>(A, R, shc, w, res, ic, cell, r, act, in_grp);
+  if constexpr (D > 2) face_axis<D, K, LMAX, MOM, XPROF, (D > 2 ? 2 : 0), ADJ>(A, R, shc, w, res, ic, cell, r, act, in_grp);
 
   // ---- source and output -------------------------------------------------
-  if (A.st.with_source && F.src && r == 0) {
+  if constexpr (ADJ) {
+    if (A.adj.mass_out) {
+      ref_mass<D, K, false>(res);
+      const double jac = cell_jacobian<D>(M, ic);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) res[b] *= jac;
+    }
+    if (A.adj.fwd && A.adj.grad_nu) {
+      // d/dnu_c of <lambda, beta L(fwd)> = -beta t_col sum_lms C (M mu) . fwd
+      double mw[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) mw[b] = w[b];
+      ref_mass<D, K, false>(mw);
+      double part = 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) part = fma(mw[b], act ? A.adj.fwd[cbase + (size_t)b * N] : 0.0, part);
+      part *= R.cv * cell_jacobian<D>(M, ic);
+      if (in_grp) shc[r] = part;
+      __syncthreads();
+      if (act && r == 0) {
+        double sum = 0.0;
+        for (int j = 0; j < N; ++j) sum += shc[j];
+        A.adj.grad_nu[cell] -= A.st.beta * F.t_col * sum;
+      }
+    }
+    if (act && A.adj.t_out) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) A.adj.t_out[cbase + (size_t)b * N] = A.st.beta * res[b];
+    }
+  } else if (A.st.with_source && F.src && r == 0) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) res[b] += F.src[(size_t)cell * NB + b];
   }
@@ -427,42 +531,94 @@ __global__ __launch_bounds__(kThreads) void stage_kernel(KernelArgs A) {
   }
 }
 
-template <int D, int K, int LMAX, bool MOM, bool XPROF>
+template <int D, int K, int LMAX, bool MOM, bool XPROF, bool ADJ>
 void launch_stage_t(const KernelArgs& a, hipStream_t s) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int CPB = Tile<N>::cpb;
   const int blocks = (a.mesh.ncells + CPB - 1) / CPB;
-  hipLaunchKernelGGL((stage_kernel<D, K, LMAX, MOM, XPROF>), dim3(blocks), dim3(kThreads), 0, s, a);
+  hipLaunchKernelGGL((stage_kernel<D, K, LMAX, MOM, XPROF, ADJ>), dim3(blocks), dim3(kThreads), 0, s, a);
 }
 
-template <int D, int K, bool MOM, bool XPROF>
+template <int D, int K, bool MOM, bool XPROF, bool ADJ>
 StageLauncher pick_lmax(int lmax) {
   switch (lmax) {
-    case 1: return &launch_stage_t<D, K, 1, MOM, XPROF>;
-    case 2: return &launch_stage_t<D, K, 2, MOM, XPROF>;
-    case 3: return &launch_stage_t<D, K, 3, MOM, XPROF>;
-    case 4: return &launch_stage_t<D, K, 4, MOM, XPROF>;
-    case 5: return &launch_stage_t<D, K, 5, MOM, XPROF>;
-    case 6: return &launch_stage_t<D, K, 6, MOM, XPROF>;
-    case 7: return &launch_stage_t<D, K, 7, MOM, XPROF>;
+    case 1: return &launch_stage_t<D, K, 1, MOM, XPROF, ADJ>;
+    case 2: return &launch_stage_t<D, K, 2, MOM, XPROF, ADJ>;
+    case 3: return &launch_stage_t<D, K, 3, MOM, XPROF, ADJ>;
+    case 4: return &launch_stage_t<D, K, 4, MOM, XPROF, ADJ>;
+    case 5: return &launch_stage_t<D, K, 5, MOM, XPROF, ADJ>;
+    case 6: return &launch_stage_t<D, K, 6, MOM, XPROF, ADJ>;
+    case 7: return &launch_stage_t<D, K, 7, MOM, XPROF, ADJ>;
     default: return nullptr;
   }
 }
 
-template <int D, bool MOM, bool XPROF>
+template <int D, bool MOM, bool XPROF, bool ADJ>
 StageLauncher pick_k(int k, int lmax) {
-  if (k == 1) return pick_lmax<D, 1, MOM, XPROF>(lmax);
-  if (k == 2) return pick_lmax<D, 2, MOM, XPROF>(lmax);
+  if (k == 1) return pick_lmax<D, 1, MOM, XPROF, ADJ>(lmax);
+  if (k == 2) return pick_lmax<D, 2, MOM, XPROF, ADJ>(lmax);
   return nullptr;
+}
+
+template <bool ADJ>
+StageLauncher pick_family(int D, int k, int lmax, bool mom, bool xprof) {
+  if (D == 1 && !mom) return xprof ? pick_k<1, false, true, ADJ>(k, lmax) : pick_k<1, false, false, ADJ>(k, lmax);
+  if (D == 2 && !mom && !xprof) return pick_k<2, false, false, ADJ>(k, lmax);
+  if (D == 2 && mom && xprof) return pick_k<2, true, true, ADJ>(k, lmax);
+  if (D == 3 && !mom && !xprof) return pick_k<3, false, false, ADJ>(k, lmax);
+  return nullptr;
+}
+
+// Cell mass matrix (or its inverse) applied per (cell, lms) lane.
+template <int D, int K, bool INV>
+__global__ __launch_bounds__(kThreads) void mass_kernel(MeshArgs M, int n, const double* in, double* out) {
+  constexpr int NB = IPow<K + 1, D>::v;
+  const size_t t = (size_t)blockIdx.x * kThreads + threadIdx.x;
+  if (t >= (size_t)M.ncells * n) return;
+  const int cell = (int)(t / n);
+  const int r = (int)(t - (size_t)cell * n);
+  int ic[3];
+  {
+    int c = cell;
+    ic[0] = c % M.n[0];
+    c /= M.n[0];
+    ic[1] = c % M.n[1];
+    ic[2] = c / M.n[1];
+  }
+  const size_t base = (size_t)cell * NB * n + r;
+  double v[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) v[b] = in[base + (size_t)b * n];
+  ref_mass<D, K, INV>(v);
+  const double jac = cell_jacobian<D>(M, ic);
+  const double sc = INV ? 1.0 / jac : jac;
+#pragma unroll
+  for (int b = 0; b < NB; ++b) out[base + (size_t)b * n] = sc * v[b];
+}
+
+template <int D, int K>
+void launch_mass_t(const MeshArgs& m, int n, const double* in, double* out, bool inv, hipStream_t s) {
+  const size_t lanes = (size_t)m.ncells * n;
+  const int blocks = (int)((lanes + kThreads - 1) / kThreads);
+  if (inv)
+    hipLaunchKernelGGL((mass_kernel<D, K, true>), dim3(blocks), dim3(kThreads), 0, s, m, n, in, out);
+  else
+    hipLaunchKernelGGL((mass_kernel<D, K, false>), dim3(blocks), dim3(kThreads), 0, s, m, n, in, out);
 }
 
 }  // namespace
 
 StageLauncher find_stage_launcher(int D, int k, int lmax, bool mom, bool xprof) {
-  if (D == 1 && !mom) return xprof ? pick_k<1, false, true>(k, lmax) : pick_k<1, false, false>(k, lmax);
-  if (D == 2 && !mom && !xprof) return pick_k<2, false, false>(k, lmax);
-  if (D == 2 && mom && xprof) return pick_k<2, true, true>(k, lmax);
-  if (D == 3 && !mom && !xprof) return pick_k<3, false, false>(k, lmax);
+  return pick_family<false>(D, k, lmax, mom, xprof);
+}
+
+StageLauncher find_adjoint_launcher(int D, int k, int lmax, bool mom, bool xprof) {
+  return pick_family<true>(D, k, lmax, mom, xprof);
+}
+
+MassLauncher find_mass_launcher(int D, int k) {
+  if (k == 1) return D == 1 ? &launch_mass_t<1, 1> : D == 2 ? &launch_mass_t<2, 1> : &launch_mass_t<3, 1>;
+  if (k == 2) return D == 1 ? &launch_mass_t<1, 2> : D == 2 ? &launch_mass_t<2, 2> : &launch_mass_t<3, 2>;
   return nullptr;
 }
 

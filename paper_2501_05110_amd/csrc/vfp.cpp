@@ -142,6 +142,13 @@ Basis1D make_basis(int k) {
     B.lift[0][i] = Mi[i][0];
     B.lift[1][i] = Mi[i][k];
   }
+  for (int q = 0; q < K1; ++q)
+    for (int j = 0; j < K1; ++j) B.dphi[q][j] = dlag(j, g[q]);
+  for (int i = 0; i < K1; ++i)
+    for (int j = 0; j < K1; ++j) {
+      B.mass[i][j] = M1[i][j];
+      B.imass[i][j] = Mi[i][j];
+    }
   return B;
 }
 
@@ -189,6 +196,9 @@ struct vfp_ctx {
   FieldArgs fld{};
   MeshArgs meshargs{};
   StageLauncher launcher = nullptr;
+  StageLauncher adj_launcher = nullptr;
+  MassLauncher mass_launcher = nullptr;
+  DevBuf d_scratch;         // ndofs doubles, used by vfp_apply_adjoint
   double beta_pmax = 0.0;   // spectral-radius bound of beta^{ln p} over p faces
   double vmax = 0.0;
   double lam_max = 0.0;     // largest eigenvalue of A^x
@@ -221,6 +231,7 @@ int build_row_tables(vfp_ctx* c) {
   auto dalloc = [&](size_t cnt) { size_t o = dv.size(); dv.resize(o + cnt, 0.0); return o; };
   size_t o_axc = ialloc(2 * n), o_axv = dalloc(2 * n), o_g1v = dalloc(2 * n);
   size_t o_axxc = ialloc(2 * n), o_axxv = dalloc(3 * n), o_g2v = dalloc(3 * n);
+  size_t o_g1t = dalloc(2 * n), o_g2t = dalloc(3 * n);
   size_t o_omc = ialloc(6 * n), o_omv = dalloc(6 * n);
   size_t o_ayzc = ialloc(8 * n), o_ayzv = dalloc(8 * n);
   size_t o_cv = dalloc(n);
@@ -260,6 +271,12 @@ int build_row_tables(vfp_ctx* c) {
     dv[o_g2v + r] = (cpp != r) ? S.G2(r, cpp) : 0.0;
     dv[o_g2v + n + r] = S.G2(r, r);
     dv[o_g2v + 2 * n + r] = (cmm != r) ? S.G2(r, cmm) : 0.0;
+    // transposed values on the same patterns (both are symmetric in l <-> l')
+    dv[o_g1t + r] = (cp != r) ? S.G1(cp, r) : 0.0;
+    dv[o_g1t + n + r] = (cm != r) ? S.G1(cm, r) : 0.0;
+    dv[o_g2t + r] = (cpp != r) ? S.G2(cpp, r) : 0.0;
+    dv[o_g2t + n + r] = S.G2(r, r);
+    dv[o_g2t + 2 * n + r] = (cmm != r) ? S.G2(cmm, r) : 0.0;
     if (int e = check_covered(S.AXX, r, {cpp, r, cmm}, "(AxAx)_t")) return e;
     if (int e = check_covered(S.G2, r, {cpp, r, cmm}, "G2")) return e;
     for (int cc = 0; cc < 3; ++cc) {
@@ -394,6 +411,8 @@ int build_row_tables(vfp_ctx* c) {
   T.axx_col = ib + o_axxc;
   T.axx_val = db + o_axxv;
   T.g2_val = db + o_g2v;
+  T.g1t_val = db + o_g1t;
+  T.g2t_val = db + o_g2t;
   T.om_col = ib + o_omc;
   T.om_val = db + o_omv;
   T.ayz_col = ib + o_ayzc;
@@ -650,6 +669,8 @@ int refresh(vfp_ctx* c) {
   if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general)
     c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot);
   if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
+  c->adj_launcher = find_adjoint_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
+  c->mass_launcher = find_mass_launcher(c->naxes, c->k);
   return VFP_OK;
 }
 
@@ -888,12 +909,26 @@ int vfp_set_scattering(vfp_ctx* c, double nu, const double* nu_cell) {
   if (!c) return fail(VFP_EINVAL, "null context");
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
   if (nu_cell) {
-    if (int e = upload(c->d_nu, nu_cell, (size_t)c->ncells * sizeof(double))) return e;
+    for (int i = 0; i < c->ncells; ++i)
+      if (!std::isfinite(nu_cell[i])) return fail(VFP_EINVAL, "nu_cell[%d] not finite", i);
+    if (c->have_nu_cell && c->d_nu.bytes == (size_t)c->ncells * sizeof(double)) {
+      // same size: overwrite in place (ordered after work already queued on
+      // the null stream; callers on other streams synchronise first)
+      HIP_TRY(hipMemcpy(c->d_nu.p, nu_cell, c->d_nu.bytes, hipMemcpyHostToDevice));
+    } else if (int e = upload(c->d_nu, nu_cell, (size_t)c->ncells * sizeof(double))) {
+      return e;
+    }
     c->have_nu_cell = true;
   } else {
     if (!std::isfinite(nu)) return fail(VFP_EINVAL, "nu not finite");
     c->nu0 = nu;
     c->have_nu_cell = false;
+  }
+  if (c->launcher) {
+    // only the scattering fields change: no table rebuild
+    c->fld.nu0 = c->nu0;
+    c->fld.nu_cell = c->have_nu_cell ? c->d_nu.as<double>() : nullptr;
+    return VFP_OK;
   }
   return refresh(c);
 }
@@ -964,7 +999,7 @@ int vfp_cfl_dt(const vfp_ctx* c, double courant, double* dt) {
 
 static int launch(vfp_ctx* c, const double* w_in, const double* u, double* w_out, double alpha, double beta,
                   int with_source, void* stream) {
-  KernelArgs a;
+  KernelArgs a{};
   a.mesh = c->meshargs;
   a.fld = c->fld;
   a.tab = c->tab;
@@ -1011,6 +1046,175 @@ int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, 
     if (int e = launch(c, wa, u, u, 1.0, dt, 1, stream)) return e;
   }
   return VFP_OK;
+}
+
+static bool overlaps(const double* a, int64_t na, const double* b, int64_t nb) {
+  if (!a || !b) return false;
+  return a < b + nb && b < a + na;
+}
+
+static int launch_adj(vfp_ctx* c, const double* mu_in, const double* acc_in, double* acc_out, double alpha,
+                      double beta, double* t_out, const double* fwd, double* grad_nu, int mass_out,
+                      void* stream) {
+  if (!c->adj_launcher) return fail(VFP_EUNSUPPORTED, "no adjoint kernel for this configuration");
+  KernelArgs a{};
+  a.mesh = c->meshargs;
+  a.fld = c->fld;
+  a.tab = c->tab;
+  a.st.w_in = mu_in;
+  a.st.u = acc_in;
+  a.st.w_out = acc_out;
+  a.st.alpha = alpha;
+  a.st.beta = beta;
+  a.st.with_source = 0;
+  a.adj.t_out = t_out;
+  a.adj.fwd = fwd;
+  a.adj.grad_nu = grad_nu;
+  a.adj.mass_out = mass_out;
+  c->adj_launcher(a, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return VFP_OK;
+}
+
+static int launch_mass(vfp_ctx* c, const double* in, double* out, bool inv, void* stream) {
+  if (!c->mass_launcher) return fail(VFP_EUNSUPPORTED, "no mass kernel for this configuration");
+  c->mass_launcher(c->meshargs, c->n, in, out, inv, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return VFP_OK;
+}
+
+int vfp_mass(vfp_ctx* c, const double* in, double* out, int inverse, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!in || !out) return fail(VFP_EINVAL, "null state pointer");
+  return launch_mass(c, in, out, inverse != 0, stream);
+}
+
+int vfp_apply_adjoint(vfp_ctx* c, const double* in, double* out, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!in || !out) return fail(VFP_EINVAL, "null state pointer");
+  if (in == out) return fail(VFP_EINVAL, "in and out must not alias");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  if (c->d_scratch.bytes < (size_t)N * sizeof(double)) {
+    c->d_scratch.release();
+    if (std::getenv("VFP_FAIL_ALLOC")) return fail(VFP_ENOMEM, "allocation refused (VFP_FAIL_ALLOC)");
+    hipError_t e = hipMalloc(&c->d_scratch.p, (size_t)N * sizeof(double));
+    if (e != hipSuccess) {
+      c->d_scratch.p = nullptr;
+      return fail(VFP_ENOMEM, "hipMalloc(%lld doubles): %s", (long long)N, hipGetErrorString(e));
+    }
+    c->d_scratch.bytes = (size_t)N * sizeof(double);
+  }
+  double* mu = c->d_scratch.as<double>();
+  if (int e = launch_mass(c, in, mu, true, stream)) return e;
+  return launch_adj(c, mu, nullptr, out, 0.0, 1.0, nullptr, nullptr, nullptr, 1, stream);
+}
+
+int vfp_adjoint_stage(vfp_ctx* c, const double* mu_in, const double* acc_in, const double* fwd, double cdt,
+                      double* t_out, double* acc_out, double* grad_nu, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!mu_in || !acc_in || !acc_out) return fail(VFP_EINVAL, "null state pointer");
+  if (!std::isfinite(cdt)) return fail(VFP_EINVAL, "cdt not finite");
+  if (grad_nu && !fwd) return fail(VFP_EINVAL, "grad_nu needs the forward stage input fwd");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  if (overlaps(acc_out, N, mu_in, N) || overlaps(t_out, N, mu_in, N) || overlaps(t_out, N, acc_in, N) ||
+      overlaps(t_out, N, acc_out, N))
+    return fail(VFP_EINVAL, "t_out / acc_out alias an input that other cells read");
+  if (overlaps(acc_out, N, acc_in, N) && acc_out != acc_in)
+    return fail(VFP_EINVAL, "acc_out partially overlaps acc_in");
+  if (grad_nu && (overlaps(grad_nu, c->ncells, acc_out, N) || overlaps(grad_nu, c->ncells, t_out, N)))
+    return fail(VFP_EINVAL, "grad_nu overlaps an output");
+  return launch_adj(c, mu_in, acc_in, acc_out, 1.0, cdt, t_out, grad_nu ? fwd : nullptr, grad_nu, 0, stream);
+}
+
+int vfp_advance_tape(vfp_ctx* c, const double* u0, double dt, int64_t nsteps, double* tape, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!u0 || !tape) return fail(VFP_EINVAL, "null state pointer");
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  if (overlaps(u0, N, tape, 4 * nsteps * N)) return fail(VFP_EINVAL, "tape overlaps u0");
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const double* un = s == 0 ? u0 : tape + (4 * s - 1) * N;
+    double* w = tape + 4 * s * N;
+    if (int e = launch(c, un, un, w, 1.0, 0.25 * dt, 1, stream)) return e;
+    if (int e = launch(c, w, un, w + N, 1.0, dt / 3.0, 1, stream)) return e;
+    if (int e = launch(c, w + N, un, w + 2 * N, 1.0, 0.5 * dt, 1, stream)) return e;
+    if (int e = launch(c, w + 2 * N, un, w + 3 * N, 1.0, dt, 1, stream)) return e;
+  }
+  return VFP_OK;
+}
+
+int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double dt, int64_t nsteps, double* mu,
+                      double* grad_nu, double* work, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!u0 || !tape || !mu || !work) return fail(VFP_EINVAL, "null state pointer");
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  if (overlaps(work, 3 * N, mu, N) || overlaps(work, 3 * N, tape, 4 * nsteps * N) || overlaps(work, 3 * N, u0, N) ||
+      overlaps(mu, N, tape, 4 * nsteps * N) || overlaps(mu, N, u0, N))
+    return fail(VFP_EINVAL, "work / mu overlap the tape or each other");
+  if (grad_nu && (overlaps(grad_nu, c->ncells, work, 3 * N) || overlaps(grad_nu, c->ncells, mu, N)))
+    return fail(VFP_EINVAL, "grad_nu overlaps a state buffer");
+  double* acc = work;
+  double* b1 = work + N;
+  double* b2 = work + 2 * N;
+  for (int64_t s = nsteps - 1; s >= 0; --s) {
+    const double* un = s == 0 ? u0 : tape + (4 * s - 1) * N;
+    const double* w = tape + 4 * s * N;
+    const double* f3 = grad_nu ? w + 2 * N : nullptr;
+    const double* f2 = grad_nu ? w + N : nullptr;
+    const double* f1 = grad_nu ? w : nullptr;
+    const double* f0 = grad_nu ? un : nullptr;
+    if (int e = launch_adj(c, mu, mu, acc, 1.0, dt, b1, f3, grad_nu, 0, stream)) return e;
+    if (int e = launch_adj(c, b1, acc, acc, 1.0, 0.5 * dt, b2, f2, grad_nu, 0, stream)) return e;
+    if (int e = launch_adj(c, b2, acc, acc, 1.0, dt / 3.0, b1, f1, grad_nu, 0, stream)) return e;
+    if (int e = launch_adj(c, b1, acc, mu, 1.0, 0.25 * dt, nullptr, f0, grad_nu, 0, stream)) return e;
+  }
+  return VFP_OK;
+}
+
+int vfp_forward_checkpoints(vfp_ctx* c, double* u, double dt, int64_t nsteps, int64_t seg, double* ckpt,
+                            double* work, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!u || !ckpt || !work) return fail(VFP_EINVAL, "null state pointer");
+  if (nsteps < 0 || seg < 1 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps / seg");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  const int64_t nseg = (nsteps + seg - 1) / seg;
+  if (overlaps(ckpt, nseg * N, u, N) || overlaps(ckpt, nseg * N, work, 2 * N))
+    return fail(VFP_EINVAL, "checkpoints overlap u or work");
+  for (int64_t j = 0; j < nseg; ++j) {
+    HIP_TRY(hipMemcpyAsync(ckpt + j * N, u, (size_t)N * sizeof(double), hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    const int64_t cnt = std::min(seg, nsteps - j * seg);
+    if (int e = vfp_advance(c, u, dt, cnt, work, stream)) return e;
+  }
+  return VFP_OK;
+}
+
+int vfp_adjoint_checkpointed(vfp_ctx* c, const double* ckpt, double dt, int64_t nsteps, int64_t seg,
+                             double* tape, double* lam, double* grad_nu, double* work, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!ckpt || !tape || !lam || !work) return fail(VFP_EINVAL, "null state pointer");
+  if (nsteps < 0 || seg < 1 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps / seg");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  const int64_t nseg = (nsteps + seg - 1) / seg;
+  const int64_t ntape = 4 * std::min(seg, nsteps) * N;
+  if (overlaps(tape, ntape, ckpt, nseg * N) || overlaps(lam, N, ckpt, nseg * N) || overlaps(lam, N, tape, ntape) ||
+      overlaps(work, 3 * N, tape, ntape) || overlaps(work, 3 * N, lam, N) || overlaps(work, 3 * N, ckpt, nseg * N))
+    return fail(VFP_EINVAL, "checkpoint, tape, lam and work buffers must be disjoint");
+  if (int e = launch_mass(c, lam, lam, true, stream)) return e;
+  for (int64_t j = nseg - 1; j >= 0; --j) {
+    const int64_t cnt = std::min(seg, nsteps - j * seg);
+    const double* u0 = ckpt + j * N;
+    if (int e = vfp_advance_tape(c, u0, dt, cnt, tape, stream)) return e;
+    if (int e = vfp_adjoint_steps(c, u0, tape, dt, cnt, lam, grad_nu, work, stream)) return e;
+  }
+  return launch_mass(c, lam, lam, false, stream);
 }
 
 }  // extern "C"

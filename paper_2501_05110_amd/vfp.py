@@ -60,6 +60,13 @@ def load(path: str = None):
         "vfp_apply": (I, [P, P, P, I, P]),
         "vfp_stage": (I, [P, P, P, P, D, P]),
         "vfp_advance": (I, [P, P, D, L, P, P]),
+        "vfp_mass": (I, [P, P, P, I, P]),
+        "vfp_apply_adjoint": (I, [P, P, P, P]),
+        "vfp_adjoint_stage": (I, [P, P, P, P, D, P, P, P, P]),
+        "vfp_advance_tape": (I, [P, P, D, L, P, P]),
+        "vfp_adjoint_steps": (I, [P, P, P, D, L, P, P, P, P]),
+        "vfp_forward_checkpoints": (I, [P, P, D, L, L, P, P, P]),
+        "vfp_adjoint_checkpointed": (I, [P, P, D, L, L, P, P, P, P, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -74,7 +81,8 @@ def exported_symbols():
             "vfp_query_points", "vfp_set_flow_uniform", "vfp_set_flow_planar",
             "vfp_set_magnetic_uniform", "vfp_set_magnetic_points", "vfp_set_scattering",
             "vfp_set_source_points", "vfp_ndofs", "vfp_cfl_dt", "vfp_apply", "vfp_stage",
-            "vfp_advance"]
+            "vfp_advance", "vfp_mass", "vfp_apply_adjoint", "vfp_adjoint_stage", "vfp_advance_tape",
+            "vfp_adjoint_steps", "vfp_forward_checkpoints", "vfp_adjoint_checkpointed"]
 
 
 def _check(rc):
@@ -202,11 +210,14 @@ class Operator:
             _check(_lib.vfp_set_scattering(self._ctx, 0.0, _dptr(_f64(nu))))
 
     # -- compute ------------------------------------------------------------
-    def _t(self, x, name):
+    def _t(self, x, name, size=None, optional=False):
         import torch
+        if x is None and optional:
+            return None
+        size = self.ndofs if size is None else size
         if not isinstance(x, torch.Tensor) or not x.is_cuda or x.dtype != torch.float64 \
-                or not x.is_contiguous() or x.numel() < self.ndofs:
-            raise VFPError(f"{name} must be a contiguous float64 CUDA tensor of >= {self.ndofs} elements")
+                or not x.is_contiguous() or x.numel() < size:
+            raise VFPError(f"{name} must be a contiguous float64 CUDA tensor of >= {size} elements")
         return C.c_void_p(x.data_ptr())
 
     def apply(self, zin, zout, with_source=True, stream=None):
@@ -224,6 +235,52 @@ class Operator:
         _check(_lib.vfp_advance(self._ctx, self._t(u, "u"), float(dt), int(nsteps),
                                 self._t(work, "work"), _stream_handle(stream)))
 
+    # -- adjoint ------------------------------------------------------------
+    def mass(self, zin, zout, inverse=False, stream=None):
+        _check(_lib.vfp_mass(self._ctx, self._t(zin, "in"), self._t(zout, "out"), int(bool(inverse)),
+                             _stream_handle(stream)))
+
+    def apply_adjoint(self, zin, zout, stream=None):
+        _check(_lib.vfp_apply_adjoint(self._ctx, self._t(zin, "in"), self._t(zout, "out"),
+                                      _stream_handle(stream)))
+
+    def adjoint_stage(self, mu_in, acc_in, fwd, cdt, t_out, acc_out, grad_nu=None, stream=None):
+        _check(_lib.vfp_adjoint_stage(
+            self._ctx, self._t(mu_in, "mu_in"), self._t(acc_in, "acc_in"),
+            self._t(fwd, "fwd", optional=True), float(cdt), self._t(t_out, "t_out", optional=True),
+            self._t(acc_out, "acc_out"), self._t(grad_nu, "grad_nu", self.ncells, optional=True),
+            _stream_handle(stream)))
+
+    def advance_tape(self, u0, dt, nsteps, tape, stream=None):
+        _check(_lib.vfp_advance_tape(self._ctx, self._t(u0, "u0"), float(dt), int(nsteps),
+                                     self._t(tape, "tape", 4 * nsteps * self.ndofs),
+                                     _stream_handle(stream)))
+
+    def adjoint_steps(self, u0, tape, dt, nsteps, mu, grad_nu, work, stream=None):
+        _check(_lib.vfp_adjoint_steps(
+            self._ctx, self._t(u0, "u0"), self._t(tape, "tape", 4 * nsteps * self.ndofs), float(dt),
+            int(nsteps), self._t(mu, "mu"), self._t(grad_nu, "grad_nu", self.ncells, optional=True),
+            self._t(work, "work", 3 * self.ndofs), _stream_handle(stream)))
+
+    def forward_checkpoints(self, u, dt, nsteps, seg, ckpt, work, stream=None):
+        nseg = -(-nsteps // seg)
+        _check(_lib.vfp_forward_checkpoints(
+            self._ctx, self._t(u, "u"), float(dt), int(nsteps), int(seg),
+            self._t(ckpt, "ckpt", nseg * self.ndofs), self._t(work, "work", 2 * self.ndofs),
+            _stream_handle(stream)))
+
+    def adjoint_checkpointed(self, ckpt, dt, nsteps, seg, tape, lam, grad_nu, work, stream=None):
+        nseg = -(-nsteps // seg)
+        _check(_lib.vfp_adjoint_checkpointed(
+            self._ctx, self._t(ckpt, "ckpt", nseg * self.ndofs), float(dt), int(nsteps), int(seg),
+            self._t(tape, "tape", 4 * min(seg, nsteps) * self.ndofs), self._t(lam, "lam"),
+            self._t(grad_nu, "grad_nu", self.ncells, optional=True),
+            self._t(work, "work", 3 * self.ndofs), _stream_handle(stream)))
+
+    @property
+    def ncells(self):
+        return self.wl.ncells
+
     def cfl_dt(self, courant=None):
         c = self.wl.courant if courant is None else courant
         dt = C.c_double()
@@ -240,3 +297,53 @@ class Operator:
             self.close()
         except Exception:
             pass
+
+
+def checkpoint_segment(nsteps: int) -> int:
+    """Segment length for sqrt(N) checkpointing."""
+    return max(1, int(math.ceil(math.sqrt(max(nsteps, 1)))))
+
+
+class _AdvanceFn:
+    """Namespace for the autograd function (built lazily so that importing
+    this module does not need torch)."""
+    fn = None
+
+
+def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: int = None):
+    """u_N = RK4^N(u0) with the scattering frequency nu_cell (one value per
+    cell) as a differentiable input: backward returns dJ/du0 and dJ/dnu_cell
+    from the checkpointed discrete adjoint of the library."""
+    import torch
+    if _AdvanceFn.fn is None:
+        class AdvanceFn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, u0, nu, op, dt, nsteps, seg):
+                op.set_scattering(nu.detach().cpu().numpy())
+                N = op.ndofs
+                nseg = -(-nsteps // seg)
+                u = u0.detach().clone().contiguous()
+                ckpt = torch.empty(max(nseg, 1) * N, dtype=torch.float64, device=u.device)
+                work = torch.empty(2 * N, dtype=torch.float64, device=u.device)
+                op.forward_checkpoints(u, dt, nsteps, seg, ckpt, work)
+                ctx.op, ctx.dt, ctx.nsteps, ctx.seg = op, dt, nsteps, seg
+                ctx.nu = nu.detach().cpu().numpy().copy()
+                ctx.save_for_backward(ckpt)
+                return u
+
+            @staticmethod
+            def backward(ctx, g):
+                (ckpt,) = ctx.saved_tensors
+                op, N = ctx.op, ctx.op.ndofs
+                op.set_scattering(ctx.nu)
+                lam = g.detach().to(torch.float64).contiguous().clone()
+                grad_nu = torch.zeros(op.ncells, dtype=torch.float64, device=lam.device)
+                if ctx.nsteps > 0:
+                    tape = torch.empty(4 * min(ctx.seg, ctx.nsteps) * N, dtype=torch.float64,
+                                       device=lam.device)
+                    work = torch.empty(3 * N, dtype=torch.float64, device=lam.device)
+                    op.adjoint_checkpointed(ckpt, ctx.dt, ctx.nsteps, ctx.seg, tape, lam, grad_nu, work)
+                return lam, grad_nu, None, None, None, None
+        _AdvanceFn.fn = AdvanceFn
+    seg = checkpoint_segment(nsteps) if seg is None else int(seg)
+    return _AdvanceFn.fn.apply(u0, nu_cell, op, float(dt), int(nsteps), seg)

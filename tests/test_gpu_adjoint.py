@@ -1,0 +1,217 @@
+"""Parity of the library's adjoint path with the oracle.
+
+* vfp_mass and vfp_apply_adjoint element by element against the oracle's
+  assembled M, M^{-1} and -D^T M^{-1} (1e-12 relative, max norm);
+* one adjoint stage (t, acc, d/dnu) against the oracle's matrices;
+* the reverse sweep over a taped run and the checkpointed driver against the
+  oracle's reverse-mode classical RK4 (1e-10);
+* at full size, where the oracle cannot assemble columns, the transpose
+  identity <y, L_lin x> = <L_lin^T y, x> on seeded vectors (1e-12 relative to
+  sum |y_i (L_lin x)_i|).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import dg
+from paper_2501_05110_amd import workloads as W
+
+from gpu_cases import APPLY_TOL, CASES, _say, rel_inf, shock
+
+pytestmark = pytest.mark.gpu
+GRAD_TOL = 1e-10
+
+
+def _dev(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64).ravel()).cuda()
+
+
+def _host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("name", ["c1", "shock_k2_l3", "shock_k1_l5", "uniform2d", "cube_k1_l3"])
+def test_mass_parity(lib, cuda, name):
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = CASES[name]()
+    _say(f"[mass] {name}: ndofs={wl.ndofs}")
+    op = Operator(wl)
+    S = dg.assemble(wl)
+    z = W.random_state(wl, 41).ravel()
+    tz = _dev(z)
+    out = torch.empty_like(tz)
+    op.mass(tz, out, inverse=False)
+    assert rel_inf(_host(out), S.M @ z) <= APPLY_TOL
+    op.mass(tz, out, inverse=True)
+    assert rel_inf(_host(out), S.Minv @ z) <= APPLY_TOL
+    op.mass(tz, tz, inverse=True)           # in place
+    assert rel_inf(_host(tz), S.Minv @ z) <= APPLY_TOL
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_apply_adjoint_parity(lib, cuda, name):
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = CASES[name]()
+    _say(f"[adjoint] {name}: cells={wl.ncells_axis} ndofs={wl.ndofs}")
+    op = Operator(wl)
+    S = dg.assemble(wl)
+    lam = W.random_state(wl, 313).ravel()
+    tl = _dev(lam)
+    out = torch.empty_like(tl)
+    op.apply_adjoint(tl, out)
+    err = rel_inf(_host(out), dg.apply_adjoint(S, lam))
+    _say(f"   rel_inf={err:.3e}")
+    assert err <= APPLY_TOL, (name, err)
+
+
+def test_adjoint_stage_parity(lib, cuda):
+    """t = c K mu, acc_out = acc_in + t and grad_nu against
+    K = M^{-1} (-D^T M^{-1}) M and d apply / d nu_c = -M^{-1} dD/dnu_c."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = shock(17, 7, 2, 3)
+    op = Operator(wl)
+    S = dg.assemble(wl)
+    Sc = dg.collision_system(wl)
+    g = np.random.default_rng(19)
+    mu, acc, fwd = (g.standard_normal(wl.ndofs) for _ in range(3))
+    c = 0.0123
+    t_want = c * (S.Minv @ dg.apply_adjoint(S, S.M @ mu))
+    dapp = -(S.Minv @ (Sc.D @ fwd))
+    gnu_want = c * ((S.M @ mu) * dapp).reshape(wl.ncells, -1).sum(axis=1)
+    tm, ta, tf = _dev(mu), _dev(acc), _dev(fwd)
+    t_out = torch.empty_like(tm)
+    acc_out = torch.empty_like(tm)
+    gnu = torch.zeros(wl.ncells, dtype=torch.float64, device="cuda")
+    op.adjoint_stage(tm, ta, tf, c, t_out, acc_out, gnu)
+    assert rel_inf(_host(t_out), t_want) <= APPLY_TOL
+    assert rel_inf(_host(acc_out), acc + t_want) <= APPLY_TOL
+    assert rel_inf(_host(gnu), gnu_want) <= APPLY_TOL
+    # in place accumulation, acc_in == mu_in, no t_out
+    ta2 = tm.clone()
+    op.adjoint_stage(tm, tm, None, c, None, ta2)
+    assert rel_inf(_host(ta2), mu + t_want) <= APPLY_TOL
+
+
+def _oracle_grad(wl, z0, dt, n, gN):
+    S = dg.assemble(wl)
+    return dg.rk4_gradient(S, z0, dt, n, gN, dsys=dg.collision_system(wl))
+
+
+@pytest.mark.parametrize("case", ["shock_k2_l3", "shock_k1_l1", "uniform2d"])
+def test_reverse_sweep_parity(lib, cuda, case):
+    """Taped forward + vfp_adjoint_steps, and the checkpointed driver, against
+    the oracle's reverse mode of classical RK4 (same step map, G8)."""
+    import torch
+    from gpu_cases import uniform2d
+    from paper_2501_05110_amd.vfp import Operator
+    wl = {"shock_k2_l3": lambda: shock(16, 8, 2, 3),
+          "shock_k1_l1": lambda: shock(20, 6, 1, 1),
+          "uniform2d": lambda: uniform2d()}[case]()
+    if np.isscalar(wl.nu):
+        wl.nu = np.full(wl.ncells, float(wl.nu))
+    op = Operator(wl)
+    dt = op.cfl_dt(0.2)
+    n = 30
+    g = np.random.default_rng(23)
+    z0 = g.standard_normal(wl.ndofs)
+    gN = g.standard_normal(wl.ndofs)
+    _say(f"[reverse] {case}: ndofs={wl.ndofs} steps={n} dt={dt:.3e}")
+    want_z, want_nu = _oracle_grad(wl, z0, dt, n, gN)
+    N = op.ndofs
+    # taped forward + one reverse sweep
+    tz0 = _dev(z0)
+    tape = torch.empty(4 * n * N, dtype=torch.float64, device="cuda")
+    op.advance_tape(tz0, dt, n, tape)
+    mu = _dev(gN)
+    op.mass(mu, mu, inverse=True)
+    gnu = torch.zeros(wl.ncells, dtype=torch.float64, device="cuda")
+    work = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+    op.adjoint_steps(tz0, tape, dt, n, mu, gnu, work)
+    op.mass(mu, mu, inverse=False)
+    ez, en = rel_inf(_host(mu), want_z), rel_inf(_host(gnu), want_nu)
+    _say(f"   taped: dJ/dz0 {ez:.3e}  dJ/dnu {en:.3e}")
+    assert ez <= GRAD_TOL and en <= GRAD_TOL
+    # the forward tape's last slot is u_n: matches the oracle's forward
+    zN = dg.rk4(dg.assemble(wl), z0, dt, n)
+    assert rel_inf(_host(tape[(4 * n - 1) * N: 4 * n * N]), zN) <= GRAD_TOL
+    # checkpointed driver, segments of 7 steps (ragged last segment)
+    seg = 7
+    u = _dev(z0)
+    ckpt = torch.empty(-(-n // seg) * N, dtype=torch.float64, device="cuda")
+    w2 = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+    op.forward_checkpoints(u, dt, n, seg, ckpt, w2)
+    lam = _dev(gN)
+    gnu2 = torch.zeros(wl.ncells, dtype=torch.float64, device="cuda")
+    tape2 = torch.empty(4 * seg * N, dtype=torch.float64, device="cuda")
+    op.adjoint_checkpointed(ckpt, dt, n, seg, tape2, lam, gnu2, work)
+    assert rel_inf(_host(u), zN) <= GRAD_TOL
+    ez2, en2 = rel_inf(_host(lam), want_z), rel_inf(_host(gnu2), want_nu)
+    _say(f"   checkpointed: dJ/dz0 {ez2:.3e}  dJ/dnu {en2:.3e}")
+    assert ez2 <= GRAD_TOL and en2 <= GRAD_TOL
+
+
+def test_autograd_function(lib, cuda):
+    """advance_with_grad: the loss of the adjoint case (squared misfit of
+    f_000 on the trace of the cells just downstream of x = L/2) -- gradients
+    w.r.t. the initial state and nu per cell against the oracle."""
+    import torch
+    from paper_2501_05110_amd import vfp
+    wl = shock(16, 6, 2, 3)
+    op = vfp.Operator(wl)
+    dt = op.cfl_dt(0.2)
+    n = 24
+    z0 = W.random_state(wl, 3, 1e-3).ravel()
+    nu = np.asarray(wl.nu, float)
+    # trace nodes i0 = 0 of the x-cells starting at x = +L/2, all p cells
+    nx, npc = wl.ncells_axis
+    ix = nx * 3 // 4
+    K1 = wl.k + 1
+    sel = np.zeros(wl.shape, bool)
+    for jp in range(npc):
+        for bq in range(K1):
+            sel[jp * nx + ix, bq * K1 + 0, 0] = True
+    target = np.random.default_rng(9).standard_normal(int(sel.sum())) * 1e-3
+    tsel = torch.from_numpy(sel.ravel()).cuda()
+    u0 = torch.from_numpy(z0).cuda().requires_grad_(True)
+    tnu = torch.from_numpy(nu.copy()).cuda().requires_grad_(True)
+    uN = vfp.advance_with_grad(op, u0, tnu, dt, n, seg=5)
+    loss = 0.5 * ((uN[tsel] - torch.from_numpy(target).cuda()) ** 2).sum()
+    loss.backward()
+    S = dg.assemble(wl)
+    zN = dg.rk4(S, z0, dt, n)
+    gN = np.zeros(wl.ndofs)
+    gN[sel.ravel()] = zN[sel.ravel()] - target
+    want_z, want_nu = _oracle_grad(wl, z0, dt, n, gN)
+    ez = rel_inf(u0.grad.cpu().numpy(), want_z)
+    en = rel_inf(tnu.grad.cpu().numpy(), want_nu)
+    _say(f"[autograd] dJ/dz0 {ez:.3e}  dJ/dnu {en:.3e}")
+    assert ez <= GRAD_TOL and en <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name", ["config2_full", "config5_full", "config3_full"])
+def test_full_size_transpose_identity(lib, cuda, name):
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = {"config2_full": W.config2, "config5_full": W.config5, "config3_full": W.config3}[name]()
+    _say(f"[adjoint full] {name}: ndofs={wl.ndofs}")
+    op = Operator(wl)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1234)
+    x = torch.randn(wl.ndofs, dtype=torch.float64, device="cuda", generator=gen)
+    y = torch.randn(wl.ndofs, dtype=torch.float64, device="cuda", generator=gen)
+    Lx = torch.empty_like(x)
+    Lty = torch.empty_like(y)
+    op.apply(x, Lx, with_source=False)
+    op.apply_adjoint(y, Lty)
+    torch.cuda.synchronize()
+    lhs = float(torch.dot(y, Lx))
+    rhs = float(torch.dot(Lty, x))
+    scale = float(torch.sum(torch.abs(y * Lx)))
+    _say(f"   <y,Lx>={lhs:.6e} <L^T y,x>={rhs:.6e} rel={abs(lhs - rhs) / scale:.3e}")
+    assert abs(lhs - rhs) <= APPLY_TOL * scale

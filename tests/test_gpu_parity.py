@@ -7,77 +7,15 @@ tail; full-size configurations are checked on rows the oracle assembles cell
 by cell.
 """
 
-import math
-import sys
-
 import numpy as np
 import pytest
 
 from oracle import dg
 from paper_2501_05110_amd import workloads as W
 
+from gpu_cases import APPLY_TOL, CASES, STEPS_TOL, _say, cube, gpu_apply, rel_inf, shock
+
 pytestmark = pytest.mark.gpu
-
-APPLY_TOL = 1e-12
-STEPS_TOL = 1e-10
-
-
-def _say(msg):
-    print(msg, flush=True)
-    sys.stdout.flush()
-
-
-def rel_inf(a, b):
-    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
-
-
-def gpu_apply(op, z, with_source=True):
-    import torch
-    zin = torch.from_numpy(np.ascontiguousarray(z).ravel()).cuda()
-    zout = torch.empty_like(zin)
-    op.apply(zin, zout, with_source)
-    torch.cuda.synchronize()
-    return zout.cpu().numpy()
-
-
-def shock(nx, np_, k, lmax, seed=2, **kw):
-    return W.shock_workload(f"shock_{nx}x{np_}_k{k}_l{lmax}", nx, np_, k, lmax, seed=seed, **kw)
-
-
-def uniform2d(lmax=3, k=1):
-    return W.Workload(
-        name="xy", lmax=lmax, k=k, axes=("x", "y"),
-        nodes=(np.linspace(-1, 1, 14), np.linspace(0, 2.2, 10) ** 1.1),
-        bc=((W.ZERO_INFLOW, W.CONTINUOUS), (W.PERIODIC, W.PERIODIC)),
-        terms=frozenset({W.ADVECTION, W.ROTATION, W.COLLISION}), p_fixed=1.3,
-        flow=W.uniform_flow([0.1, -0.05, 0.02]), magnetic=W.uniform_field((0.3, -0.6, 1.1)), nu=0.7)
-
-
-def planar1d(lmax=3, k=2):
-    return W.Workload(
-        name="x_planar", lmax=lmax, k=k, axes=("x",), nodes=(np.linspace(-3, 3, 41),),
-        bc=((W.ZERO_INFLOW, W.CONTINUOUS),),
-        terms=frozenset({W.ADVECTION, W.ROTATION, W.COLLISION}), p_fixed=2.0,
-        flow=W.shock_flow(0.1, 4.0, 0.3), magnetic=W.uniform_field((0.5, 0.2, 0.0)), nu=0.4)
-
-
-def cube(n=(5, 4, 3), lmax=5, k=2):
-    return W.config3(n, lmax=lmax, k=k)
-
-
-CASES = {
-    "c1": lambda: W.config1(),
-    "shock_k2_l3": lambda: shock(25, 11, 2, 3),
-    "shock_k1_l3": lambda: shock(19, 7, 1, 3),
-    "shock_k2_l1": lambda: shock(13, 9, 2, 1),
-    "shock_k1_l5": lambda: shock(11, 6, 1, 5),
-    "shock_k2_l7": lambda: shock(9, 5, 2, 7),
-    "uniform2d": lambda: uniform2d(),
-    "uniform2d_k2_l2": lambda: uniform2d(2, 2),
-    "planar1d": lambda: planar1d(),
-    "cube_k2_l5": lambda: cube(),
-    "cube_k1_l3": lambda: cube((4, 3, 5), 3, 1),
-}
 
 
 @pytest.mark.parametrize("name", list(CASES))
