@@ -22,6 +22,7 @@ MassLauncher find_mass_launcher(int D, int k);
 // Specialised kernel for two axes (x, ln p) with a planar x flow and a
 // uniform B; nrot = padded non-zeros per row of B.Omega (1 or 5).
 StageLauncher find_shock_launcher(int k, int lmax, int nrot);
+StageLauncher find_shock_adjoint_launcher(int k, int lmax, int nrot);
 
 hipError_t upload_basis(const Basis1D* b);
 

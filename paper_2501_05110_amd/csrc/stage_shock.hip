@@ -16,6 +16,15 @@
 //   L = -T(G) + (2/h_x) T'_x(F^x) + (2/h_p) T'_p(F^p) + face lifts + M^{-1} h
 // is contracted row by row of Gauss points (sum factorisation).
 //
+// With ADJ = true the same kernel applies the adjoint operator
+// K = -M^{-1} D^T in mu = M^{-1} lambda variables:
+//   K mu = T(beta^x d_x mu + beta^p d_p mu - (R - div beta)^T mu) + face lifts
+// (all tested with phi, derivative interpolation of mu; G1, G2 and B.Omega
+// transposed), and the faces take the forward flux routine with the traces
+// (d, 0) / (0, d), d = mu(own) - mu(other), or (own, own) at a continuous
+// boundary.  Each row of Gauss points then exchanges three fields (mu and its
+// two derivatives) through LDS.
+//
 // Scheduling.  All global loads (own state, the four neighbour traces, the
 // per-cell field scalars) are issued at the start; the scalars go to LDS.
 // Each face side, and each row of Gauss points, then passes through one small
@@ -74,14 +83,14 @@ __device__ __forceinline__ void cell_sync() {
   }
 }
 
-template <int K, int LMAX, int NROT>
+template <int K, int LMAX, int NROT, bool ADJ>
 __global__ __launch_bounds__(Launch<(LMAX + 1) * (LMAX + 1)>::kThreads) __attribute__((amdgpu_waves_per_eu(VFP_SHOCK_WAVES)))
 void shock_kernel(KernelArgs A) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
   constexpr int NB = K1 * K1;
   constexpr int CPB = Launch<N>::kCells;
-  constexpr int XR = 2 * K1;          // exchange rows per cell
+  constexpr int XR = (ADJ ? 3 : 2) * K1;   // exchange rows per cell
   using CB = CBasis<K>;
   static_assert(K1 <= 3, "basis tables");
   __shared__ double shx[CPB * XR * N];
@@ -192,6 +201,15 @@ void shock_kernel(KernelArgs A) {
       own[j] = w[(side ? K : 0) + K1 * j];
       oth[j] = use_n[0][side] ? tn[0][side][j] : (bc == 1 ? 0.0 : own[j]);
     }
+    if constexpr (ADJ) {
+      if (use_n[0][side] || bc != 2) {
+#pragma unroll
+        for (int j = 0; j < K1; ++j) {
+          own[j] -= oth[j];
+          oth[j] = 0.0;
+        }
+      }
+    }
     // lower cell's trace to rows [0, K1), upper cell's to rows [K1, 2 K1)
     if (in_grp) {
 #pragma unroll
@@ -262,6 +280,15 @@ void shock_kernel(KernelArgs A) {
       own[j] = w[j + K1 * (side ? K : 0)];
       oth[j] = use_n[1][side] ? tn[1][side][j] : (bc == 1 ? 0.0 : own[j]);
     }
+    if constexpr (ADJ) {
+      if (use_n[1][side] || bc != 2) {
+#pragma unroll
+        for (int j = 0; j < K1; ++j) {
+          own[j] -= oth[j];
+          oth[j] = 0.0;
+        }
+      }
+    }
     if (in_grp) {
 #pragma unroll
       for (int q = 0; q < K1; ++q) {
@@ -316,9 +343,15 @@ void shock_kernel(KernelArgs A) {
   const bool use_u = A.st.alpha != 0.0;
 #pragma unroll
   for (int b = 0; b < NB; ++b) uu[b] = (act && use_u) ? A.st.u[cbase + (size_t)b * N] : 0.0;
+  double ff[ADJ ? NB : 1];
+  const bool use_g = ADJ && A.adj.fwd && A.adj.grad_nu;
+  if constexpr (ADJ) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b) ff[b] = (act && use_g) ? A.adj.fwd[cbase + (size_t)b * N] : 0.0;
+  }
 
   // ---- volume, one row of Gauss points (fixed q1) at a time -----------------
-  {
+  if constexpr (!ADJ) {
     const double g1v0 = T.g1_val[r], g1v1 = T.g1_val[N + r];
     const double g2v0 = T.g2_val[r], g2v1 = T.g2_val[N + r], g2v2 = T.g2_val[2 * N + r];
     int rc[NROT];
@@ -404,10 +437,153 @@ void shock_kernel(KernelArgs A) {
         }
       cell_sync<N>();
     }
+  } else {
+    const double g1t0 = T.g1t_val[r], g1t1 = T.g1t_val[N + r];
+    const double g2t0 = T.g2t_val[r], g2t1 = T.g2t_val[N + r], g2t2 = T.g2t_val[2 * N + r];
+    int rc[NROT];
+    double rv[NROT];
+#pragma unroll
+    for (int s = 0; s < NROT; ++s) {
+      rc[s] = T.rot_col[s * N + r];
+      rv[s] = T.rot_val[s * N + r];
+    }
+    const double nuc = T.c_val[r] * sc[C_NU];
+    const double mom_s2hp = -F.t_mom * sc[P_S2H];
+    const double t_adv = F.t_adv, t_mom = F.t_mom;
+    const double tas2hx = t_adv * sc[X_S2H];
+    // along x once: values t and x-derivatives tx at [q0 + K1 j1]
+    double t[NB], tx[NB];
+#pragma unroll
+    for (int j1 = 0; j1 < K1; ++j1)
+#pragma unroll
+      for (int q0 = 0; q0 < K1; ++q0) {
+        double a = 0.0, d = 0.0;
+#pragma unroll
+        for (int j0 = 0; j0 < K1; ++j0) {
+          a = fma(CB::phi[q0][j0], w[j0 + K1 * j1], a);
+          if (CB::dphi[q0][j0] != 0.0) d = fma(CB::dphi[q0][j0], w[j0 + K1 * j1], d);
+        }
+        t[q0 + K1 * j1] = a;
+        tx[q0 + K1 * j1] = d;
+      }
+#pragma unroll
+    for (int q1 = 0; q1 < K1; ++q1) {
+      if (in_grp) {
+#pragma unroll
+        for (int q0 = 0; q0 < K1; ++q0) {
+          double f = 0.0, dx = 0.0, dp = 0.0;
+#pragma unroll
+          for (int j1 = 0; j1 < K1; ++j1) {
+            if (CB::phi[q1][j1] != 0.0) {
+              f = fma(CB::phi[q1][j1], t[q0 + K1 * j1], f);
+              dx = fma(CB::phi[q1][j1], tx[q0 + K1 * j1], dx);
+            }
+            if (CB::dphi[q1][j1] != 0.0) dp = fma(CB::dphi[q1][j1], t[q0 + K1 * j1], dp);
+          }
+          X[q0 * N + r] = f;
+          X[(K1 + q0) * N + r] = dx;
+          X[(2 * K1 + q0) * N + r] = dp;
+        }
+      }
+      cell_sync<N>();
+      const double pV = tas2hx * sc[P_V + q1];
+      const double piV = sc[P_IV + q1];
+      const double pid = sc[P_ID + q1];
+      const double pig = sc[P_IG + q1];
+      double ac[K1];
+#pragma unroll
+      for (int i = 0; i < K1; ++i) ac[i] = 0.0;
+#pragma unroll
+      for (int q0 = 0; q0 < K1; ++q0) {
+        const double U = sc[X_U + q0];
+        const double dU = sc[X_DU + q0];
+        const double a = sc[X_A + q0];
+        const double* P = X + q0 * N;
+        const double* Qx = X + (K1 + q0) * N;
+        const double* Qp = X + (2 * K1 + q0) * N;
+        const double f = P[r];
+        const double fxp = P[axc0], fxm = P[axc1];
+        const double fpp = P[axxc0], fmm = P[axxc1];
+        double Rf = 0.0;
+#pragma unroll
+        for (int s = 0; s < NROT; ++s) Rf = fma(rv[s], P[rc[s]], Rf);
+        const double Axf = fma(axv0, fxp, axv1 * fxm);
+        const double G1t = fma(g1t0, fxp, g1t1 * fxm);
+        const double G2t = fma(g2t0, fpp, fma(g2t1, f, g2t2 * fmm));
+        const double aiV = a * piV;
+        double G = fma(aiV, G1t, dU * fma(t_mom, G2t, -t_adv * f));
+        G = fma(-a * pid, Axf, G);
+        G = fma(pig, Rf, G);                // (B.Omega)^T = -B.Omega
+        G = fma(nuc, f, G);
+        const double Axd = fma(axv0, Qx[axc0], axv1 * Qx[axc1]);
+        const double Xa = fma(U, Qx[r], pV * Axd);
+        const double Axp = fma(axv0, Qp[axc0], axv1 * Qp[axc1]);
+        const double A2p = fma(axxv0, Qp[axxc0], fma(axxv1, Qp[r], axxv2 * Qp[axxc1]));
+        const double Pa = mom_s2hp * fma(aiV, Axp, dU * A2p);
+        const double h = Xa + Pa - G;
+#pragma unroll
+        for (int i = 0; i < K1; ++i)
+          if (CB::tst[i][q0] != 0.0) ac[i] = fma(CB::tst[i][q0], h, ac[i]);
+      }
+#pragma unroll
+      for (int i1 = 0; i1 < K1; ++i1)
+#pragma unroll
+        for (int i0 = 0; i0 < K1; ++i0)
+          if (CB::tst[i1][q1] != 0.0) res[i0 + K1 * i1] = fma(CB::tst[i1][q1], ac[i0], res[i0 + K1 * i1]);
+      cell_sync<N>();
+    }
   }
 
   // ---- source and output ---------------------------------------------------
-  if (A.st.with_source && F.src && r == 0 && act) {
+  if constexpr (ADJ) {
+    // (M1 x M1) v on the reference cell
+    auto ref_mass2 = [&](double* v) {
+      double tm[NB];
+#pragma unroll
+      for (int i1 = 0; i1 < K1; ++i1)
+#pragma unroll
+        for (int i0 = 0; i0 < K1; ++i0) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j0 = 0; j0 < K1; ++j0) acc = fma(CB::mass[i0][j0], v[j0 + K1 * i1], acc);
+          tm[i0 + K1 * i1] = acc;
+        }
+#pragma unroll
+      for (int i1 = 0; i1 < K1; ++i1)
+#pragma unroll
+        for (int i0 = 0; i0 < K1; ++i0) {
+          double acc = 0.0;
+#pragma unroll
+          for (int j1 = 0; j1 < K1; ++j1) acc = fma(CB::mass[i1][j1], tm[i0 + K1 * j1], acc);
+          v[i0 + K1 * i1] = acc;
+        }
+    };
+    const double jac = 1.0 / (sc[X_S2H] * sc[P_S2H]);
+    if (A.adj.mass_out) {
+      ref_mass2(res);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) res[b] *= jac;
+    }
+    if (use_g) {
+      // d/dnu_c of <M mu, beta L(fwd)> = -beta t_col sum C (M mu) . fwd
+      ref_mass2(w);
+      double part = 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) part = fma(w[b], ff[b], part);
+      part *= T.c_val[r] * jac;
+      if (in_grp) X[r] = part;
+      cell_sync<N>();
+      if (act && r == 0) {
+        double sum = 0.0;
+        for (int j = 0; j < N; ++j) sum += X[j];
+        A.adj.grad_nu[cell] -= A.st.beta * F.t_col * sum;
+      }
+    }
+    if (act && A.adj.t_out) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) A.adj.t_out[cbase + (size_t)b * N] = A.st.beta * res[b];
+    }
+  } else if (A.st.with_source && F.src && r == 0 && act) {
     double src[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) src[b] = F.src[(size_t)cell * NB + b];
@@ -421,35 +597,42 @@ void shock_kernel(KernelArgs A) {
   }
 }
 
-template <int K, int LMAX, int NROT>
+template <int K, int LMAX, int NROT, bool ADJ>
 void launch_shock_t(const KernelArgs& a, hipStream_t s) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   using L = Launch<N>;
   const int blocks = (a.mesh.ncells + L::kCells - 1) / L::kCells;
-  hipLaunchKernelGGL((shock_kernel<K, LMAX, NROT>), dim3(blocks), dim3(L::kThreads), 0, s, a);
+  hipLaunchKernelGGL((shock_kernel<K, LMAX, NROT, ADJ>), dim3(blocks), dim3(L::kThreads), 0, s, a);
 }
 
-template <int K, int NROT>
+template <int K, int NROT, bool ADJ>
 StageLauncher pick(int lmax) {
   switch (lmax) {
-    case 1: return &launch_shock_t<K, 1, NROT>;
-    case 2: return &launch_shock_t<K, 2, NROT>;
-    case 3: return &launch_shock_t<K, 3, NROT>;
-    case 4: return &launch_shock_t<K, 4, NROT>;
-    case 5: return &launch_shock_t<K, 5, NROT>;
-    case 6: return &launch_shock_t<K, 6, NROT>;
-    case 7: return &launch_shock_t<K, 7, NROT>;
+    case 1: return &launch_shock_t<K, 1, NROT, ADJ>;
+    case 2: return &launch_shock_t<K, 2, NROT, ADJ>;
+    case 3: return &launch_shock_t<K, 3, NROT, ADJ>;
+    case 4: return &launch_shock_t<K, 4, NROT, ADJ>;
+    case 5: return &launch_shock_t<K, 5, NROT, ADJ>;
+    case 6: return &launch_shock_t<K, 6, NROT, ADJ>;
+    case 7: return &launch_shock_t<K, 7, NROT, ADJ>;
     default: return nullptr;
   }
 }
 
+template <bool ADJ>
+StageLauncher pick_shock(int k, int lmax, int nrot) {
+  if (nrot != 1 && nrot != 5) return nullptr;
+  if (k == 1) return nrot == 1 ? pick<1, 1, ADJ>(lmax) : pick<1, 5, ADJ>(lmax);
+  if (k == 2) return nrot == 1 ? pick<2, 1, ADJ>(lmax) : pick<2, 5, ADJ>(lmax);
+  return nullptr;
+}
+
 }  // namespace
 
-StageLauncher find_shock_launcher(int k, int lmax, int nrot) {
-  if (nrot != 1 && nrot != 5) return nullptr;
-  if (k == 1) return nrot == 1 ? pick<1, 1>(lmax) : pick<1, 5>(lmax);
-  if (k == 2) return nrot == 1 ? pick<2, 1>(lmax) : pick<2, 5>(lmax);
-  return nullptr;
+StageLauncher find_shock_launcher(int k, int lmax, int nrot) { return pick_shock<false>(k, lmax, nrot); }
+
+StageLauncher find_shock_adjoint_launcher(int k, int lmax, int nrot) {
+  return pick_shock<true>(k, lmax, nrot);
 }
 
 }  // namespace vfp

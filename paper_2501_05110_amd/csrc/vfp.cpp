@@ -669,7 +669,10 @@ int refresh(vfp_ctx* c) {
   if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general)
     c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot);
   if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
-  c->adj_launcher = find_adjoint_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
+  c->adj_launcher = nullptr;
+  if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general)
+    c->adj_launcher = find_shock_adjoint_launcher(c->k, c->lmax, c->tab.nrot);
+  if (!c->adj_launcher) c->adj_launcher = find_adjoint_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
   c->mass_launcher = find_mass_launcher(c->naxes, c->k);
   return VFP_OK;
 }

@@ -215,3 +215,33 @@ def test_full_size_transpose_identity(lib, cuda, name):
     scale = float(torch.sum(torch.abs(y * Lx)))
     _say(f"   <y,Lx>={lhs:.6e} <L^T y,x>={rhs:.6e} rel={abs(lhs - rhs) / scale:.3e}")
     assert abs(lhs - rhs) <= APPLY_TOL * scale
+
+
+@pytest.mark.parametrize("name", ["shock_k2_l3", "shock_k1_l5", "shock_k2_l7"])
+def test_specialised_matches_general(lib, cuda, name, monkeypatch):
+    """The (x, ln p) kernels against the general kernel family on the same
+    inputs (forward apply, adjoint apply, one adjoint stage with d/dnu): the
+    two differ only in summation order."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = CASES[name]()
+    g = np.random.default_rng(31)
+    z, mu, fwd = (g.standard_normal(wl.ndofs) for _ in range(3))
+    outs = {}
+    for kind in ("shock", "general"):
+        if kind == "general":
+            monkeypatch.setenv("VFP_KERNEL", "general")
+        else:
+            monkeypatch.delenv("VFP_KERNEL", raising=False)
+        op = Operator(wl)
+        a, b, t, acc = (torch.empty(wl.ndofs, dtype=torch.float64, device="cuda") for _ in range(4))
+        gnu = torch.zeros(wl.ncells, dtype=torch.float64, device="cuda")
+        op.apply(_dev(z), a)
+        op.apply_adjoint(_dev(z), b)
+        op.adjoint_stage(_dev(mu), _dev(mu), _dev(fwd), 0.01, t, acc, gnu)
+        outs[kind] = [_host(x) for x in (a, b, t, acc, gnu)]
+        op.close()
+    for i, label in enumerate(("apply", "apply_adjoint", "t", "acc", "grad_nu")):
+        err = rel_inf(outs["shock"][i], outs["general"][i])
+        _say(f"[kernels] {name} {label}: {err:.3e}")
+        assert err <= 1e-13, (label, err)
