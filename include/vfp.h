@@ -247,6 +247,52 @@ int vfp_forward_checkpoints(vfp_ctx* ctx, double* u, double dt, int64_t nsteps, 
 int vfp_adjoint_checkpointed(vfp_ctx* ctx, const double* ckpt, double dt, int64_t nsteps, int64_t seg,
                              double* tape, double* lam, double* grad_nu, double* work, void* stream);
 
+/* ------------------------------------------------------------------ batches
+ *
+ * Many independent runs (each its own context: mesh, l_max, k, fields, time
+ * step) advanced together.  The runs are grouped into classes of equal
+ * (k, l_max, rows of B.Omega); for the (x, ln p) runs of Sec. 4.4 one launch
+ * per Runge-Kutta stage and class walks the (run, tile) items of all its
+ * runs, other runs are launched one by one.  Each run's arithmetic is the
+ * same as vfp_advance's, so results agree with the runs advanced alone to
+ * the last bit.
+ */
+typedef struct vfp_batch vfp_batch;
+
+#define VFP_BATCH_GRAPH 1u   /* replay each step as a captured HIP graph */
+
+/* Group nruns ready contexts (all on one device, none repeated).  The batch
+ * borrows the contexts: they must outlive it, and set-up calls on them
+ * after vfp_batch_bind need a new vfp_batch_bind. */
+int vfp_batch_create(vfp_batch** out, vfp_ctx* const* runs, int nruns, unsigned flags);
+
+void vfp_batch_destroy(vfp_batch* b);
+
+/* Bind the state u[r] (ndofs_r doubles) and work[r] (2 ndofs_r doubles,
+ * disjoint from u[r]) device buffers and the time step dt[r] of every run
+ * (host arrays of nruns entries).  Synchronous (uploads the per-run stage
+ * descriptors); drops a captured graph. */
+int vfp_batch_bind(vfp_batch* b, double* const* u, double* const* work, const double* dt);
+
+/* Advance every bound run by nsteps Runge-Kutta steps (as vfp_advance).
+ * With VFP_BATCH_GRAPH the first call captures one step into a graph on a
+ * private stream, ordered after `stream` by events, and later calls replay
+ * it; `stream` waits for the replays. */
+int vfp_batch_advance(vfp_batch* b, int64_t nsteps, void* stream);
+
+/* Time the batched kernel of every class over the bound buffers (stage-1
+ * form: reads u, writes the first work vector; u is unchanged), reps
+ * launches per candidate, for each tile order -- launch order, or each of the
+ * 8 XCDs taking one contiguous range of tiles -- and keep the faster.
+ * Synchronises `stream`; drops a captured graph. */
+int vfp_batch_autotune(vfp_batch* b, int reps, void* stream);
+
+/* Number of classes, and for class i: info[0..7] = k, l_max, rows of B.Omega,
+ * runs, batched (1/0), tiles, workgroups per launch (one per tile), tile order
+ * (1: XCD ranges). */
+int vfp_batch_nclasses(const vfp_batch* b);
+int vfp_batch_class_info(const vfp_batch* b, int i, int* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -128,6 +128,17 @@ struct KernelArgs {
   RowTables tab;
   StageArgs st;
   AdjArgs adj;
+  int tile_map;           // 1: launch order -> tile by XCD ranges (shock kernels)
+};
+
+// Batched (x, ln p) stage: one launch walks the tiles of many runs.  Run r
+// owns tiles [start[r], start[r+1]); descs[r] holds its arguments.
+struct BatchArgs {
+  const KernelArgs* descs;
+  const int* start;       // nruns + 1 prefix sums of tiles
+  int nruns;
+  int total;              // start[nruns]
+  int tile_map;
 };
 
 }  // namespace vfp

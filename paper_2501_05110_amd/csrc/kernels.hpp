@@ -23,6 +23,17 @@ namespace vfp {
 
 extern __constant__ Basis1D c_basis[kMaxK];
 
+// A generic pointer known to address global memory, retyped into the global
+// address space: loads and stores through it are global (not flat) memory
+// instructions, also for pointers that were themselves loaded from memory.
+template <class T>
+using global_ptr = __attribute__((address_space(1))) T*;
+
+template <class T>
+__device__ __forceinline__ global_ptr<T> gp(T* p) {
+  return (global_ptr<T>)p;
+}
+
 template <int B, int E>
 struct IPow { static constexpr int v = B * IPow<B, E - 1>::v; };
 template <int B>

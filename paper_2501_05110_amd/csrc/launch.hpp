@@ -24,6 +24,15 @@ MassLauncher find_mass_launcher(int D, int k);
 StageLauncher find_shock_launcher(int k, int lmax, int nrot);
 StageLauncher find_shock_adjoint_launcher(int k, int lmax, int nrot);
 
+// Batched (x, ln p) forward stage over many runs of one (k, l_max, nrot)
+// class: one workgroup per tile.
+struct BatchKernel {
+  void (*launch)(const BatchArgs&, hipStream_t) = nullptr;
+  int cells_per_tile = 0;
+};
+BatchKernel find_shock_batch_kernel(int k, int lmax, int nrot);
+int shock_cells_per_tile(int lmax);
+
 hipError_t upload_basis(const Basis1D* b);
 
 int stage_cells_per_block(int lmax);

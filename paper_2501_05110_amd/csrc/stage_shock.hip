@@ -1,600 +1,17 @@
-// Fused operator / Runge-Kutta stage for the (x, ln p) configuration with a
-// planar flow U_x(x), a uniform magnetic field and a per-cell or uniform
-// scattering rate -- the parallel-shock runs of Sec. 4.4.
-//
-//   w_out = alpha u + beta L(w_in),   L(w) = M^{-1}(h - D w)
-//
-// Lane = (cell, lms); the cell's (k+1)^2 nodal values of that coefficient stay
-// in registers.  Per Gauss point the lane needs the coefficients
-// (l+-1, m, s), (l+-2, m, s) and the rotation row of its own cell, which are
-// exchanged through LDS:
-//   F^x = U f + V A^x f                                 (advection, x)
-//   F^p = -(dU/dt / V) A^x f - U' (A^x A^x)_t f         (beta^{ln p} f)
-//   G   = (dU/dt / V) G1 f + U' (G2 f - f) - dU/dt m/(gamma p) A^x f
-//         - (q/(gamma m)) (B.Omega) f + nu C f         ((R - div beta) f)
-// with G1 = (A^y Om^z - A^z Om^y)_t, G2 = (A^x G1)_t.  The weak form
-//   L = -T(G) + (2/h_x) T'_x(F^x) + (2/h_p) T'_p(F^p) + face lifts + M^{-1} h
-// is contracted row by row of Gauss points (sum factorisation).
-//
-// With ADJ = true the same kernel applies the adjoint operator
-// K = -M^{-1} D^T in mu = M^{-1} lambda variables:
-//   K mu = T(beta^x d_x mu + beta^p d_p mu - (R - div beta)^T mu) + face lifts
-// (all tested with phi, derivative interpolation of mu; G1, G2 and B.Omega
-// transposed), and the faces take the forward flux routine with the traces
-// (d, 0) / (0, d), d = mu(own) - mu(other), or (own, own) at a continuous
-// boundary.  Each row of Gauss points then exchanges three fields (mu and its
-// two derivatives) through LDS.
-//
-// Scheduling.  All global loads (own state, the four neighbour traces, the
-// per-cell field scalars) are issued at the start; the scalars go to LDS.
-// Each face side, and each row of Gauss points, then passes through one small
-// LDS exchange area of 2(k+1) rows per cell, so that few values are live at
-// once.  When a cell's n lanes never straddle a wavefront (n divides 64) the
-// workgroup is one wavefront and the exchanges need no workgroup barrier.
-#include "basis.hpp"
-#include "kernels.hpp"
-#include "launch.hpp"
+// Single-run (x, ln p) stage kernels: forward (w_out = alpha u + beta L(w_in))
+// and adjoint, one launch per stage over all cells of one run.
+#include "shock_body.hpp"
 
 namespace vfp {
 namespace {
 
-#ifndef VFP_SHOCK_WAVES
-#define VFP_SHOCK_WAVES 1
-#endif
-
-// per-cell scalar record in LDS (doubles): the packed x record of the cell's
-// x column, the packed p record of its p row, the p-face codes and nu
-enum : int {
-  X_U = 0,       // t_adv (2/h_x) U_x at the x Gauss points            [3]
-  X_DU = 3,      // dU_x/dx                                             [3]
-  X_A = 6,       // t_mom dU_x/dt                                       [3]
-  X_UF = 9,      // t_adv U_x at the lo / hi x face                     [2]
-  X_S2H = 11,    // 2/h_x
-  P_V = 16,      // V at the p Gauss points                             [3]
-  P_IV = 19,     // 1/V                                                 [3]
-  P_ID = 22,     // m/(gamma p)                                         [3]
-  P_IG = 25,     // t_rot q/(gamma m)                                   [3]
-  P_IVF = 28,    // t_mom / V at the lo / hi p face                     [2]
-  P_S2H = 30,    // 2/h_p
-  C_CODE = 32,   // p-face upwind codes [side][x point]                 [2*K1]
-  C_NU = 38,     // t_col nu
-  S_STRIDE = 40
-};
-static_assert(kRec == 16, "record layout");
-
-template <int N>
-struct Launch {
-  static constexpr bool kWave = (64 % N) == 0;
-  static constexpr int kThreads = kWave ? 64 : 256;
-  static constexpr int kCells = (kThreads / N) > 0 ? kThreads / N : 1;
-};
-
-// Orders the LDS exchange between the lanes of one cell.  LDS operations of
-// one wavefront complete in order, so within a wavefront a compiler-level
-// fence suffices; otherwise the workgroup synchronises.
-template <int N>
-__device__ __forceinline__ void cell_sync() {
-  if constexpr (Launch<N>::kWave) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
-}
+using namespace shock;
 
 template <int K, int LMAX, int NROT, bool ADJ>
 __global__ __launch_bounds__(Launch<(LMAX + 1) * (LMAX + 1)>::kThreads) __attribute__((amdgpu_waves_per_eu(VFP_SHOCK_WAVES)))
 void shock_kernel(KernelArgs A) {
-  constexpr int N = (LMAX + 1) * (LMAX + 1);
-  constexpr int K1 = K + 1;
-  constexpr int NB = K1 * K1;
-  constexpr int CPB = Launch<N>::kCells;
-  constexpr int XR = (ADJ ? 3 : 2) * K1;   // exchange rows per cell
-  using CB = CBasis<K>;
-  static_assert(K1 <= 3, "basis tables");
-  __shared__ double shx[CPB * XR * N];
-  __shared__ double shs[CPB * S_STRIDE];
-
-  const int tid = threadIdx.x;
-  const int cl = tid / N;
-  const int r = tid - cl * N;
-  const bool in_grp = cl < CPB;
-  const MeshArgs& M = A.mesh;
-  const FieldArgs& F = A.fld;
-  const RowTables& T = A.tab;
-  const int cell0 = blockIdx.x * CPB + cl;
-  const bool act = in_grp && cell0 < M.ncells;
-  const int cell = act ? cell0 : 0;
-  const int nx = M.n[0], np = M.n[1];
-  const int ix = cell % nx, ip = cell / nx;
-  const int clc = in_grp ? cl : 0;
-  double* X = shx + clc * XR * N;
-  double* sc = shs + clc * S_STRIDE;
-
-  // ---- issue every global load, in order of first use ------------------------
-  constexpr int NREC = (kRec + N - 1) / N;
-  constexpr int NCODE = (2 * K1 + N - 1) / N;
-  double rx[NREC], rp[NREC], rcode[NCODE], rnu = 0.0;
-#pragma unroll
-  for (int it = 0; it < NREC; ++it) {
-    const int e = r + it * N;
-    rx[it] = (in_grp && e < kRec) ? F.xrec[(size_t)ix * kRec + e] : 0.0;
-    rp[it] = (in_grp && e < kRec) ? F.prec[(size_t)ip * kRec + e] : 0.0;
-  }
-#pragma unroll
-  for (int it = 0; it < NCODE; ++it) {
-    const int e = r + it * N;
-    rcode[it] = (in_grp && e < 2 * K1) ? F.pf_coded[(size_t)(ip + e / K1) * (nx * K1) + ix * K1 + e % K1]
-                                       : 0.0;
-  }
-  if (in_grp && r == 0) rnu = F.t_col * (F.nu_cell ? F.nu_cell[cell] : F.nu0);
-
-  const size_t cbase = (size_t)cell * NB * N + r;
-  const double* win = A.st.w_in + cbase;
-  double w[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) w[b] = act ? win[(size_t)b * N] : 0.0;
-
-  // neighbour traces: tn[axis][side][j]; x faces carry nodes along p, p faces
-  // nodes along x.  Boundary sides are resolved to 0 (zero inflow) or the own
-  // trace (continuous) below.
-  double tn[2][2][K1];
-  bool use_n[2][2];
-#pragma unroll
-  for (int ax = 0; ax < 2; ++ax)
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int ia = ax ? ip : ix, na = ax ? np : nx, st = ax ? nx : 1;
-      int ni = side ? ia + 1 : ia - 1;
-      const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
-      use_n[ax][side] = (ni >= 0 && ni < na) || bc == 0;
-      ni = (ni + na) % na;
-      const double* nb0 = A.st.w_in + (size_t)(cell + (ni - ia) * st) * NB * N + r;
-      const int jn = side ? 0 : K;
-#pragma unroll
-      for (int j = 0; j < K1; ++j) {
-        const int node = ax ? (j + K1 * jn) : (jn + K1 * j);
-        tn[ax][side][j] = (act && use_n[ax][side]) ? nb0[(size_t)node * N] : 0.0;
-      }
-    }
-
-  // rows for the x faces
-  int mem[LMAX + 1];
-  double wcol[LMAX + 1], wrow[LMAX + 1];
-#pragma unroll
-  for (int i = 0; i <= LMAX; ++i) {
-    mem[i] = T.blk_mem[i * N + r];
-    wcol[i] = T.w_col[i * N + r];
-    wrow[i] = T.w_row[i * N + r];
-  }
-  const double lam = T.lam[r];
-
-  if (in_grp) {
-#pragma unroll
-    for (int it = 0; it < NREC; ++it) {
-      const int e = r + it * N;
-      if (e < kRec) {
-        sc[e] = rx[it];
-        sc[kRec + e] = rp[it];
-      }
-    }
-#pragma unroll
-    for (int it = 0; it < NCODE; ++it) {
-      const int e = r + it * N;
-      if (e < 2 * K1) sc[C_CODE + e] = rcode[it];
-    }
-    if (r == 0) sc[C_NU] = rnu;
-  }
-
-  double res[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) res[b] = 0.0;
-
-  // ---- x faces: characteristic variables of A^x ------------------------------
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    double own[K1], oth[K1];
-    const int bc = side ? M.bc_hi[0] : M.bc_lo[0];
-#pragma unroll
-    for (int j = 0; j < K1; ++j) {
-      own[j] = w[(side ? K : 0) + K1 * j];
-      oth[j] = use_n[0][side] ? tn[0][side][j] : (bc == 1 ? 0.0 : own[j]);
-    }
-    if constexpr (ADJ) {
-      if (use_n[0][side] || bc != 2) {
-#pragma unroll
-        for (int j = 0; j < K1; ++j) {
-          own[j] -= oth[j];
-          oth[j] = 0.0;
-        }
-      }
-    }
-    // lower cell's trace to rows [0, K1), upper cell's to rows [K1, 2 K1)
-    if (in_grp) {
-#pragma unroll
-      for (int q = 0; q < K1; ++q) {
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int j = 0; j < K1; ++j) {
-          a = fma(CB::phi[q][j], side ? own[j] : oth[j], a);
-          b = fma(CB::phi[q][j], side ? oth[j] : own[j], b);
-        }
-        X[q * N + r] = a;
-        X[(K1 + q) * N + r] = b;
-      }
-    }
-    cell_sync<N>();
-    double Jc[K1];
-    const double UF = sc[X_UF + side];
-#pragma unroll
-    for (int q = 0; q < K1; ++q) {
-      double c1 = 0.0, c2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= LMAX; ++j) {
-        c1 = fma(wcol[j], X[q * N + mem[j]], c1);
-        c2 = fma(wcol[j], X[(K1 + q) * N + mem[j]], c2);
-      }
-      const double mu = fma(F.t_adv * lam, sc[P_V + q], UF);
-      Jc[q] = fmax(mu, 0.0) * c1 + fmin(mu, 0.0) * c2;
-    }
-    cell_sync<N>();
-    if (in_grp) {
-#pragma unroll
-      for (int q = 0; q < K1; ++q) X[q * N + r] = Jc[q];
-    }
-    cell_sync<N>();
-    double J[K1];
-#pragma unroll
-    for (int q = 0; q < K1; ++q) {
-      double acc = 0.0;
-#pragma unroll
-      for (int i = 0; i <= LMAX; ++i) acc = fma(wrow[i], X[q * N + mem[i]], acc);
-      J[q] = acc;
-    }
-    const double scl = side ? -sc[X_S2H] : sc[X_S2H];
-#pragma unroll
-    for (int i1 = 0; i1 < K1; ++i1) {
-      double jn = 0.0;
-#pragma unroll
-      for (int q = 0; q < K1; ++q)
-        if (CB::tst[i1][q] != 0.0) jn = fma(CB::tst[i1][q], J[q], jn);
-      jn *= scl;
-#pragma unroll
-      for (int i0 = 0; i0 < K1; ++i0) res[i0 + K1 * i1] = fma(CB::lift[side][i0], jn, res[i0 + K1 * i1]);
-    }
-    cell_sync<N>();
-  }
-
-  // ---- ln p faces: beta^{ln p} = a1 A^x + a2 (A^x A^x)_t per point ---------
-  const int axc0 = T.ax_col[r], axc1 = T.ax_col[N + r];
-  const double axv0 = T.ax_val[r], axv1 = T.ax_val[N + r];
-  const int axxc0 = T.axx_col[r], axxc1 = T.axx_col[N + r];
-  const double axxv0 = T.axx_val[r], axxv1 = T.axx_val[N + r], axxv2 = T.axx_val[2 * N + r];
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    double own[K1], oth[K1];
-    const int bc = side ? M.bc_hi[1] : M.bc_lo[1];
-#pragma unroll
-    for (int j = 0; j < K1; ++j) {
-      own[j] = w[j + K1 * (side ? K : 0)];
-      oth[j] = use_n[1][side] ? tn[1][side][j] : (bc == 1 ? 0.0 : own[j]);
-    }
-    if constexpr (ADJ) {
-      if (use_n[1][side] || bc != 2) {
-#pragma unroll
-        for (int j = 0; j < K1; ++j) {
-          own[j] -= oth[j];
-          oth[j] = 0.0;
-        }
-      }
-    }
-    if (in_grp) {
-#pragma unroll
-      for (int q = 0; q < K1; ++q) {
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int j = 0; j < K1; ++j) {
-          a = fma(CB::phi[q][j], side ? own[j] : oth[j], a);
-          b = fma(CB::phi[q][j], side ? oth[j] : own[j], b);
-        }
-        X[q * N + r] = a;
-        X[(K1 + q) * N + r] = b;
-      }
-    }
-    cell_sync<N>();
-    const double iVf = sc[P_IVF + side];
-    double J[K1];
-#pragma unroll
-    for (int q = 0; q < K1; ++q) {
-      const double a1 = -sc[X_A + q] * iVf;
-      const double a2 = -F.t_mom * sc[X_DU + q];
-      const int code = (int)sc[C_CODE + side * K1 + q];
-      const double* P1 = X + q * N;
-      const double* P2 = X + (K1 + q) * N;
-      const double* Pu = (code == -1) ? P1 : P2;
-      double jv = a1 * fma(axv0, Pu[axc0], axv1 * Pu[axc1]) +
-                  a2 * fma(axxv0, Pu[axxc0], fma(axxv1, Pu[r], axxv2 * Pu[axxc1]));
-      if (code >= 0) {
-        const double* tb = F.pf_tab + ((size_t)code * N + r) * (LMAX + 1);
-#pragma unroll
-        for (int i = 0; i <= LMAX; ++i) jv = fma(tb[i], P1[mem[i]] - P2[mem[i]], jv);
-      }
-      J[q] = jv;
-    }
-    const double scl = side ? -sc[P_S2H] : sc[P_S2H];
-#pragma unroll
-    for (int i0 = 0; i0 < K1; ++i0) {
-      double jn = 0.0;
-#pragma unroll
-      for (int q = 0; q < K1; ++q)
-        if (CB::tst[i0][q] != 0.0) jn = fma(CB::tst[i0][q], J[q], jn);
-      jn *= scl;
-#pragma unroll
-      for (int i1 = 0; i1 < K1; ++i1) res[i0 + K1 * i1] = fma(CB::lift[side][i1], jn, res[i0 + K1 * i1]);
-    }
-    cell_sync<N>();
-  }
-
-  // u (the stage base) is loaded now so that its latency hides behind the
-  // volume work; each lane reads its own entries before writing them, which
-  // keeps the in-place form w_out == u correct
-  double uu[NB];
-  const bool use_u = A.st.alpha != 0.0;
-#pragma unroll
-  for (int b = 0; b < NB; ++b) uu[b] = (act && use_u) ? A.st.u[cbase + (size_t)b * N] : 0.0;
-  double ff[ADJ ? NB : 1];
-  const bool use_g = ADJ && A.adj.fwd && A.adj.grad_nu;
-  if constexpr (ADJ) {
-#pragma unroll
-    for (int b = 0; b < NB; ++b) ff[b] = (act && use_g) ? A.adj.fwd[cbase + (size_t)b * N] : 0.0;
-  }
-
-  // ---- volume, one row of Gauss points (fixed q1) at a time -----------------
-  if constexpr (!ADJ) {
-    const double g1v0 = T.g1_val[r], g1v1 = T.g1_val[N + r];
-    const double g2v0 = T.g2_val[r], g2v1 = T.g2_val[N + r], g2v2 = T.g2_val[2 * N + r];
-    int rc[NROT];
-    double rv[NROT];
-#pragma unroll
-    for (int s = 0; s < NROT; ++s) {
-      rc[s] = T.rot_col[s * N + r];
-      rv[s] = T.rot_val[s * N + r];
-    }
-    const double nuc = T.c_val[r] * sc[C_NU];
-    const double mom_s2hp = -F.t_mom * sc[P_S2H];
-    const double t_adv = F.t_adv, t_mom = F.t_mom;
-    const double tas2hx = t_adv * sc[X_S2H];
-    // interpolate along x once: t[q0 + K1 j1]
-    double t[NB];
-#pragma unroll
-    for (int j1 = 0; j1 < K1; ++j1)
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        double acc = 0.0;
-#pragma unroll
-        for (int j0 = 0; j0 < K1; ++j0) acc = fma(CB::phi[q0][j0], w[j0 + K1 * j1], acc);
-        t[q0 + K1 * j1] = acc;
-      }
-#pragma unroll
-    for (int q1 = 0; q1 < K1; ++q1) {
-      if (in_grp) {
-#pragma unroll
-        for (int q0 = 0; q0 < K1; ++q0) {
-          double acc = 0.0;
-#pragma unroll
-          for (int j1 = 0; j1 < K1; ++j1)
-            if (CB::phi[q1][j1] != 0.0) acc = fma(CB::phi[q1][j1], t[q0 + K1 * j1], acc);
-          X[q0 * N + r] = acc;
-        }
-      }
-      cell_sync<N>();
-      const double pV = tas2hx * sc[P_V + q1];
-      const double piV = sc[P_IV + q1];
-      const double pid = sc[P_ID + q1];
-      const double pig = sc[P_IG + q1];
-      double ac[K1], bc[K1];
-#pragma unroll
-      for (int i = 0; i < K1; ++i) ac[i] = bc[i] = 0.0;
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        const double U = sc[X_U + q0];
-        const double dU = sc[X_DU + q0];
-        const double a = sc[X_A + q0];
-        const double* P = X + q0 * N;
-        const double f = P[r];
-        const double fxp = P[axc0], fxm = P[axc1];
-        const double fpp = P[axxc0], fmm = P[axxc1];
-        double Rf = 0.0;
-#pragma unroll
-        for (int s = 0; s < NROT; ++s) Rf = fma(rv[s], P[rc[s]], Rf);
-        const double Axf = fma(axv0, fxp, axv1 * fxm);
-        const double G1f = fma(g1v0, fxp, g1v1 * fxm);
-        const double A2f = fma(axxv0, fpp, fma(axxv1, f, axxv2 * fmm));
-        const double G2f = fma(g2v0, fpp, fma(g2v1, f, g2v2 * fmm));
-        const double aiV = a * piV;
-        const double Xf = fma(U, f, pV * Axf);
-        const double Pp = mom_s2hp * fma(aiV, Axf, dU * A2f);
-        double G = fma(aiV, G1f, dU * fma(t_mom, G2f, -t_adv * f));
-        G = fma(-a * pid, Axf, G);
-        G = fma(-pig, Rf, G);
-        G = fma(nuc, f, G);
-#pragma unroll
-        for (int i = 0; i < K1; ++i) {
-          if (CB::tst[i][q0] != 0.0) ac[i] = fma(-CB::tst[i][q0], G, ac[i]);
-          if (CB::dtst[i][q0] != 0.0) ac[i] = fma(CB::dtst[i][q0], Xf, ac[i]);
-          if (CB::tst[i][q0] != 0.0) bc[i] = fma(CB::tst[i][q0], Pp, bc[i]);
-        }
-      }
-#pragma unroll
-      for (int i1 = 0; i1 < K1; ++i1)
-#pragma unroll
-        for (int i0 = 0; i0 < K1; ++i0) {
-          double v = res[i0 + K1 * i1];
-          if (CB::tst[i1][q1] != 0.0) v = fma(CB::tst[i1][q1], ac[i0], v);
-          if (CB::dtst[i1][q1] != 0.0) v = fma(CB::dtst[i1][q1], bc[i0], v);
-          res[i0 + K1 * i1] = v;
-        }
-      cell_sync<N>();
-    }
-  } else {
-    const double g1t0 = T.g1t_val[r], g1t1 = T.g1t_val[N + r];
-    const double g2t0 = T.g2t_val[r], g2t1 = T.g2t_val[N + r], g2t2 = T.g2t_val[2 * N + r];
-    int rc[NROT];
-    double rv[NROT];
-#pragma unroll
-    for (int s = 0; s < NROT; ++s) {
-      rc[s] = T.rot_col[s * N + r];
-      rv[s] = T.rot_val[s * N + r];
-    }
-    const double nuc = T.c_val[r] * sc[C_NU];
-    const double mom_s2hp = -F.t_mom * sc[P_S2H];
-    const double t_adv = F.t_adv, t_mom = F.t_mom;
-    const double tas2hx = t_adv * sc[X_S2H];
-    // along x once: values t and x-derivatives tx at [q0 + K1 j1]
-    double t[NB], tx[NB];
-#pragma unroll
-    for (int j1 = 0; j1 < K1; ++j1)
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        double a = 0.0, d = 0.0;
-#pragma unroll
-        for (int j0 = 0; j0 < K1; ++j0) {
-          a = fma(CB::phi[q0][j0], w[j0 + K1 * j1], a);
-          if (CB::dphi[q0][j0] != 0.0) d = fma(CB::dphi[q0][j0], w[j0 + K1 * j1], d);
-        }
-        t[q0 + K1 * j1] = a;
-        tx[q0 + K1 * j1] = d;
-      }
-#pragma unroll
-    for (int q1 = 0; q1 < K1; ++q1) {
-      if (in_grp) {
-#pragma unroll
-        for (int q0 = 0; q0 < K1; ++q0) {
-          double f = 0.0, dx = 0.0, dp = 0.0;
-#pragma unroll
-          for (int j1 = 0; j1 < K1; ++j1) {
-            if (CB::phi[q1][j1] != 0.0) {
-              f = fma(CB::phi[q1][j1], t[q0 + K1 * j1], f);
-              dx = fma(CB::phi[q1][j1], tx[q0 + K1 * j1], dx);
-            }
-            if (CB::dphi[q1][j1] != 0.0) dp = fma(CB::dphi[q1][j1], t[q0 + K1 * j1], dp);
-          }
-          X[q0 * N + r] = f;
-          X[(K1 + q0) * N + r] = dx;
-          X[(2 * K1 + q0) * N + r] = dp;
-        }
-      }
-      cell_sync<N>();
-      const double pV = tas2hx * sc[P_V + q1];
-      const double piV = sc[P_IV + q1];
-      const double pid = sc[P_ID + q1];
-      const double pig = sc[P_IG + q1];
-      double ac[K1];
-#pragma unroll
-      for (int i = 0; i < K1; ++i) ac[i] = 0.0;
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        const double U = sc[X_U + q0];
-        const double dU = sc[X_DU + q0];
-        const double a = sc[X_A + q0];
-        const double* P = X + q0 * N;
-        const double* Qx = X + (K1 + q0) * N;
-        const double* Qp = X + (2 * K1 + q0) * N;
-        const double f = P[r];
-        const double fxp = P[axc0], fxm = P[axc1];
-        const double fpp = P[axxc0], fmm = P[axxc1];
-        double Rf = 0.0;
-#pragma unroll
-        for (int s = 0; s < NROT; ++s) Rf = fma(rv[s], P[rc[s]], Rf);
-        const double Axf = fma(axv0, fxp, axv1 * fxm);
-        const double G1t = fma(g1t0, fxp, g1t1 * fxm);
-        const double G2t = fma(g2t0, fpp, fma(g2t1, f, g2t2 * fmm));
-        const double aiV = a * piV;
-        double G = fma(aiV, G1t, dU * fma(t_mom, G2t, -t_adv * f));
-        G = fma(-a * pid, Axf, G);
-        G = fma(pig, Rf, G);                // (B.Omega)^T = -B.Omega
-        G = fma(nuc, f, G);
-        const double Axd = fma(axv0, Qx[axc0], axv1 * Qx[axc1]);
-        const double Xa = fma(U, Qx[r], pV * Axd);
-        const double Axp = fma(axv0, Qp[axc0], axv1 * Qp[axc1]);
-        const double A2p = fma(axxv0, Qp[axxc0], fma(axxv1, Qp[r], axxv2 * Qp[axxc1]));
-        const double Pa = mom_s2hp * fma(aiV, Axp, dU * A2p);
-        const double h = Xa + Pa - G;
-#pragma unroll
-        for (int i = 0; i < K1; ++i)
-          if (CB::tst[i][q0] != 0.0) ac[i] = fma(CB::tst[i][q0], h, ac[i]);
-      }
-#pragma unroll
-      for (int i1 = 0; i1 < K1; ++i1)
-#pragma unroll
-        for (int i0 = 0; i0 < K1; ++i0)
-          if (CB::tst[i1][q1] != 0.0) res[i0 + K1 * i1] = fma(CB::tst[i1][q1], ac[i0], res[i0 + K1 * i1]);
-      cell_sync<N>();
-    }
-  }
-
-  // ---- source and output ---------------------------------------------------
-  if constexpr (ADJ) {
-    // (M1 x M1) v on the reference cell
-    auto ref_mass2 = [&](double* v) {
-      double tm[NB];
-#pragma unroll
-      for (int i1 = 0; i1 < K1; ++i1)
-#pragma unroll
-        for (int i0 = 0; i0 < K1; ++i0) {
-          double acc = 0.0;
-#pragma unroll
-          for (int j0 = 0; j0 < K1; ++j0) acc = fma(CB::mass[i0][j0], v[j0 + K1 * i1], acc);
-          tm[i0 + K1 * i1] = acc;
-        }
-#pragma unroll
-      for (int i1 = 0; i1 < K1; ++i1)
-#pragma unroll
-        for (int i0 = 0; i0 < K1; ++i0) {
-          double acc = 0.0;
-#pragma unroll
-          for (int j1 = 0; j1 < K1; ++j1) acc = fma(CB::mass[i1][j1], tm[i0 + K1 * j1], acc);
-          v[i0 + K1 * i1] = acc;
-        }
-    };
-    const double jac = 1.0 / (sc[X_S2H] * sc[P_S2H]);
-    if (A.adj.mass_out) {
-      ref_mass2(res);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) res[b] *= jac;
-    }
-    if (use_g) {
-      // d/dnu_c of <M mu, beta L(fwd)> = -beta t_col sum C (M mu) . fwd
-      ref_mass2(w);
-      double part = 0.0;
-#pragma unroll
-      for (int b = 0; b < NB; ++b) part = fma(w[b], ff[b], part);
-      part *= T.c_val[r] * jac;
-      if (in_grp) X[r] = part;
-      cell_sync<N>();
-      if (act && r == 0) {
-        double sum = 0.0;
-        for (int j = 0; j < N; ++j) sum += X[j];
-        A.adj.grad_nu[cell] -= A.st.beta * F.t_col * sum;
-      }
-    }
-    if (act && A.adj.t_out) {
-#pragma unroll
-      for (int b = 0; b < NB; ++b) A.adj.t_out[cbase + (size_t)b * N] = A.st.beta * res[b];
-    }
-  } else if (A.st.with_source && F.src && r == 0 && act) {
-    double src[NB];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) src[b] = F.src[(size_t)cell * NB + b];
-#pragma unroll
-    for (int b = 0; b < NB; ++b) res[b] += src[b];
-  }
-  if (act) {
-    const double al = A.st.alpha, be = A.st.beta;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) A.st.w_out[cbase + (size_t)b * N] = fma(be, res[b], al * uu[b]);
-  }
+  const int blk = A.tile_map ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
+  shock_body<K, LMAX, NROT, ADJ>(A, blk);
 }
 
 template <int K, int LMAX, int NROT, bool ADJ>

@@ -13,6 +13,7 @@
 #include <limits>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "kargs.hpp"
@@ -204,6 +205,8 @@ struct vfp_ctx {
   double lam_max = 0.0;     // largest eigenvalue of A^x
   size_t o_rot[2] = {0, 0};
   bool force_general = false;
+  bool shock = false;       // the (x, ln p) kernels are in use
+  int tile_map = 0;         // XCD-range tile order for the (x, ln p) kernels (VFP_TILE_MAP=1)
 };
 
 namespace {
@@ -471,87 +474,171 @@ int build_momentum_data(vfp_ctx* c) {
   return VFP_OK;
 }
 
+// Eigen-decomposition of a small symmetric matrix (cyclic Jacobi), in place:
+// on return a[i][i] are the eigenvalues and v the eigenvectors (columns).
+constexpr int kBlk = kMaxLmax + 1;
+void small_eigh(int n, double (&a)[kBlk][kBlk], double (&v)[kBlk][kBlk]) {
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) v[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        tot += a[i][j] * a[i][j];
+        if (i != j) off += a[i][j] * a[i][j];
+      }
+    if (off <= 1e-32 * tot || off == 0.0) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = a[p][q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < n; ++k) {
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = cs * akp - sn * akq;
+          a[k][q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = cs * apk - sn * aqk;
+          a[q][k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double vkp = v[k][p], vkq = v[k][q];
+          v[k][p] = cs * vkp - sn * vkq;
+          v[k][q] = sn * vkp + cs * vkq;
+        }
+      }
+  }
+}
+
+int host_threads() {
+  for (const char* name : {"VFP_HOST_THREADS", "OMP_NUM_THREADS"}) {
+    const char* e = std::getenv(name);
+    if (e && std::atoi(e) > 0) return std::min(std::atoi(e), 64);
+  }
+  const unsigned hw = std::thread::hardware_concurrency();
+  return hw ? (int)std::min(hw, 16u) : 1;
+}
+
 // p-face upwind data: beta^{ln p} = a1 A^x + a2 (A^x A^x)_t at each (x point,
-// p face); it keeps the (m,s) blocks of A^x, so each block is diagonalised.
+// p face); it keeps the (m,s) blocks of A^x (and the s = 0 and s = 1 blocks
+// of one m are equal), so each m block is diagonalised once.  Points where
+// beta^{ln p} vanishes (no flow gradient) are trivially code -1.
 int build_pface_data(vfp_ctx* c) {
   if (!c->mom || !c->mesh_set) return VFP_OK;
   const int pa = c->naxes - 1, K1 = c->K1, n = c->n, L = c->lmax;
   const int nxp = c->ncell[0] * K1, npf = c->ncell[pa] + 1;
   const std::vector<double>& nd = c->nodes[pa];
   const double tm = (c->terms & VFP_TERM_MOMENTUM) ? 1.0 : 0.0;
+  // the m blocks of A^x and (A^x A^x)_t
+  std::vector<double> ab((size_t)(L + 1) * kBlk * kBlk, 0.0), xb(ab.size(), 0.0);
+  for (int m = 0; m <= L; ++m)
+    for (int i = 0; i <= L - m; ++i)
+      for (int j = 0; j <= L - m; ++j) {
+        const int ri = lms_index(m + i, m, 0), rj = lms_index(m + j, m, 0);
+        ab[((size_t)m * kBlk + i) * kBlk + j] = c->S.A[0](ri, rj);
+        xb[((size_t)m * kBlk + i) * kBlk + j] = c->S.AXX(ri, rj);
+      }
+  std::vector<double> inv_v(npf);
+  for (int f = 0; f < npf; ++f) {
+    const double p = std::exp(nd[f]);
+    const double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
+    inv_v[f] = gam * c->mass / p;
+  }
+  const size_t rowsz = (size_t)n * (L + 1);
+  struct Part {
+    std::vector<int> code_ix;            // [ix - lo][f]
+    std::vector<double> tab;             // rows of mixed-sign points, in (ix, f) order
+    double bmax = 0.0;
+  };
+  const int nth = std::max(1, std::min(host_threads(), nxp));
+  std::vector<Part> parts(nth);
+  auto work = [&](int t) {
+    const int lo = (int)((long long)nxp * t / nth), hi = (int)((long long)nxp * (t + 1) / nth);
+    Part& P = parts[t];
+    P.code_ix.assign((size_t)(hi - lo) * npf, -1);
+    std::vector<double> rows(rowsz);
+    double a[kBlk][kBlk], v[kBlk][kBlk];
+    for (int ix = lo; ix < hi; ++ix) {
+      const double av = c->planar ? c->a_vol[ix] : 0.0;
+      const double du = c->planar ? c->du_vol[ix] : 0.0;
+      for (int f = 0; f < npf; ++f) {
+        const double a1 = -tm * av * inv_v[f], a2 = -tm * du;
+        if (a1 == 0.0 && a2 == 0.0) continue;       // beta = 0: code -1
+        double bnorm = 0.0;
+        double ev[kBlk][kBlk];                       // eigenvalues per block
+        double vec[kBlk][kBlk][kBlk];                // eigenvectors per block
+        for (int m = 0; m <= L; ++m) {
+          const int bsz = L - m + 1;
+          for (int i = 0; i < bsz; ++i)
+            for (int j = 0; j < bsz; ++j)
+              a[i][j] = a1 * ab[((size_t)m * kBlk + i) * kBlk + j] + a2 * xb[((size_t)m * kBlk + i) * kBlk + j];
+          small_eigh(bsz, a, v);
+          for (int i = 0; i < bsz; ++i) {
+            ev[m][i] = a[i][i];
+            bnorm = std::max(bnorm, std::fabs(a[i][i]));
+            for (int j = 0; j < bsz; ++j) vec[m][i][j] = v[i][j];
+          }
+        }
+        P.bmax = std::max(P.bmax, bnorm);
+        // eigenvalues within rounding of zero count as zero
+        const double tol = 1e-14 * bnorm;
+        bool anypos = false, anyneg = false;
+        for (int m = 0; m <= L; ++m)
+          for (int i = 0; i <= L - m; ++i) {
+            anypos |= ev[m][i] > tol;
+            anyneg |= ev[m][i] < -tol;
+          }
+        int cd = -1;
+        if (anyneg && !anypos) cd = -2;
+        if (anyneg && anypos) {
+          // beta_+ rows, for the s = 0 and s = 1 rows of each m alike
+          for (int m = 0; m <= L; ++m) {
+            const int bsz = L - m + 1;
+            for (int i = 0; i < bsz; ++i)
+              for (int j = 0; j < bsz; ++j) {
+                double acc = 0.0;
+                for (int e = 0; e < bsz; ++e) acc += vec[m][i][e] * std::max(ev[m][e], 0.0) * vec[m][j][e];
+                for (int s = 0; s <= (m ? 1 : 0); ++s)
+                  rows[(size_t)lms_index(m + i, m, s) * (L + 1) + j] = acc;
+              }
+          }
+          cd = (int)(P.tab.size() / rowsz);     // local index, offset on merge
+          P.tab.insert(P.tab.end(), rows.begin(), rows.end());
+        }
+        P.code_ix[(size_t)(ix - lo) * npf + f] = cd;
+      }
+    }
+  };
+  if (nth == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
   std::vector<int> code((size_t)nxp * npf, -1);
   std::vector<double> tab;
   c->beta_pmax = 0.0;
-  std::vector<double> Bp_rows((size_t)n * (L + 1));
-  for (int ix = 0; ix < nxp; ++ix) {
-    const double a = c->planar ? c->a_vol[ix] : 0.0;
-    const double du = c->planar ? c->du_vol[ix] : 0.0;
-    for (int f = 0; f < npf; ++f) {
-      double p = std::exp(nd[f]);
-      double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
-      const double a1 = -tm * a * gam * c->mass / p, a2 = -tm * du;
-      bool anypos = false, anyneg = false;
-      double bnorm = 0.0;
-      std::fill(Bp_rows.begin(), Bp_rows.end(), 0.0);
-      for (int m = 0; m <= L; ++m) {
-        const int bsz = L - m + 1;
-        Mat blk(bsz);
-        for (int i = 0; i < bsz; ++i)
-          for (int j = 0; j < bsz; ++j) {
-            int ri = lms_index(m + i, m, 0), rj = lms_index(m + j, m, 0);
-            blk(i, j) = a1 * c->S.A[0](ri, rj) + a2 * c->S.AXX(ri, rj);
-          }
-        std::vector<double> lam;
-        Mat W;
-        jacobi_eigh(blk, lam, W);
-        for (double l : lam) bnorm = std::max(bnorm, std::fabs(l));
-        for (int i = 0; i < bsz; ++i) {
-          if (lam[i] > 0) anypos = true;
-          if (lam[i] < 0) anyneg = true;
-        }
-        // beta_+ rows of this block, for s = 0 and s = 1 rows alike
-        for (int i = 0; i < bsz; ++i)
-          for (int j = 0; j < bsz; ++j) {
-            double acc = 0.0;
-            for (int e = 0; e < bsz; ++e) acc += W(i, e) * std::max(lam[e], 0.0) * W(j, e);
-            for (int s = 0; s <= (m ? 1 : 0); ++s)
-              Bp_rows[(size_t)lms_index(m + i, m, s) * (L + 1) + j] = acc;
-          }
+  for (int t = 0; t < nth; ++t) {
+    const int lo = (int)((long long)nxp * t / nth), hi = (int)((long long)nxp * (t + 1) / nth);
+    const int off = (int)(tab.size() / rowsz);
+    const Part& P = parts[t];
+    for (int ix = lo; ix < hi; ++ix)
+      for (int f = 0; f < npf; ++f) {
+        const int cd = P.code_ix[(size_t)(ix - lo) * npf + f];
+        code[(size_t)f * nxp + ix] = cd >= 0 ? cd + off : cd;
       }
-      c->beta_pmax = std::max(c->beta_pmax, bnorm);
-      // treat eigenvalues within rounding of zero as zero
-      const double tol = 1e-14 * bnorm;
-      anypos = anyneg = false;
-      for (int m = 0; m <= L; ++m) {
-        const int bsz = L - m + 1;
-        Mat blk(bsz);
-        for (int i = 0; i < bsz; ++i)
-          for (int j = 0; j < bsz; ++j) {
-            int ri = lms_index(m + i, m, 0), rj = lms_index(m + j, m, 0);
-            blk(i, j) = a1 * c->S.A[0](ri, rj) + a2 * c->S.AXX(ri, rj);
-          }
-        std::vector<double> lam;
-        Mat W;
-        jacobi_eigh(blk, lam, W);
-        for (double l : lam) {
-          if (l > tol) anypos = true;
-          if (l < -tol) anyneg = true;
-        }
-      }
-      int cd;
-      if (!anyneg) cd = -1;
-      else if (!anypos) cd = -2;
-      else {
-        cd = (int)(tab.size() / ((size_t)n * (L + 1)));
-        tab.insert(tab.end(), Bp_rows.begin(), Bp_rows.end());
-      }
-      code[(size_t)f * nxp + ix] = cd;
-    }
+    tab.insert(tab.end(), P.tab.begin(), P.tab.end());
+    c->beta_pmax = std::max(c->beta_pmax, P.bmax);
   }
   if (int e = upload_vec(c->d_pf_code, code)) return e;
   std::vector<double> coded(code.begin(), code.end());
   if (int e = upload_vec(c->d_pf_coded, coded)) return e;
-  if (tab.empty()) tab.assign((size_t)n * (L + 1), 0.0);
+  if (tab.empty()) tab.assign(rowsz, 0.0);
   if (int e = upload_vec(c->d_pf_tab, tab)) return e;
   return VFP_OK;
 }
@@ -619,13 +706,20 @@ int build_records(vfp_ctx* c) {
   return VFP_OK;
 }
 
-int refresh(vfp_ctx* c) {
+// What a set-up call invalidates.
+enum : unsigned { R_TAB = 1, R_MOM = 2, R_PFACE = 4, R_REC = 8, R_ALL = 15 };
+
+int refresh(vfp_ctx* c, unsigned what) {
   if (!c->mesh_set) return VFP_OK;
   if (int e = ensure_device(c)) return e;
-  if (int e = build_row_tables(c)) return e;
-  if (int e = build_momentum_data(c)) return e;
-  if (int e = build_pface_data(c)) return e;
-  if (int e = build_records(c)) return e;
+  if (what & R_TAB)
+    if (int e = build_row_tables(c)) return e;
+  if (what & R_MOM)
+    if (int e = build_momentum_data(c)) return e;
+  if (what & R_PFACE)
+    if (int e = build_pface_data(c)) return e;
+  if (what & R_REC)
+    if (int e = build_records(c)) return e;
   FieldArgs& F = c->fld;
   F = FieldArgs{};
   F.u_vol = c->d_u_vol.as<double>();
@@ -666,8 +760,11 @@ int refresh(vfp_ctx* c) {
     return VFP_OK;
   }
   c->launcher = nullptr;
-  if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general)
+  c->shock = false;
+  if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general) {
     c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot);
+    c->shock = c->launcher != nullptr;
+  }
   if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
   c->adj_launcher = nullptr;
   if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general)
@@ -741,6 +838,8 @@ int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
   {
     const char* kv = std::getenv("VFP_KERNEL");
     c->force_general = kv && std::strcmp(kv, "general") == 0;
+    const char* tm = std::getenv("VFP_TILE_MAP");
+    c->tile_map = tm ? (std::atoi(tm) != 0) : 0;
   }
   c->S = build_sh_matrices(lmax);
   {
@@ -813,7 +912,7 @@ int vfp_set_mesh(vfp_ctx* c, const int* ncells, const double* const* nodes, cons
     if (int e = upload_vec(c->d_u_face, c->u_face)) return e;
   }
   if (!c->mom && !(c->p_fixed > 0)) return VFP_OK;
-  return refresh(c);
+  return refresh(c, R_ALL);
 }
 
 int vfp_set_momentum(vfp_ctx* c, double p) {
@@ -821,7 +920,7 @@ int vfp_set_momentum(vfp_ctx* c, double p) {
   if (c->mom) return fail(VFP_EINVAL, "context has a ln p axis; momentum is a coordinate");
   if (!(p > 0) || !std::isfinite(p)) return fail(VFP_EINVAL, "p=%g must be positive", p);
   c->p_fixed = p;
-  return refresh(c);
+  return refresh(c, R_TAB);
 }
 
 int vfp_query_points(const vfp_ctx* c, int which, int axis, double* coords, int64_t* count) {
@@ -865,7 +964,7 @@ int vfp_set_flow_uniform(vfp_ctx* c, const double* U) {
   } else {
     c->planar = false;
   }
-  return refresh(c);
+  return refresh(c, R_TAB | R_PFACE | R_REC);
 }
 
 int vfp_set_flow_planar(vfp_ctx* c, const double* u, const double* dudx, const double* dudt,
@@ -887,7 +986,7 @@ int vfp_set_flow_planar(vfp_ctx* c, const double* u, const double* dudx, const d
   if (int e = upload_vec(c->d_du_vol, c->du_vol)) return e;
   if (int e = upload_vec(c->d_a_vol, c->a_vol)) return e;
   if (int e = upload_vec(c->d_u_face, c->u_face)) return e;
-  return refresh(c);
+  return refresh(c, R_PFACE | R_REC);
 }
 
 int vfp_set_magnetic_uniform(vfp_ctx* c, const double* B) {
@@ -895,7 +994,7 @@ int vfp_set_magnetic_uniform(vfp_ctx* c, const double* B) {
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
   for (int i = 0; i < 3; ++i) c->B[i] = B[i];
   c->have_Bpts = false;
-  return refresh(c);
+  return refresh(c, R_TAB);
 }
 
 int vfp_set_magnetic_points(vfp_ctx* c, const double* B) {
@@ -905,7 +1004,7 @@ int vfp_set_magnetic_points(vfp_ctx* c, const double* B) {
   if (int e = upload(c->d_Bpts, B, (size_t)c->ncells * c->nb * 3 * sizeof(double))) return e;
   c->have_Bpts = true;
   for (int i = 0; i < 3; ++i) c->B[i] = 0.0;
-  return refresh(c);
+  return refresh(c, R_TAB);
 }
 
 int vfp_set_scattering(vfp_ctx* c, double nu, const double* nu_cell) {
@@ -933,7 +1032,7 @@ int vfp_set_scattering(vfp_ctx* c, double nu, const double* nu_cell) {
     c->fld.nu_cell = c->have_nu_cell ? c->d_nu.as<double>() : nullptr;
     return VFP_OK;
   }
-  return refresh(c);
+  return refresh(c, 0);
 }
 
 int vfp_set_source_points(vfp_ctx* c, const double* s) {
@@ -964,7 +1063,7 @@ int vfp_set_source_points(vfp_ctx* c, const double* s) {
   }
   if (int e = upload_vec(c->d_src, out)) return e;
   c->have_src = true;
-  return refresh(c);
+  return refresh(c, 0);
 }
 
 int vfp_ndofs(const vfp_ctx* c, int64_t* n) {
@@ -1000,6 +1099,17 @@ int vfp_cfl_dt(const vfp_ctx* c, double courant, double* dt) {
   return VFP_OK;
 }
 
+// c_s dt of stage s (Horner form, c = 1/4, 1/3, 1/2, 1), rounded the same way
+// by every caller so that all stepping paths agree bit for bit.
+static double stage_cdt(int s, double dt) {
+  switch (s) {
+    case 0: return 0.25 * dt;
+    case 1: return dt / 3.0;
+    case 2: return 0.5 * dt;
+    default: return dt;
+  }
+}
+
 static int launch(vfp_ctx* c, const double* w_in, const double* u, double* w_out, double alpha, double beta,
                   int with_source, void* stream) {
   KernelArgs a{};
@@ -1012,6 +1122,7 @@ static int launch(vfp_ctx* c, const double* w_in, const double* u, double* w_out
   a.st.alpha = alpha;
   a.st.beta = beta;
   a.st.with_source = with_source && (c->terms & VFP_TERM_SOURCE);
+  a.tile_map = c->tile_map;
   c->launcher(a, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return VFP_OK;
@@ -1043,10 +1154,10 @@ int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, 
   if ((u >= work && u < work + 2 * N) || (work >= u && work < u + N))
     return fail(VFP_EINVAL, "work overlaps u");
   for (int64_t s = 0; s < nsteps; ++s) {
-    if (int e = launch(c, u, u, wa, 1.0, 0.25 * dt, 1, stream)) return e;
-    if (int e = launch(c, wa, u, wb, 1.0, dt / 3.0, 1, stream)) return e;
-    if (int e = launch(c, wb, u, wa, 1.0, 0.5 * dt, 1, stream)) return e;
-    if (int e = launch(c, wa, u, u, 1.0, dt, 1, stream)) return e;
+    if (int e = launch(c, u, u, wa, 1.0, stage_cdt(0, dt), 1, stream)) return e;
+    if (int e = launch(c, wa, u, wb, 1.0, stage_cdt(1, dt), 1, stream)) return e;
+    if (int e = launch(c, wb, u, wa, 1.0, stage_cdt(2, dt), 1, stream)) return e;
+    if (int e = launch(c, wa, u, u, 1.0, stage_cdt(3, dt), 1, stream)) return e;
   }
   return VFP_OK;
 }
@@ -1074,6 +1185,7 @@ static int launch_adj(vfp_ctx* c, const double* mu_in, const double* acc_in, dou
   a.adj.fwd = fwd;
   a.adj.grad_nu = grad_nu;
   a.adj.mass_out = mass_out;
+  a.tile_map = c->tile_map;
   c->adj_launcher(a, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return VFP_OK;
@@ -1141,10 +1253,10 @@ int vfp_advance_tape(vfp_ctx* c, const double* u0, double dt, int64_t nsteps, do
   for (int64_t s = 0; s < nsteps; ++s) {
     const double* un = s == 0 ? u0 : tape + (4 * s - 1) * N;
     double* w = tape + 4 * s * N;
-    if (int e = launch(c, un, un, w, 1.0, 0.25 * dt, 1, stream)) return e;
-    if (int e = launch(c, w, un, w + N, 1.0, dt / 3.0, 1, stream)) return e;
-    if (int e = launch(c, w + N, un, w + 2 * N, 1.0, 0.5 * dt, 1, stream)) return e;
-    if (int e = launch(c, w + 2 * N, un, w + 3 * N, 1.0, dt, 1, stream)) return e;
+    if (int e = launch(c, un, un, w, 1.0, stage_cdt(0, dt), 1, stream)) return e;
+    if (int e = launch(c, w, un, w + N, 1.0, stage_cdt(1, dt), 1, stream)) return e;
+    if (int e = launch(c, w + N, un, w + 2 * N, 1.0, stage_cdt(2, dt), 1, stream)) return e;
+    if (int e = launch(c, w + 2 * N, un, w + 3 * N, 1.0, stage_cdt(3, dt), 1, stream)) return e;
   }
   return VFP_OK;
 }
@@ -1171,10 +1283,10 @@ int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double d
     const double* f2 = grad_nu ? w + N : nullptr;
     const double* f1 = grad_nu ? w : nullptr;
     const double* f0 = grad_nu ? un : nullptr;
-    if (int e = launch_adj(c, mu, mu, acc, 1.0, dt, b1, f3, grad_nu, 0, stream)) return e;
-    if (int e = launch_adj(c, b1, acc, acc, 1.0, 0.5 * dt, b2, f2, grad_nu, 0, stream)) return e;
-    if (int e = launch_adj(c, b2, acc, acc, 1.0, dt / 3.0, b1, f1, grad_nu, 0, stream)) return e;
-    if (int e = launch_adj(c, b1, acc, mu, 1.0, 0.25 * dt, nullptr, f0, grad_nu, 0, stream)) return e;
+    if (int e = launch_adj(c, mu, mu, acc, 1.0, stage_cdt(3, dt), b1, f3, grad_nu, 0, stream)) return e;
+    if (int e = launch_adj(c, b1, acc, acc, 1.0, stage_cdt(2, dt), b2, f2, grad_nu, 0, stream)) return e;
+    if (int e = launch_adj(c, b2, acc, acc, 1.0, stage_cdt(1, dt), b1, f1, grad_nu, 0, stream)) return e;
+    if (int e = launch_adj(c, b1, acc, mu, 1.0, stage_cdt(0, dt), nullptr, f0, grad_nu, 0, stream)) return e;
   }
   return VFP_OK;
 }
@@ -1218,6 +1330,319 @@ int vfp_adjoint_checkpointed(vfp_ctx* c, const double* ckpt, double dt, int64_t 
     if (int e = vfp_adjoint_steps(c, u0, tape, dt, cnt, lam, grad_nu, work, stream)) return e;
   }
   return launch_mass(c, lam, lam, false, stream);
+}
+
+}  // extern "C"
+
+// ================================================================= batches
+
+struct vfp_batch {
+  struct Class {
+    int k = 0, lmax = 0, nrot = 0;
+    bool batched = false;              // one launch per stage for all members
+    std::vector<int> members;
+    BatchKernel bk;
+    DevBuf descs;                      // [stage][member] KernelArgs
+    DevBuf start;                      // members + 1 tile offsets
+    int total = 0;                     // tiles = workgroups per launch
+    int tile_map = 0;                  // tuned
+  };
+  std::vector<vfp_ctx*> runs;
+  std::vector<Class> classes;
+  std::vector<double*> u, work;
+  std::vector<double> dt;
+  bool bound = false;
+  bool use_graph = false;
+  int device = -1;
+  hipStream_t stream = nullptr;        // private stream (default priority) for graphs
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~vfp_batch() { drop_graph(); if (ev_in) (void)hipEventDestroy(ev_in); if (ev_out) (void)hipEventDestroy(ev_out);
+                 if (stream) (void)hipStreamDestroy(stream); }
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+  }
+};
+
+namespace {
+
+// Stage s of a step (Horner form): (w_in, w_out, c_s dt) with u the step base.
+void stage_ptrs(int s, double* u, double* work, int64_t N, double dt, const double*& w_in, double*& w_out,
+                double& cdt) {
+  double* wa = work;
+  double* wb = work + N;
+  cdt = stage_cdt(s, dt);
+  switch (s) {
+    case 0: w_in = u; w_out = wa; break;
+    case 1: w_in = wa; w_out = wb; break;
+    case 2: w_in = wb; w_out = wa; break;
+    default: w_in = wa; w_out = u; break;
+  }
+}
+
+KernelArgs stage_args(vfp_ctx* c, const double* w_in, const double* u, double* w_out, double beta) {
+  KernelArgs a{};
+  a.mesh = c->meshargs;
+  a.fld = c->fld;
+  a.tab = c->tab;
+  a.st.w_in = w_in;
+  a.st.u = u;
+  a.st.w_out = w_out;
+  a.st.alpha = 1.0;
+  a.st.beta = beta;
+  a.st.with_source = (c->terms & VFP_TERM_SOURCE) ? 1 : 0;
+  a.tile_map = c->tile_map;
+  return a;
+}
+
+int batch_launch_stage(vfp_batch* b, vfp_batch::Class& cl, int s, hipStream_t st) {
+  if (cl.batched) {
+    BatchArgs ba;
+    ba.descs = cl.descs.as<KernelArgs>() + (size_t)s * cl.members.size();
+    ba.start = cl.start.as<int>();
+    ba.nruns = (int)cl.members.size();
+    ba.total = cl.total;
+    ba.tile_map = cl.tile_map;
+    cl.bk.launch(ba, st);
+  } else {
+    for (int r : cl.members) {
+      vfp_ctx* c = b->runs[r];
+      int64_t N = 0;
+      vfp_ndofs(c, &N);
+      const double* w_in;
+      double* w_out;
+      double cdt;
+      stage_ptrs(s, b->u[r], b->work[r], N, b->dt[r], w_in, w_out, cdt);
+      KernelArgs a = stage_args(c, w_in, b->u[r], w_out, cdt);
+      c->launcher(a, st);
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  return VFP_OK;
+}
+
+int batch_step(vfp_batch* b, hipStream_t st) {
+  for (int s = 0; s < 4; ++s)
+    for (auto& cl : b->classes)
+      if (int e = batch_launch_stage(b, cl, s, st)) return e;
+  return VFP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vfp_batch_create(vfp_batch** out, vfp_ctx* const* runs, int nruns, unsigned flags) {
+  if (!out) return fail(VFP_EINVAL, "out is null");
+  *out = nullptr;
+  if (!runs || nruns < 1) return fail(VFP_EINVAL, "need at least one run");
+  if (flags & ~1u) return fail(VFP_EINVAL, "unknown batch flags 0x%x", flags);
+  vfp_batch* b = new (std::nothrow) vfp_batch;
+  if (!b) return fail(VFP_ENOMEM, "batch");
+  b->use_graph = flags & VFP_BATCH_GRAPH;
+  for (int i = 0; i < nruns; ++i) {
+    if (int e = check_ready(runs[i])) {
+      delete b;
+      return fail(e, "run %d: %s", i, g_err.c_str());
+    }
+    if (b->device < 0) b->device = runs[i]->device;
+    if (runs[i]->device != b->device) {
+      delete b;
+      return fail(VFP_EINVAL, "run %d lives on device %d, not %d", i, runs[i]->device, b->device);
+    }
+    for (int j = 0; j < i; ++j)
+      if (runs[j] == runs[i]) {
+        delete b;
+        return fail(VFP_EINVAL, "run %d repeats run %d", i, j);
+      }
+    b->runs.push_back(runs[i]);
+  }
+  for (int i = 0; i < nruns; ++i) {
+    vfp_ctx* c = runs[i];
+    const int nrot = c->tab.nrot;
+    const bool batched = c->shock;
+    vfp_batch::Class* cl = nullptr;
+    for (auto& x : b->classes)
+      if (x.batched == batched && x.k == c->k && x.lmax == c->lmax && x.nrot == nrot) cl = &x;
+    if (!cl) {
+      b->classes.emplace_back();
+      cl = &b->classes.back();
+      cl->k = c->k;
+      cl->lmax = c->lmax;
+      cl->nrot = nrot;
+      cl->batched = batched;
+      if (batched) {
+        cl->bk = find_shock_batch_kernel(c->k, c->lmax, nrot);
+        if (!cl->bk.launch) {
+          delete b;
+          return fail(VFP_EUNSUPPORTED, "no batched kernel for k=%d lmax=%d", c->k, c->lmax);
+        }
+      }
+    }
+    cl->members.push_back(i);
+  }
+  for (auto& cl : b->classes) {
+    if (!cl.batched) continue;
+    std::vector<int> st(cl.members.size() + 1, 0);
+    long long tot = 0;
+    for (size_t j = 0; j < cl.members.size(); ++j) {
+      st[j] = (int)tot;
+      tot += (runs[cl.members[j]]->ncells + cl.bk.cells_per_tile - 1) / cl.bk.cells_per_tile;
+      if (tot > (1LL << 30)) {
+        delete b;
+        return fail(VFP_EINVAL, "batch too large (%lld tiles)", tot);
+      }
+    }
+    st.back() = (int)tot;
+    cl.total = (int)tot;
+    if (int e = upload_vec(cl.start, st)) {
+      delete b;
+      return e;
+    }
+  }
+  *out = b;
+  return VFP_OK;
+}
+
+void vfp_batch_destroy(vfp_batch* b) { delete b; }
+
+int vfp_batch_bind(vfp_batch* b, double* const* u, double* const* work, const double* dt) {
+  if (!b || !u || !work || !dt) return fail(VFP_EINVAL, "null argument");
+  const int nr = (int)b->runs.size();
+  for (int r = 0; r < nr; ++r) {
+    if (!u[r] || !work[r]) return fail(VFP_EINVAL, "run %d: null buffer", r);
+    if (!std::isfinite(dt[r])) return fail(VFP_EINVAL, "run %d: dt not finite", r);
+    int64_t N = 0;
+    vfp_ndofs(b->runs[r], &N);
+    if (overlaps(u[r], N, work[r], 2 * N)) return fail(VFP_EINVAL, "run %d: work overlaps u", r);
+  }
+  b->u.assign(u, u + nr);
+  b->work.assign(work, work + nr);
+  b->dt.assign(dt, dt + nr);
+  for (auto& cl : b->classes) {
+    if (!cl.batched) continue;
+    const size_t m = cl.members.size();
+    std::vector<KernelArgs> d(4 * m);
+    for (int s = 0; s < 4; ++s)
+      for (size_t j = 0; j < m; ++j) {
+        const int r = cl.members[j];
+        vfp_ctx* c = b->runs[r];
+        int64_t N = 0;
+        vfp_ndofs(c, &N);
+        const double* w_in;
+        double* w_out;
+        double cdt;
+        stage_ptrs(s, b->u[r], b->work[r], N, b->dt[r], w_in, w_out, cdt);
+        d[s * m + j] = stage_args(c, w_in, b->u[r], w_out, cdt);
+      }
+    if (int e = upload_vec(cl.descs, d)) return e;
+  }
+  b->drop_graph();
+  b->bound = true;
+  return VFP_OK;
+}
+
+int vfp_batch_advance(vfp_batch* b, int64_t nsteps, void* stream) {
+  if (!b) return fail(VFP_EINVAL, "null batch");
+  if (!b->bound) return fail(VFP_ESTATE, "vfp_batch_bind has not been called");
+  if (nsteps < 0) return fail(VFP_EINVAL, "nsteps < 0");
+  hipStream_t st = (hipStream_t)stream;
+  if (!b->use_graph) {
+    for (int64_t i = 0; i < nsteps; ++i)
+      if (int e = batch_step(b, st)) return e;
+    return VFP_OK;
+  }
+  if (!b->stream) {
+    HIP_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+  }
+  if (!b->exec) {
+    HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    int e = batch_step(b, b->stream);
+    hipGraph_t g = nullptr;
+    hipError_t ce = hipStreamEndCapture(b->stream, &g);
+    if (e) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    if (ce != hipSuccess) return fail(VFP_EDEVICE, "graph capture: %s", hipGetErrorString(ce));
+    b->graph = g;
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  }
+  // order after the caller's stream, replay, and order the caller after us
+  HIP_TRY(hipEventRecord(b->ev_in, st));
+  HIP_TRY(hipStreamWaitEvent(b->stream, b->ev_in, 0));
+  for (int64_t i = 0; i < nsteps; ++i) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+  HIP_TRY(hipEventRecord(b->ev_out, b->stream));
+  HIP_TRY(hipStreamWaitEvent(st, b->ev_out, 0));
+  return VFP_OK;
+}
+
+static int tune_class(vfp_batch* b, vfp_batch::Class& cl, int reps, hipStream_t st, hipEvent_t e0,
+                      hipEvent_t e1) {
+  float best = 1e30f;
+  int bt = cl.tile_map;
+  for (int tm : {0, 1}) {
+    cl.tile_map = tm;
+    // stage 1 form (reads u, writes the first work vector): u is untouched
+    if (int e = batch_launch_stage(b, cl, 0, st)) return e;
+    HIP_TRY(hipEventRecord(e0, st));
+    for (int i = 0; i < reps; ++i)
+      if (int e = batch_launch_stage(b, cl, 0, st)) return e;
+    HIP_TRY(hipEventRecord(e1, st));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      bt = tm;
+    }
+  }
+  cl.tile_map = bt;
+  return VFP_OK;
+}
+
+int vfp_batch_autotune(vfp_batch* b, int reps, void* stream) {
+  if (!b) return fail(VFP_EINVAL, "null batch");
+  if (!b->bound) return fail(VFP_ESTATE, "vfp_batch_bind has not been called");
+  if (reps < 1) reps = 3;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(VFP_EDEVICE, "hipEventCreate");
+  }
+  int rc = VFP_OK;
+  for (auto& cl : b->classes) {
+    if (!cl.batched) continue;
+    if ((rc = tune_class(b, cl, reps, (hipStream_t)stream, e0, e1))) break;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  b->drop_graph();
+  return rc;
+}
+
+int vfp_batch_nclasses(const vfp_batch* b) { return b ? (int)b->classes.size() : 0; }
+
+int vfp_batch_class_info(const vfp_batch* b, int i, int* info) {
+  if (!b || !info) return fail(VFP_EINVAL, "null argument");
+  if (i < 0 || i >= (int)b->classes.size()) return fail(VFP_EINVAL, "class %d", i);
+  const auto& cl = b->classes[i];
+  info[0] = cl.k;
+  info[1] = cl.lmax;
+  info[2] = cl.nrot;
+  info[3] = (int)cl.members.size();
+  info[4] = cl.batched ? 1 : 0;
+  info[5] = cl.total;
+  info[6] = cl.total;
+  info[7] = cl.tile_map;
+  return VFP_OK;
 }
 
 }  // extern "C"

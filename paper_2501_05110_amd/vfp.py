@@ -67,6 +67,13 @@ def load(path: str = None):
         "vfp_adjoint_steps": (I, [P, P, P, D, L, P, P, P, P]),
         "vfp_forward_checkpoints": (I, [P, P, D, L, L, P, P, P]),
         "vfp_adjoint_checkpointed": (I, [P, P, D, L, L, P, P, P, P, P]),
+        "vfp_batch_create": (I, [C.POINTER(P), C.POINTER(P), I, U]),
+        "vfp_batch_destroy": (None, [P]),
+        "vfp_batch_bind": (I, [P, C.POINTER(P), C.POINTER(P), dp]),
+        "vfp_batch_advance": (I, [P, L, P]),
+        "vfp_batch_autotune": (I, [P, I, P]),
+        "vfp_batch_nclasses": (I, [P]),
+        "vfp_batch_class_info": (I, [P, I, C.POINTER(I)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -82,7 +89,9 @@ def exported_symbols():
             "vfp_set_magnetic_uniform", "vfp_set_magnetic_points", "vfp_set_scattering",
             "vfp_set_source_points", "vfp_ndofs", "vfp_cfl_dt", "vfp_apply", "vfp_stage",
             "vfp_advance", "vfp_mass", "vfp_apply_adjoint", "vfp_adjoint_stage", "vfp_advance_tape",
-            "vfp_adjoint_steps", "vfp_forward_checkpoints", "vfp_adjoint_checkpointed"]
+            "vfp_adjoint_steps", "vfp_forward_checkpoints", "vfp_adjoint_checkpointed",
+            "vfp_batch_create", "vfp_batch_destroy", "vfp_batch_bind", "vfp_batch_advance",
+            "vfp_batch_autotune", "vfp_batch_nclasses", "vfp_batch_class_info"]
 
 
 def _check(rc):
@@ -291,6 +300,53 @@ class Operator:
         if self._ctx:
             _lib.vfp_destroy(self._ctx)
             self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many runs advanced together (vfp_batch_*): one launch per stage and
+    (k, l_max) class walks the tiles of all runs of that class."""
+
+    def __init__(self, ops, graph=True):
+        lib = load()
+        self.ops = list(ops)
+        arr = (C.c_void_p * len(self.ops))(*[op._ctx.value for op in self.ops])
+        self._b = C.c_void_p()
+        _check(lib.vfp_batch_create(C.byref(self._b), arr, len(self.ops), 1 if graph else 0))
+
+    def bind(self, u, work, dt):
+        """u[r], work[r]: float64 CUDA tensors (ndofs, 2 ndofs); dt[r]."""
+        n = len(self.ops)
+        up = (C.c_void_p * n)(*[op._t(x, "u").value for op, x in zip(self.ops, u)])
+        wp = (C.c_void_p * n)(*[op._t(x, "work", 2 * op.ndofs).value for op, x in zip(self.ops, work)])
+        dts = _f64([float(d) for d in dt])
+        self._keep = (list(u), list(work))
+        _check(_lib.vfp_batch_bind(self._b, up, wp, _dptr(dts)))
+
+    def advance(self, nsteps, stream=None):
+        _check(_lib.vfp_batch_advance(self._b, int(nsteps), _stream_handle(stream)))
+
+    def autotune(self, reps=3, stream=None):
+        _check(_lib.vfp_batch_autotune(self._b, int(reps), _stream_handle(stream)))
+
+    def classes(self):
+        out = []
+        for i in range(_lib.vfp_batch_nclasses(self._b)):
+            info = (C.c_int * 8)()
+            _check(_lib.vfp_batch_class_info(self._b, i, info))
+            out.append(dict(zip(("k", "lmax", "nrot", "runs", "batched", "tiles", "grid", "tile_map"),
+                                list(info))))
+        return out
+
+    def close(self):
+        if self._b:
+            _lib.vfp_batch_destroy(self._b)
+            self._b = C.c_void_p()
 
     def __del__(self):
         try:

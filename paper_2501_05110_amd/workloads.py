@@ -245,7 +245,7 @@ def config1(ncells=64):
 
 def shock_workload(name, nx, np_, k, lmax, U0=0.1, r=4.0, L=10.0, w_frac=0.01,
                    nu0=1.0, lnp=(0.0, 10.0), seed=2, steps=2000, Q=0.1,
-                   lnp_inj=0.5, sigma_lnp=1.0 / 8):
+                   lnp_inj=0.5, sigma_lnp=1.0 / 8, init=True):
     w = w_frac * L
     xn = uniform_nodes(-L, L, nx)
     pn = uniform_nodes(lnp[0], lnp[1], np_)
@@ -259,7 +259,8 @@ def shock_workload(name, nx, np_, k, lmax, U0=0.1, r=4.0, L=10.0, w_frac=0.01,
         nu=nu_cell, source=gaussian_source(Q, 0.0, lnp_inj, w, sigma_lnp),
         steps=steps,
         meta={"U0": U0, "r": r, "w": w, "L": L, "nu0": nu0})
-    wl.meta["init"] = random_state(wl, SEED_BASE + seed, 1e-3)
+    if init:
+        wl.meta["init"] = random_state(wl, SEED_BASE + seed, 1e-3)
     return wl
 
 
@@ -291,6 +292,24 @@ def config3(ncell=48, steps=500, lmax=5, k=2):
     wl.meta["init_func"] = f0
     wl.meta["B_field"] = B
     return wl
+
+
+# C4: a batch of independent shock runs of mixed sizes and orders; the
+# states are not generated here (about 2e9 DoF in total): callers draw them
+# on the device.
+def config4(nruns=256, steps=100, seed=4):
+    g = np.random.default_rng(SEED_BASE + seed)
+    runs = []
+    for i in range(nruns):
+        nx = int(g.integers(128, 1025))
+        np_ = int(g.integers(32, 129))
+        k = int(g.integers(1, 3))
+        lmax = int(g.choice([1, 3, 5, 7]))
+        r = float(g.uniform(2.0, 4.0))
+        nu0 = float(np.exp(g.uniform(np.log(0.1), np.log(10.0))))
+        runs.append(shock_workload(f"batch_{i}_{nx}x{np_}_k{k}_lmax{lmax}", nx, np_, k, lmax, r=r,
+                                   nu0=nu0, seed=seed, steps=steps, init=False))
+    return runs
 
 
 # C5: adjoint case, C2 physics on 512 x 64 cells

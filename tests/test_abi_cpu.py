@@ -69,6 +69,16 @@ def test_calls_out_of_order(lib):
     assert lib.vfp_adjoint_steps(ctx, None, None, 0.1, 1, None, None, None, None) == -4
     assert lib.vfp_forward_checkpoints(ctx, None, 0.1, 1, 1, None, None, None) == -4
     assert lib.vfp_adjoint_checkpointed(ctx, None, 0.1, 1, 1, None, None, None, None, None) == -4
+    # a batch needs ready contexts
+    b = C.c_void_p()
+    arr = (C.c_void_p * 1)(ctx.value)
+    assert lib.vfp_batch_create(C.byref(b), arr, 1, 0) == -4
+    assert lib.vfp_batch_create(C.byref(b), arr, 0, 0) == -1
+    assert lib.vfp_batch_create(C.byref(b), arr, 1, 8) == -1
+    assert lib.vfp_batch_create(None, arr, 1, 0) == -1
+    assert lib.vfp_batch_advance(None, 1, None) == -1
+    assert lib.vfp_batch_nclasses(None) == 0
+    lib.vfp_batch_destroy(None)
     assert lib.vfp_set_momentum(ctx, 1.0) == -1       # ln p axis: momentum is a coordinate
     lib.vfp_destroy(ctx)
     lib.vfp_destroy(None)
