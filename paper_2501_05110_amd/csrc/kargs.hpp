@@ -80,7 +80,8 @@ struct FieldArgs {
   const double* pf_tab;
   // packed per-cell-row scalars for the (x, ln p) kernel (kRec doubles each):
   // xrec[ix]: t_adv (2/h_x) U(x_q) [3], U'(x_q) [3], t_mom dU/dt(x_q) [3],
-  //           t_adv U at the lo / hi face [2], 2/h_x
+  //           t_adv U at the lo / hi face [2], 2/h_x, gradient flag
+  //           (1 if dU/dx or dU/dt is non-zero at one of its Gauss points)
   // prec[ip]: V(p_q) [3], 1/V [3], m/(gamma p) [3], t_rot q/(gamma m) [3],
   //           t_mom / V at the lo / hi face [2], 2/h_p
   const double* xrec;

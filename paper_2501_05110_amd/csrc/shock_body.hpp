@@ -34,6 +34,8 @@
 // once.  When a cell's n lanes never straddle a wavefront (n divides 64) the
 // workgroup is one wavefront and the exchanges need no workgroup barrier.
 #pragma once
+#include <type_traits>
+
 #include "basis.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -53,6 +55,7 @@ enum : int {
   X_A = 6,       // t_mom dU_x/dt                                       [3]
   X_UF = 9,      // t_adv U_x at the lo / hi x face                     [2]
   X_S2H = 11,    // 2/h_x
+  X_GRAD = 12,   // 1 if dU_x/dx or dU_x/dt is non-zero at a Gauss point of the cell
   P_V = 16,      // V at the p Gauss points                             [3]
   P_IV = 19,     // 1/V                                                 [3]
   P_ID = 22,     // m/(gamma p)                                         [3]
@@ -270,6 +273,16 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
     cell_sync<N>();
   }
 
+  // Where the flow has no gradient (dU/dx = dU/dt = 0 at every Gauss point of
+  // the x cell) beta^{ln p} vanishes and so do all momentum terms: the p-face
+  // flux is zero and the volume drops those terms (exactly: they are products
+  // with zero).  The test is uniform over the workgroup (the records of all
+  // its cells are in LDS after the x faces), so every barrier below is taken
+  // by all lanes alike.
+  bool grad = false;
+#pragma unroll
+  for (int c2 = 0; c2 < CPB; ++c2) grad |= shs[c2 * S_STRIDE + X_GRAD] != 0.0;
+
   // ---- ln p faces: beta^{ln p} = a1 A^x + a2 (A^x A^x)_t per point ---------
   const int axc0 = gp(T.ax_col)[r], axc1 = gp(T.ax_col)[N + r];
   const double axv0 = gp(T.ax_val)[r], axv1 = gp(T.ax_val)[N + r];
@@ -277,6 +290,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   const double axxv0 = gp(T.axx_val)[r], axxv1 = gp(T.axx_val)[N + r], axxv2 = gp(T.axx_val)[2 * N + r];
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
+    if (!grad) break;
     double own[K1], oth[K1];
     const int bc = side ? M.bc_hi[1] : M.bc_lo[1];
 #pragma unroll
@@ -380,67 +394,79 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
         for (int j0 = 0; j0 < K1; ++j0) acc = fma(CB::phi[q0][j0], w[j0 + K1 * j1], acc);
         t[q0 + K1 * j1] = acc;
       }
+    // GR = false: no flow gradient in the workgroup (the momentum terms and
+    // the divergence term are zero)
+    auto rows = [&](auto gtag) {
+      constexpr bool GR = decltype(gtag)::value;
 #pragma unroll
-    for (int q1 = 0; q1 < K1; ++q1) {
-      if (in_grp) {
+      for (int q1 = 0; q1 < K1; ++q1) {
+        if (in_grp) {
+#pragma unroll
+          for (int q0 = 0; q0 < K1; ++q0) {
+            double acc = 0.0;
+#pragma unroll
+            for (int j1 = 0; j1 < K1; ++j1)
+              if (CB::phi[q1][j1] != 0.0) acc = fma(CB::phi[q1][j1], t[q0 + K1 * j1], acc);
+            X[q0 * N + r] = acc;
+          }
+        }
+        cell_sync<N>();
+        const double pV = tas2hx * sc[P_V + q1];
+        const double piV = sc[P_IV + q1];
+        const double pid = sc[P_ID + q1];
+        const double pig = sc[P_IG + q1];
+        double ac[K1], bc[K1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i) ac[i] = bc[i] = 0.0;
 #pragma unroll
         for (int q0 = 0; q0 < K1; ++q0) {
-          double acc = 0.0;
+          const double U = sc[X_U + q0];
+          const double* P = X + q0 * N;
+          const double f = P[r];
+          const double fxp = P[axc0], fxm = P[axc1];
+          double Rf = 0.0;
 #pragma unroll
-          for (int j1 = 0; j1 < K1; ++j1)
-            if (CB::phi[q1][j1] != 0.0) acc = fma(CB::phi[q1][j1], t[q0 + K1 * j1], acc);
-          X[q0 * N + r] = acc;
+          for (int s = 0; s < NROT; ++s) Rf = fma(rv[s], P[rc[s]], Rf);
+          const double Axf = fma(axv0, fxp, axv1 * fxm);
+          const double Xf = fma(U, f, pV * Axf);
+          double G = 0.0, Pp = 0.0;
+          if constexpr (GR) {
+            const double dU = sc[X_DU + q0];
+            const double a = sc[X_A + q0];
+            const double fpp = P[axxc0], fmm = P[axxc1];
+            const double G1f = fma(g1v0, fxp, g1v1 * fxm);
+            const double A2f = fma(axxv0, fpp, fma(axxv1, f, axxv2 * fmm));
+            const double G2f = fma(g2v0, fpp, fma(g2v1, f, g2v2 * fmm));
+            const double aiV = a * piV;
+            Pp = mom_s2hp * fma(aiV, Axf, dU * A2f);
+            G = fma(aiV, G1f, dU * fma(t_mom, G2f, -t_adv * f));
+            G = fma(-a * pid, Axf, G);
+          }
+          G = fma(-pig, Rf, G);
+          G = fma(nuc, f, G);
+#pragma unroll
+          for (int i = 0; i < K1; ++i) {
+            if (CB::tst[i][q0] != 0.0) ac[i] = fma(-CB::tst[i][q0], G, ac[i]);
+            if (CB::dtst[i][q0] != 0.0) ac[i] = fma(CB::dtst[i][q0], Xf, ac[i]);
+            if constexpr (GR)
+              if (CB::tst[i][q0] != 0.0) bc[i] = fma(CB::tst[i][q0], Pp, bc[i]);
+          }
         }
+#pragma unroll
+        for (int i1 = 0; i1 < K1; ++i1)
+#pragma unroll
+          for (int i0 = 0; i0 < K1; ++i0) {
+            double v = res[i0 + K1 * i1];
+            if (CB::tst[i1][q1] != 0.0) v = fma(CB::tst[i1][q1], ac[i0], v);
+            if constexpr (GR)
+              if (CB::dtst[i1][q1] != 0.0) v = fma(CB::dtst[i1][q1], bc[i0], v);
+            res[i0 + K1 * i1] = v;
+          }
+        cell_sync<N>();
       }
-      cell_sync<N>();
-      const double pV = tas2hx * sc[P_V + q1];
-      const double piV = sc[P_IV + q1];
-      const double pid = sc[P_ID + q1];
-      const double pig = sc[P_IG + q1];
-      double ac[K1], bc[K1];
-#pragma unroll
-      for (int i = 0; i < K1; ++i) ac[i] = bc[i] = 0.0;
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        const double U = sc[X_U + q0];
-        const double dU = sc[X_DU + q0];
-        const double a = sc[X_A + q0];
-        const double* P = X + q0 * N;
-        const double f = P[r];
-        const double fxp = P[axc0], fxm = P[axc1];
-        const double fpp = P[axxc0], fmm = P[axxc1];
-        double Rf = 0.0;
-#pragma unroll
-        for (int s = 0; s < NROT; ++s) Rf = fma(rv[s], P[rc[s]], Rf);
-        const double Axf = fma(axv0, fxp, axv1 * fxm);
-        const double G1f = fma(g1v0, fxp, g1v1 * fxm);
-        const double A2f = fma(axxv0, fpp, fma(axxv1, f, axxv2 * fmm));
-        const double G2f = fma(g2v0, fpp, fma(g2v1, f, g2v2 * fmm));
-        const double aiV = a * piV;
-        const double Xf = fma(U, f, pV * Axf);
-        const double Pp = mom_s2hp * fma(aiV, Axf, dU * A2f);
-        double G = fma(aiV, G1f, dU * fma(t_mom, G2f, -t_adv * f));
-        G = fma(-a * pid, Axf, G);
-        G = fma(-pig, Rf, G);
-        G = fma(nuc, f, G);
-#pragma unroll
-        for (int i = 0; i < K1; ++i) {
-          if (CB::tst[i][q0] != 0.0) ac[i] = fma(-CB::tst[i][q0], G, ac[i]);
-          if (CB::dtst[i][q0] != 0.0) ac[i] = fma(CB::dtst[i][q0], Xf, ac[i]);
-          if (CB::tst[i][q0] != 0.0) bc[i] = fma(CB::tst[i][q0], Pp, bc[i]);
-        }
-      }
-#pragma unroll
-      for (int i1 = 0; i1 < K1; ++i1)
-#pragma unroll
-        for (int i0 = 0; i0 < K1; ++i0) {
-          double v = res[i0 + K1 * i1];
-          if (CB::tst[i1][q1] != 0.0) v = fma(CB::tst[i1][q1], ac[i0], v);
-          if (CB::dtst[i1][q1] != 0.0) v = fma(CB::dtst[i1][q1], bc[i0], v);
-          res[i0 + K1 * i1] = v;
-        }
-      cell_sync<N>();
-    }
+    };
+    if (grad) rows(std::true_type{});
+    else rows(std::false_type{});
   } else {
     const double g1t0 = gp(T.g1t_val)[r], g1t1 = gp(T.g1t_val)[N + r];
     const double g2t0 = gp(T.g2t_val)[r], g2t1 = gp(T.g2t_val)[N + r], g2t2 = gp(T.g2t_val)[2 * N + r];
@@ -470,72 +496,81 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
         t[q0 + K1 * j1] = a;
         tx[q0 + K1 * j1] = d;
       }
+    auto rows = [&](auto gtag) {
+      constexpr bool GR = decltype(gtag)::value;
 #pragma unroll
-    for (int q1 = 0; q1 < K1; ++q1) {
-      if (in_grp) {
+      for (int q1 = 0; q1 < K1; ++q1) {
+        if (in_grp) {
+#pragma unroll
+          for (int q0 = 0; q0 < K1; ++q0) {
+            double f = 0.0, dx = 0.0, dp = 0.0;
+#pragma unroll
+            for (int j1 = 0; j1 < K1; ++j1) {
+              if (CB::phi[q1][j1] != 0.0) {
+                f = fma(CB::phi[q1][j1], t[q0 + K1 * j1], f);
+                dx = fma(CB::phi[q1][j1], tx[q0 + K1 * j1], dx);
+              }
+              if constexpr (GR)
+                if (CB::dphi[q1][j1] != 0.0) dp = fma(CB::dphi[q1][j1], t[q0 + K1 * j1], dp);
+            }
+            X[q0 * N + r] = f;
+            X[(K1 + q0) * N + r] = dx;
+            if constexpr (GR) X[(2 * K1 + q0) * N + r] = dp;
+          }
+        }
+        cell_sync<N>();
+        const double pV = tas2hx * sc[P_V + q1];
+        const double piV = sc[P_IV + q1];
+        const double pid = sc[P_ID + q1];
+        const double pig = sc[P_IG + q1];
+        double ac[K1];
+#pragma unroll
+        for (int i = 0; i < K1; ++i) ac[i] = 0.0;
 #pragma unroll
         for (int q0 = 0; q0 < K1; ++q0) {
-          double f = 0.0, dx = 0.0, dp = 0.0;
+          const double U = sc[X_U + q0];
+          const double* P = X + q0 * N;
+          const double* Qx = X + (K1 + q0) * N;
+          const double f = P[r];
+          double Rf = 0.0;
 #pragma unroll
-          for (int j1 = 0; j1 < K1; ++j1) {
-            if (CB::phi[q1][j1] != 0.0) {
-              f = fma(CB::phi[q1][j1], t[q0 + K1 * j1], f);
-              dx = fma(CB::phi[q1][j1], tx[q0 + K1 * j1], dx);
-            }
-            if (CB::dphi[q1][j1] != 0.0) dp = fma(CB::dphi[q1][j1], t[q0 + K1 * j1], dp);
+          for (int s = 0; s < NROT; ++s) Rf = fma(rv[s], P[rc[s]], Rf);
+          double G = 0.0, Pa = 0.0;
+          if constexpr (GR) {
+            const double dU = sc[X_DU + q0];
+            const double a = sc[X_A + q0];
+            const double* Qp = X + (2 * K1 + q0) * N;
+            const double fxp = P[axc0], fxm = P[axc1];
+            const double fpp = P[axxc0], fmm = P[axxc1];
+            const double Axf = fma(axv0, fxp, axv1 * fxm);
+            const double G1t = fma(g1t0, fxp, g1t1 * fxm);
+            const double G2t = fma(g2t0, fpp, fma(g2t1, f, g2t2 * fmm));
+            const double aiV = a * piV;
+            G = fma(aiV, G1t, dU * fma(t_mom, G2t, -t_adv * f));
+            G = fma(-a * pid, Axf, G);
+            const double Axp = fma(axv0, Qp[axc0], axv1 * Qp[axc1]);
+            const double A2p = fma(axxv0, Qp[axxc0], fma(axxv1, Qp[r], axxv2 * Qp[axxc1]));
+            Pa = mom_s2hp * fma(aiV, Axp, dU * A2p);
           }
-          X[q0 * N + r] = f;
-          X[(K1 + q0) * N + r] = dx;
-          X[(2 * K1 + q0) * N + r] = dp;
+          G = fma(pig, Rf, G);                // (B.Omega)^T = -B.Omega
+          G = fma(nuc, f, G);
+          const double Axd = fma(axv0, Qx[axc0], axv1 * Qx[axc1]);
+          const double Xa = fma(U, Qx[r], pV * Axd);
+          const double h = GR ? Xa + Pa - G : Xa - G;
+#pragma unroll
+          for (int i = 0; i < K1; ++i)
+            if (CB::tst[i][q0] != 0.0) ac[i] = fma(CB::tst[i][q0], h, ac[i]);
         }
+#pragma unroll
+        for (int i1 = 0; i1 < K1; ++i1)
+#pragma unroll
+          for (int i0 = 0; i0 < K1; ++i0)
+            if (CB::tst[i1][q1] != 0.0) res[i0 + K1 * i1] = fma(CB::tst[i1][q1], ac[i0], res[i0 + K1 * i1]);
+        cell_sync<N>();
       }
-      cell_sync<N>();
-      const double pV = tas2hx * sc[P_V + q1];
-      const double piV = sc[P_IV + q1];
-      const double pid = sc[P_ID + q1];
-      const double pig = sc[P_IG + q1];
-      double ac[K1];
-#pragma unroll
-      for (int i = 0; i < K1; ++i) ac[i] = 0.0;
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        const double U = sc[X_U + q0];
-        const double dU = sc[X_DU + q0];
-        const double a = sc[X_A + q0];
-        const double* P = X + q0 * N;
-        const double* Qx = X + (K1 + q0) * N;
-        const double* Qp = X + (2 * K1 + q0) * N;
-        const double f = P[r];
-        const double fxp = P[axc0], fxm = P[axc1];
-        const double fpp = P[axxc0], fmm = P[axxc1];
-        double Rf = 0.0;
-#pragma unroll
-        for (int s = 0; s < NROT; ++s) Rf = fma(rv[s], P[rc[s]], Rf);
-        const double Axf = fma(axv0, fxp, axv1 * fxm);
-        const double G1t = fma(g1t0, fxp, g1t1 * fxm);
-        const double G2t = fma(g2t0, fpp, fma(g2t1, f, g2t2 * fmm));
-        const double aiV = a * piV;
-        double G = fma(aiV, G1t, dU * fma(t_mom, G2t, -t_adv * f));
-        G = fma(-a * pid, Axf, G);
-        G = fma(pig, Rf, G);                // (B.Omega)^T = -B.Omega
-        G = fma(nuc, f, G);
-        const double Axd = fma(axv0, Qx[axc0], axv1 * Qx[axc1]);
-        const double Xa = fma(U, Qx[r], pV * Axd);
-        const double Axp = fma(axv0, Qp[axc0], axv1 * Qp[axc1]);
-        const double A2p = fma(axxv0, Qp[axxc0], fma(axxv1, Qp[r], axxv2 * Qp[axxc1]));
-        const double Pa = mom_s2hp * fma(aiV, Axp, dU * A2p);
-        const double h = Xa + Pa - G;
-#pragma unroll
-        for (int i = 0; i < K1; ++i)
-          if (CB::tst[i][q0] != 0.0) ac[i] = fma(CB::tst[i][q0], h, ac[i]);
-      }
-#pragma unroll
-      for (int i1 = 0; i1 < K1; ++i1)
-#pragma unroll
-        for (int i0 = 0; i0 < K1; ++i0)
-          if (CB::tst[i1][q1] != 0.0) res[i0 + K1 * i1] = fma(CB::tst[i1][q1], ac[i0], res[i0 + K1 * i1]);
-      cell_sync<N>();
-    }
+    };
+    if (grad) rows(std::true_type{});
+    else rows(std::false_type{});
   }
 
   // ---- source and output ---------------------------------------------------

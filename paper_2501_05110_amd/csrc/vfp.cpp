@@ -681,6 +681,11 @@ int build_records(vfp_ctx* c) {
     x[9] = ta * c->u_face[i];
     x[10] = ta * c->u_face[i + 1];
     x[11] = s2h;
+    // flow gradient present at a Gauss point of this x cell (else every
+    // momentum and divergence term of its cells is exactly zero)
+    bool g = false;
+    for (int q = 0; q < K1; ++q) g |= c->du_vol[i * K1 + q] != 0.0 || c->a_vol[i * K1 + q] != 0.0;
+    x[12] = g ? 1.0 : 0.0;
   }
   const std::vector<double>& nd = c->nodes[pa];
   std::vector<double> g = gauss_points(c->k);
