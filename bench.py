@@ -10,11 +10,15 @@ Prints one JSON line: DoF-updates/s over the timed steps, the stage kernel's
 HBM roofline fraction (algorithmic bytes / measured launch time, against
 8 TB/s), and the CPU oracle's rate on a bounded sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-adjoint] [--copy-probe]
+  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-adjoint] [--no-batch]
+                  [--batch-full] [--copy-probe]
 
 It also reports the adjoint: a 1000-step forward run of the 512 x 64 shock
 and its checkpointed reverse pass (gradients w.r.t. the initial state and
-nu per cell), with the reverse / forward time ratio.
+nu per cell), with the reverse / forward time ratio, and the batched path:
+512 small shock runs of mixed k and l_max advanced by one launch per stage
+and class against one run per launch sequence (--batch-full: the 256 runs
+of 128-1024 x 32-128 cells).
 """
 
 from __future__ import annotations
@@ -140,6 +144,61 @@ def adjoint_timing(steps=1000):
                     "with the fused dJ/dnu accumulation; dJ/du0 and dJ/dnu (32768 cells)"}
 
 
+def batch_timing(full=False, steps=None):
+    """Many independent shock runs advanced by the batched path (one launch
+    per stage and (k, l_max) class, graph replay, autotuned tile order) and,
+    on the same GPU and buffers, one run per launch sequence.  full: the 256
+    runs of mixed size, k and l_max (about 2.3e9 DoF); else 512 small runs."""
+    import numpy as np
+    import torch
+    from paper_2501_05110_amd import vfp, workloads as W
+
+    wls = W.config4() if full else W.batch_small()
+    steps = steps or (20 if full else 50)
+    t0 = time.perf_counter()
+    ops = [vfp.Operator(wl) for wl in wls]
+    t_setup = time.perf_counter() - t0
+    N = [op.ndofs for op in ops]
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev).manual_seed(4)
+    u = [torch.randn(n, dtype=torch.float64, device=dev, generator=gen) * 1e-3 for n in N]
+    work = [torch.empty(2 * n, dtype=torch.float64, device=dev) for n in N]
+    dts = [op.cfl_dt(0.2) for op in ops]
+    b = vfp.Batch(ops, graph=True)
+    b.bind(u, work, dts)
+    b.autotune(reps=2)
+    stream = torch.cuda.current_stream()
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
+
+    b.advance(2)
+    t_b = timed(lambda: b.advance(steps))
+
+    def per_run():
+        for i, op in enumerate(ops):
+            op.advance(u[i], dts[i], steps, work[i])
+    for i, op in enumerate(ops):
+        op.advance(u[i], dts[i], 2, work[i])
+    t_s = timed(per_run)
+    for x in u:
+        if not torch.isfinite(x).all():
+            raise RuntimeError("batched state is not finite")
+    tot = sum(N)
+    cls = b.classes()
+    b.close()
+    return {"workload": "batch_256_mixed" if full else "batch_512_small", "runs": len(ops), "ndofs": tot,
+            "steps": steps, "batched_dofs_per_s": tot * steps / t_b, "per_run_dofs_per_s": tot * steps / t_s,
+            "speedup": t_s / t_b, "setup_s": t_setup,
+            "classes": [{k: c[k] for k in ("k", "lmax", "runs", "tiles", "tile_map")} for c in cls]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -147,6 +206,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-full", action="store_true",
+                    help="also time the 256 mixed runs (about 2.3e9 DoF, 52 GB; minutes of set-up)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -231,6 +293,10 @@ def main():
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
+    if not args.no_batch:
+        out["batch"] = batch_timing(full=False)
+    if args.batch_full:
+        out["batch_full"] = batch_timing(full=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -132,11 +132,12 @@ struct KernelArgs {
   int tile_map;           // 1: launch order -> tile by XCD ranges (shock kernels)
 };
 
-// Batched (x, ln p) stage: one launch walks the tiles of many runs.  Run r
+// Batched (x, ln p) stage: one launch covers the tiles of many runs.  Run r
 // owns tiles [start[r], start[r+1]); descs[r] holds its arguments.
 struct BatchArgs {
   const KernelArgs* descs;
   const int* start;       // nruns + 1 prefix sums of tiles
+  const int* tile_run;    // [total] run of each tile
   int nruns;
   int total;              // start[nruns]
   int tile_map;

@@ -12,27 +12,21 @@ using namespace shock;
 
 template <int K, int LMAX, int NROT>
 __global__ __launch_bounds__(Launch<(LMAX + 1) * (LMAX + 1)>::kThreads) __attribute__((amdgpu_waves_per_eu(VFP_SHOCK_WAVES)))
-void shock_batch_kernel(const KernelArgs* __restrict__ descs, const int* __restrict__ start, int nruns,
-                        int total, int tile_map) {
-  // descs and start are read only and alias nothing the kernel writes, so
-  // their loads (uniform addresses) stay scalar like kernel arguments
+void shock_batch_kernel(const KernelArgs* __restrict__ descs, const int* __restrict__ start,
+                        const int* __restrict__ tile_run, int total, int tile_map) {
+  // descs, start and tile_run are read only and alias nothing the kernel
+  // writes, so their loads (uniform addresses) stay scalar like kernel
+  // arguments; tile_run[t] names the run of tile t in one load
   const int t = tile_map ? xcd_tile(blockIdx.x, total) : (int)blockIdx.x;
-  // the run r with start[r] <= t < start[r + 1]
-  int lo = 0, hi = nruns;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (start[mid] <= t) lo = mid;
-    else hi = mid;
-  }
-  lo = __builtin_amdgcn_readfirstlane(lo);
-  shock_body<K, LMAX, NROT, false>(descs[lo], t - start[lo]);
+  const int run = __builtin_amdgcn_readfirstlane(tile_run[t]);
+  shock_body<K, LMAX, NROT, false>(descs[run], t - start[run]);
 }
 
 template <int K, int LMAX, int NROT>
 void launch_batch_t(const BatchArgs& b, hipStream_t s) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   hipLaunchKernelGGL((shock_batch_kernel<K, LMAX, NROT>), dim3(b.total), dim3(Launch<N>::kThreads), 0, s, b.descs,
-                     b.start, b.nruns, b.total, b.tile_map);
+                     b.start, b.tile_run, b.total, b.tile_map);
 }
 
 template <int K, int NROT>

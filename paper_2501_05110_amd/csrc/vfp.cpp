@@ -1349,6 +1349,7 @@ struct vfp_batch {
     BatchKernel bk;
     DevBuf descs;                      // [stage][member] KernelArgs
     DevBuf start;                      // members + 1 tile offsets
+    DevBuf tile_run;                   // run (member index) of every tile
     int total = 0;                     // tiles = workgroups per launch
     int tile_map = 0;                  // tuned
   };
@@ -1361,10 +1362,22 @@ struct vfp_batch {
   int device = -1;
   hipStream_t stream = nullptr;        // private stream (default priority) for graphs
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // capture: one branch per class (classes share no run, so their stages may
+  // run concurrently); streams and events of the fork / join
+  std::vector<hipStream_t> branch;
+  std::vector<hipEvent_t> joins;
+  hipEvent_t fork = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  ~vfp_batch() { drop_graph(); if (ev_in) (void)hipEventDestroy(ev_in); if (ev_out) (void)hipEventDestroy(ev_out);
-                 if (stream) (void)hipStreamDestroy(stream); }
+  ~vfp_batch() {
+    drop_graph();
+    if (ev_in) (void)hipEventDestroy(ev_in);
+    if (ev_out) (void)hipEventDestroy(ev_out);
+    if (fork) (void)hipEventDestroy(fork);
+    for (auto e : joins) (void)hipEventDestroy(e);
+    for (auto st : branch) (void)hipStreamDestroy(st);
+    if (stream) (void)hipStreamDestroy(stream);
+  }
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -1409,6 +1422,7 @@ int batch_launch_stage(vfp_batch* b, vfp_batch::Class& cl, int s, hipStream_t st
     BatchArgs ba;
     ba.descs = cl.descs.as<KernelArgs>() + (size_t)s * cl.members.size();
     ba.start = cl.start.as<int>();
+    ba.tile_run = cl.tile_run.as<int>();
     ba.nruns = (int)cl.members.size();
     ba.total = cl.total;
     ba.tile_map = cl.tile_map;
@@ -1434,6 +1448,19 @@ int batch_step(vfp_batch* b, hipStream_t st) {
   for (int s = 0; s < 4; ++s)
     for (auto& cl : b->classes)
       if (int e = batch_launch_stage(b, cl, s, st)) return e;
+  return VFP_OK;
+}
+
+// One step captured as a fork / join: class i's four stages on branch i.
+int batch_step_branched(vfp_batch* b, hipStream_t st) {
+  HIP_TRY(hipEventRecord(b->fork, st));
+  for (size_t i = 0; i < b->classes.size(); ++i) {
+    HIP_TRY(hipStreamWaitEvent(b->branch[i], b->fork, 0));
+    for (int s = 0; s < 4; ++s)
+      if (int e = batch_launch_stage(b, b->classes[i], s, b->branch[i])) return e;
+    HIP_TRY(hipEventRecord(b->joins[i], b->branch[i]));
+    HIP_TRY(hipStreamWaitEvent(st, b->joins[i], 0));
+  }
   return VFP_OK;
 }
 
@@ -1504,7 +1531,14 @@ int vfp_batch_create(vfp_batch** out, vfp_ctx* const* runs, int nruns, unsigned 
     }
     st.back() = (int)tot;
     cl.total = (int)tot;
+    std::vector<int> tr((size_t)tot);
+    for (size_t j = 0; j < cl.members.size(); ++j)
+      std::fill(tr.begin() + st[j], tr.begin() + st[j + 1], (int)j);
     if (int e = upload_vec(cl.start, st)) {
+      delete b;
+      return e;
+    }
+    if (int e = upload_vec(cl.tile_run, tr)) {
       delete b;
       return e;
     }
@@ -1565,10 +1599,19 @@ int vfp_batch_advance(vfp_batch* b, int64_t nsteps, void* stream) {
     HIP_TRY(hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
     HIP_TRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+    for (size_t i = 0; i < b->classes.size(); ++i) {
+      hipStream_t bs;
+      hipEvent_t je;
+      HIP_TRY(hipStreamCreateWithFlags(&bs, hipStreamNonBlocking));
+      b->branch.push_back(bs);
+      HIP_TRY(hipEventCreateWithFlags(&je, hipEventDisableTiming));
+      b->joins.push_back(je);
+    }
   }
   if (!b->exec) {
     HIP_TRY(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    int e = batch_step(b, b->stream);
+    int e = batch_step_branched(b, b->stream);
     hipGraph_t g = nullptr;
     hipError_t ce = hipStreamEndCapture(b->stream, &g);
     if (e) {

@@ -312,6 +312,22 @@ def config4(nruns=256, steps=100, seed=4):
     return runs
 
 
+# Many small shock runs (16-64 x 8-16 cells, mixed k and l_max): the regime
+# where one launch per run is launch-bound.
+def batch_small(nruns=512, steps=50, seed=7):
+    g = np.random.default_rng(SEED_BASE + seed)
+    runs = []
+    for i in range(nruns):
+        nx = int(g.integers(16, 65))
+        np_ = int(g.integers(8, 17))
+        k = int(g.integers(1, 3))
+        lmax = int(g.choice([1, 3, 5, 7]))
+        r = float(g.uniform(2.0, 4.0))
+        runs.append(shock_workload(f"small_{i}_{nx}x{np_}_k{k}_lmax{lmax}", nx, np_, k, lmax, r=r,
+                                   seed=seed, steps=steps, init=False))
+    return runs
+
+
 # C5: adjoint case, C2 physics on 512 x 64 cells
 def config5(nx=512, np_=64, steps=1000):
     return shock_workload("shock2d_x_lnp_512x64_k2_lmax3", nx, np_, 2, 3,
