@@ -132,16 +132,30 @@ def adjoint_timing(steps=1000):
     t_fwd = timed(lambda: op.advance(u, dt, steps, work))
     u.copy_(u0)
     t_ck = timed(lambda: op.forward_checkpoints(u, dt, steps, seg, ckpt, work))
-    lam = torch.randn(N, dtype=torch.float64, device=dev,
-                      generator=torch.Generator(device=dev).manual_seed(5))
+    lam0 = torch.randn(N, dtype=torch.float64, device=dev,
+                       generator=torch.Generator(device=dev).manual_seed(5))
+    lam = lam0.clone()
     t_rev = timed(lambda: op.adjoint_checkpointed(ckpt, dt, steps, seg, tape, lam, gnu, work))
-    if not (torch.isfinite(lam).all() and torch.isfinite(gnu).all()):
+    # the same with the flow sensitivities (for dJ/d(r, w)) and their reduction
+    slots = torch.zeros(op.field_grad_size(), dtype=torch.float64, device=dev)
+    nq = wl.ncells_axis[0] * (wl.k + 1)
+    gf = [torch.empty(nq, dtype=torch.float64, device=dev) for _ in range(3)]
+    gfc = torch.empty(wl.ncells_axis[0] + 1, dtype=torch.float64, device=dev)
+    lam = lam0.clone()
+
+    def full():
+        op.adjoint_checkpointed(ckpt, dt, steps, seg, tape, lam, gnu, work, field_slots=slots)
+        op.field_grad_reduce(slots, *gf, gfc)
+    t_full = timed(full)
+    if not (torch.isfinite(lam).all() and torch.isfinite(gnu).all() and torch.isfinite(slots).all()):
         raise RuntimeError("adjoint produced non-finite values")
     return {"workload": wl.name, "ndofs": N, "steps": steps, "segment": seg,
             "forward_s": t_fwd, "forward_checkpointed_s": t_ck, "reverse_s": t_rev,
             "reverse_over_forward": t_rev / t_fwd,
-            "note": "reverse = replay of each segment into a stage tape + adjoint stages "
-                    "with the fused dJ/dnu accumulation; dJ/du0 and dJ/dnu (32768 cells)"}
+            "reverse_with_flow_s": t_full, "reverse_with_flow_over_forward": t_full / t_fwd,
+            "note": "reverse = replay of each segment into a stage tape + adjoint stages with the "
+                    "fused dJ/dnu accumulation (dJ/du0, dJ/dnu for 32768 cells); with_flow adds the "
+                    "planar-flow sensitivities that give dJ/d(r, w)"}
 
 
 def batch_timing(full=False, steps=None):

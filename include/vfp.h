@@ -227,10 +227,11 @@ int vfp_advance_tape(vfp_ctx* ctx, const double* u0, double dt, int64_t nsteps, 
  * mu = M^{-1} dJ/du_0.  Because every 4-stage fourth-order scheme has the
  * step map P(dt L_lin) = 1 + dt L_lin + ... + (dt L_lin)^4/24 on this
  * linear autonomous system, each step maps mu to P(dt K) mu.
- * grad_nu (ncells doubles, may be NULL) accumulates dJ/dnu_c.
- * work: 3 ndofs doubles. */
+ * grad_nu (ncells doubles, may be NULL) accumulates dJ/dnu_c; field_slots
+ * (vfp_field_grad_size doubles, may be NULL) accumulates the planar-flow
+ * sensitivities (see vfp_field_grad_stage).  work: 3 ndofs doubles. */
 int vfp_adjoint_steps(vfp_ctx* ctx, const double* u0, const double* tape, double dt, int64_t nsteps,
-                      double* mu, double* grad_nu, double* work, void* stream);
+                      double* mu, double* grad_nu, double* field_slots, double* work, void* stream);
 
 /* vfp_advance with checkpoints: before each segment of seg steps the current
  * u is copied into ckpt[j] (ckpt: ceil(nsteps/seg) ndofs doubles).  work:
@@ -242,10 +243,32 @@ int vfp_forward_checkpoints(vfp_ctx* ctx, double* u, double dt, int64_t nsteps, 
  * forward steps are replayed from its checkpoint into tape
  * (4 min(seg, nsteps) ndofs doubles) and swept back with vfp_adjoint_steps.
  * lam: on entry dJ/du_nsteps, on exit dJ/du_0 (Euclidean gradients).
- * grad_nu (ncells doubles, may be NULL) accumulates dJ/dnu_c.  work: 3 ndofs
- * doubles.  All buffers must be disjoint. */
+ * grad_nu (ncells doubles) and field_slots (vfp_field_grad_size doubles)
+ * accumulate, either may be NULL.  work: 3 ndofs doubles.  All buffers must
+ * be disjoint. */
 int vfp_adjoint_checkpointed(vfp_ctx* ctx, const double* ckpt, double dt, int64_t nsteps, int64_t seg,
-                             double* tape, double* lam, double* grad_nu, double* work, void* stream);
+                             double* tape, double* lam, double* grad_nu, double* field_slots,
+                             double* work, void* stream);
+
+/* Sensitivities to the planar flow of an (x, ln p) context: the arrays
+ * u, dudx, dudt (x Gauss points) and u_face (x faces) of
+ * vfp_set_flow_planar.  For a stage w_out = u + cdt L(fwd) whose output has
+ * the adjoint lambda = M mu, the contribution to dJ/dfield is
+ *     cdt <mu, d(h - D fwd)/dfield>,
+ * differentiating the volume terms, the upwind x-face flux (speeds
+ * U_F + lambda V; Heaviside 1/2 where a speed is exactly 0) and the ln p
+ * face flux B_+ f1 + B_- f2 (spectral derivative of B_+) of
+ * eq. definition-mass-and-dg-matrix.  vfp_field_grad_stage accumulates it
+ * into per-cell slots (device, *n doubles from vfp_field_grad_size,
+ * zeroed by the caller before the first stage); vfp_field_grad_reduce sums
+ * the slots into g_u, g_dudx, g_dudt (N0 (k+1) doubles each) and g_uface
+ * (N0 + 1 doubles), overwriting them.  VFP_EUNSUPPORTED for contexts without
+ * an (x, ln p) planar flow. */
+int vfp_field_grad_size(const vfp_ctx* ctx, int64_t* n);
+int vfp_field_grad_stage(vfp_ctx* ctx, const double* mu, const double* fwd, double cdt, double* slots,
+                         void* stream);
+int vfp_field_grad_reduce(vfp_ctx* ctx, const double* slots, double* g_u, double* g_dudx, double* g_dudt,
+                          double* g_uface, void* stream);
 
 /* ------------------------------------------------------------------ batches
  *

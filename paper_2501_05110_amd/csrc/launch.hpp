@@ -33,6 +33,18 @@ struct BatchKernel {
 BatchKernel find_shock_batch_kernel(int k, int lmax, int nrot);
 int shock_cells_per_tile(int lmax);
 
+// Field sensitivities of one stage (planar flow of an (x, ln p) run):
+// accumulate cdt <mu, d(h - D fwd)/dfield> into per-cell slots; reduce the
+// slots to dJ/dU, dJ/dU', dJ/d(dU/dt) at the x Gauss points and dJ/dU at the
+// x faces.
+using FieldGradLauncher = void (*)(const KernelArgs&, const double* mu, const double* fwd, double cdt,
+                                   double* slots, hipStream_t);
+using FieldGradReduce = void (*)(const MeshArgs&, const double* slots, double* g_u, double* g_du, double* g_a,
+                                 double* g_uf, hipStream_t);
+FieldGradLauncher find_field_grad_launcher(int k, int lmax);
+FieldGradReduce find_field_grad_reduce(int k);
+int field_grad_slots_per_cell(int k);
+
 hipError_t upload_basis(const Basis1D* b);
 
 int stage_cells_per_block(int lmax);

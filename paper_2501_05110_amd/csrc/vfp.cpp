@@ -191,7 +191,7 @@ struct vfp_ctx {
   // device data
   DevBuf d_s2h[3], d_u_vol, d_du_vol, d_a_vol, d_u_face;
   DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face;
-  DevBuf d_pf_code, d_pf_coded, d_pf_tab, d_Bpts, d_nu, d_src;
+  DevBuf d_pf_code, d_pf_coded, d_pf_tab, d_pf_eig, d_Bpts, d_nu, d_src;
   DevBuf d_itab, d_dtab, d_xrec, d_prec;
   RowTables tab{};
   FieldArgs fld{};
@@ -549,9 +549,14 @@ int build_pface_data(vfp_ctx* c) {
     inv_v[f] = gam * c->mass / p;
   }
   const size_t rowsz = (size_t)n * (L + 1);
+  // eigen-data of a mixed point: per m block, eigenvalues then eigenvectors
+  // (row-major, column e = eigenvector e), for the field gradients
+  size_t eigsz = 0;
+  for (int m = 0; m <= L; ++m) eigsz += (size_t)(L - m + 1) * (L - m + 2);
   struct Part {
     std::vector<int> code_ix;            // [ix - lo][f]
     std::vector<double> tab;             // rows of mixed-sign points, in (ix, f) order
+    std::vector<double> eig;             // eigen-data of the same points
     double bmax = 0.0;
   };
   const int nth = std::max(1, std::min(host_threads(), nxp));
@@ -608,6 +613,12 @@ int build_pface_data(vfp_ctx* c) {
           }
           cd = (int)(P.tab.size() / rowsz);     // local index, offset on merge
           P.tab.insert(P.tab.end(), rows.begin(), rows.end());
+          for (int m = 0; m <= L; ++m) {
+            const int bsz = L - m + 1;
+            for (int i = 0; i < bsz; ++i) P.eig.push_back(ev[m][i]);
+            for (int i = 0; i < bsz; ++i)
+              for (int e = 0; e < bsz; ++e) P.eig.push_back(vec[m][i][e]);
+          }
         }
         P.code_ix[(size_t)(ix - lo) * npf + f] = cd;
       }
@@ -621,7 +632,7 @@ int build_pface_data(vfp_ctx* c) {
     for (auto& x : th) x.join();
   }
   std::vector<int> code((size_t)nxp * npf, -1);
-  std::vector<double> tab;
+  std::vector<double> tab, eig;
   c->beta_pmax = 0.0;
   for (int t = 0; t < nth; ++t) {
     const int lo = (int)((long long)nxp * t / nth), hi = (int)((long long)nxp * (t + 1) / nth);
@@ -633,6 +644,7 @@ int build_pface_data(vfp_ctx* c) {
         code[(size_t)f * nxp + ix] = cd >= 0 ? cd + off : cd;
       }
     tab.insert(tab.end(), P.tab.begin(), P.tab.end());
+    eig.insert(eig.end(), P.eig.begin(), P.eig.end());
     c->beta_pmax = std::max(c->beta_pmax, P.bmax);
   }
   if (int e = upload_vec(c->d_pf_code, code)) return e;
@@ -640,6 +652,8 @@ int build_pface_data(vfp_ctx* c) {
   if (int e = upload_vec(c->d_pf_coded, coded)) return e;
   if (tab.empty()) tab.assign(rowsz, 0.0);
   if (int e = upload_vec(c->d_pf_tab, tab)) return e;
+  if (eig.empty()) eig.assign(eigsz, 0.0);
+  if (int e = upload_vec(c->d_pf_eig, eig)) return e;
   return VFP_OK;
 }
 
@@ -750,6 +764,7 @@ int refresh(vfp_ctx* c, unsigned what) {
   F.xrec = c->d_xrec.as<double>();
   F.prec = c->d_prec.as<double>();
   F.pf_tab = c->d_pf_tab.as<double>();
+  F.pf_eig = c->d_pf_eig.as<double>();
   for (int i = 0; i < 3; ++i) F.B[i] = c->B[i];
   F.B_pts = c->have_Bpts ? c->d_Bpts.as<double>() : nullptr;
   F.nu0 = c->nu0;
@@ -1266,8 +1281,59 @@ int vfp_advance_tape(vfp_ctx* c, const double* u0, double dt, int64_t nsteps, do
   return VFP_OK;
 }
 
+static int field_grad_ready(const vfp_ctx* c) {
+  if (!(c->naxes == 2 && c->mom && c->planar))
+    return fail(VFP_EUNSUPPORTED, "field gradients need an (x, ln p) context with a planar flow");
+  return VFP_OK;
+}
+
+static int launch_fg(vfp_ctx* c, const double* mu, const double* fwd, double cdt, double* slots, void* stream) {
+  FieldGradLauncher fl = find_field_grad_launcher(c->k, c->lmax);
+  if (!fl) return fail(VFP_EUNSUPPORTED, "no field-gradient kernel for k=%d lmax=%d", c->k, c->lmax);
+  KernelArgs a{};
+  a.mesh = c->meshargs;
+  a.fld = c->fld;
+  a.tab = c->tab;
+  fl(a, mu, fwd, cdt, slots, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return VFP_OK;
+}
+
+int vfp_field_grad_size(const vfp_ctx* c, int64_t* n) {
+  if (int e = check_ready(c)) return e;
+  if (!n) return fail(VFP_EINVAL, "null argument");
+  if (int e = field_grad_ready(c)) return e;
+  *n = (int64_t)c->ncells * field_grad_slots_per_cell(c->k);
+  return VFP_OK;
+}
+
+int vfp_field_grad_stage(vfp_ctx* c, const double* mu, const double* fwd, double cdt, double* slots,
+                         void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (int e = field_grad_ready(c)) return e;
+  if (!mu || !fwd || !slots) return fail(VFP_EINVAL, "null pointer");
+  if (!std::isfinite(cdt)) return fail(VFP_EINVAL, "cdt not finite");
+  int64_t N = 0, ns = 0;
+  vfp_ndofs(c, &N);
+  vfp_field_grad_size(c, &ns);
+  if (overlaps(slots, ns, mu, N) || overlaps(slots, ns, fwd, N)) return fail(VFP_EINVAL, "slots overlap an input");
+  return launch_fg(c, mu, fwd, cdt, slots, stream);
+}
+
+int vfp_field_grad_reduce(vfp_ctx* c, const double* slots, double* g_u, double* g_dudx, double* g_dudt,
+                          double* g_uface, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (int e = field_grad_ready(c)) return e;
+  if (!slots || !g_u || !g_dudx || !g_dudt || !g_uface) return fail(VFP_EINVAL, "null pointer");
+  FieldGradReduce fr = find_field_grad_reduce(c->k);
+  if (!fr) return fail(VFP_EUNSUPPORTED, "k=%d", c->k);
+  fr(c->meshargs, slots, g_u, g_dudx, g_dudt, g_uface, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return VFP_OK;
+}
+
 int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double dt, int64_t nsteps, double* mu,
-                      double* grad_nu, double* work, void* stream) {
+                      double* grad_nu, double* field_slots, double* work, void* stream) {
   if (int e = check_ready(c)) return e;
   if (!u0 || !tape || !mu || !work) return fail(VFP_EINVAL, "null state pointer");
   if (nsteps < 0 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps");
@@ -1278,6 +1344,14 @@ int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double d
     return fail(VFP_EINVAL, "work / mu overlap the tape or each other");
   if (grad_nu && (overlaps(grad_nu, c->ncells, work, 3 * N) || overlaps(grad_nu, c->ncells, mu, N)))
     return fail(VFP_EINVAL, "grad_nu overlaps a state buffer");
+  if (field_slots) {
+    if (int e = field_grad_ready(c)) return e;
+    int64_t ns = 0;
+    vfp_field_grad_size(c, &ns);
+    if (overlaps(field_slots, ns, work, 3 * N) || overlaps(field_slots, ns, mu, N) ||
+        overlaps(field_slots, ns, tape, 4 * nsteps * N) || overlaps(field_slots, ns, grad_nu, c->ncells))
+      return fail(VFP_EINVAL, "field_slots overlap another buffer");
+  }
   double* acc = work;
   double* b1 = work + N;
   double* b2 = work + 2 * N;
@@ -1288,9 +1362,19 @@ int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double d
     const double* f2 = grad_nu ? w + N : nullptr;
     const double* f1 = grad_nu ? w : nullptr;
     const double* f0 = grad_nu ? un : nullptr;
+    // each field-gradient launch pairs an adjoint stage input with its
+    // forward stage input, before the adjoint stage may overwrite it
+    if (field_slots)
+      if (int e = launch_fg(c, mu, w + 2 * N, stage_cdt(3, dt), field_slots, stream)) return e;
     if (int e = launch_adj(c, mu, mu, acc, 1.0, stage_cdt(3, dt), b1, f3, grad_nu, 0, stream)) return e;
+    if (field_slots)
+      if (int e = launch_fg(c, b1, w + N, stage_cdt(2, dt), field_slots, stream)) return e;
     if (int e = launch_adj(c, b1, acc, acc, 1.0, stage_cdt(2, dt), b2, f2, grad_nu, 0, stream)) return e;
+    if (field_slots)
+      if (int e = launch_fg(c, b2, w, stage_cdt(1, dt), field_slots, stream)) return e;
     if (int e = launch_adj(c, b2, acc, acc, 1.0, stage_cdt(1, dt), b1, f1, grad_nu, 0, stream)) return e;
+    if (field_slots)
+      if (int e = launch_fg(c, b1, un, stage_cdt(0, dt), field_slots, stream)) return e;
     if (int e = launch_adj(c, b1, acc, mu, 1.0, stage_cdt(0, dt), nullptr, f0, grad_nu, 0, stream)) return e;
   }
   return VFP_OK;
@@ -1316,7 +1400,8 @@ int vfp_forward_checkpoints(vfp_ctx* c, double* u, double dt, int64_t nsteps, in
 }
 
 int vfp_adjoint_checkpointed(vfp_ctx* c, const double* ckpt, double dt, int64_t nsteps, int64_t seg,
-                             double* tape, double* lam, double* grad_nu, double* work, void* stream) {
+                             double* tape, double* lam, double* grad_nu, double* field_slots, double* work,
+                             void* stream) {
   if (int e = check_ready(c)) return e;
   if (!ckpt || !tape || !lam || !work) return fail(VFP_EINVAL, "null state pointer");
   if (nsteps < 0 || seg < 1 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps / seg");
@@ -1332,7 +1417,7 @@ int vfp_adjoint_checkpointed(vfp_ctx* c, const double* ckpt, double dt, int64_t 
     const int64_t cnt = std::min(seg, nsteps - j * seg);
     const double* u0 = ckpt + j * N;
     if (int e = vfp_advance_tape(c, u0, dt, cnt, tape, stream)) return e;
-    if (int e = vfp_adjoint_steps(c, u0, tape, dt, cnt, lam, grad_nu, work, stream)) return e;
+    if (int e = vfp_adjoint_steps(c, u0, tape, dt, cnt, lam, grad_nu, field_slots, work, stream)) return e;
   }
   return launch_mass(c, lam, lam, false, stream);
 }

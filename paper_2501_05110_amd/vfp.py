@@ -64,9 +64,12 @@ def load(path: str = None):
         "vfp_apply_adjoint": (I, [P, P, P, P]),
         "vfp_adjoint_stage": (I, [P, P, P, P, D, P, P, P, P]),
         "vfp_advance_tape": (I, [P, P, D, L, P, P]),
-        "vfp_adjoint_steps": (I, [P, P, P, D, L, P, P, P, P]),
+        "vfp_adjoint_steps": (I, [P, P, P, D, L, P, P, P, P, P]),
         "vfp_forward_checkpoints": (I, [P, P, D, L, L, P, P, P]),
-        "vfp_adjoint_checkpointed": (I, [P, P, D, L, L, P, P, P, P, P]),
+        "vfp_adjoint_checkpointed": (I, [P, P, D, L, L, P, P, P, P, P, P]),
+        "vfp_field_grad_size": (I, [P, C.POINTER(L)]),
+        "vfp_field_grad_stage": (I, [P, P, P, D, P, P]),
+        "vfp_field_grad_reduce": (I, [P, P, P, P, P, P, P]),
         "vfp_batch_create": (I, [C.POINTER(P), C.POINTER(P), I, U]),
         "vfp_batch_destroy": (None, [P]),
         "vfp_batch_bind": (I, [P, C.POINTER(P), C.POINTER(P), dp]),
@@ -91,7 +94,8 @@ def exported_symbols():
             "vfp_advance", "vfp_mass", "vfp_apply_adjoint", "vfp_adjoint_stage", "vfp_advance_tape",
             "vfp_adjoint_steps", "vfp_forward_checkpoints", "vfp_adjoint_checkpointed",
             "vfp_batch_create", "vfp_batch_destroy", "vfp_batch_bind", "vfp_batch_advance",
-            "vfp_batch_autotune", "vfp_batch_nclasses", "vfp_batch_class_info"]
+            "vfp_batch_autotune", "vfp_batch_nclasses", "vfp_batch_class_info",
+            "vfp_field_grad_size", "vfp_field_grad_stage", "vfp_field_grad_reduce"]
 
 
 def _check(rc):
@@ -265,11 +269,11 @@ class Operator:
                                      self._t(tape, "tape", 4 * nsteps * self.ndofs),
                                      _stream_handle(stream)))
 
-    def adjoint_steps(self, u0, tape, dt, nsteps, mu, grad_nu, work, stream=None):
+    def adjoint_steps(self, u0, tape, dt, nsteps, mu, grad_nu, work, field_slots=None, stream=None):
         _check(_lib.vfp_adjoint_steps(
             self._ctx, self._t(u0, "u0"), self._t(tape, "tape", 4 * nsteps * self.ndofs), float(dt),
             int(nsteps), self._t(mu, "mu"), self._t(grad_nu, "grad_nu", self.ncells, optional=True),
-            self._t(work, "work", 3 * self.ndofs), _stream_handle(stream)))
+            self._slots(field_slots), self._t(work, "work", 3 * self.ndofs), _stream_handle(stream)))
 
     def forward_checkpoints(self, u, dt, nsteps, seg, ckpt, work, stream=None):
         nseg = -(-nsteps // seg)
@@ -278,13 +282,40 @@ class Operator:
             self._t(ckpt, "ckpt", nseg * self.ndofs), self._t(work, "work", 2 * self.ndofs),
             _stream_handle(stream)))
 
-    def adjoint_checkpointed(self, ckpt, dt, nsteps, seg, tape, lam, grad_nu, work, stream=None):
+    def adjoint_checkpointed(self, ckpt, dt, nsteps, seg, tape, lam, grad_nu, work, field_slots=None,
+                             stream=None):
         nseg = -(-nsteps // seg)
         _check(_lib.vfp_adjoint_checkpointed(
             self._ctx, self._t(ckpt, "ckpt", nseg * self.ndofs), float(dt), int(nsteps), int(seg),
             self._t(tape, "tape", 4 * min(seg, nsteps) * self.ndofs), self._t(lam, "lam"),
             self._t(grad_nu, "grad_nu", self.ncells, optional=True),
-            self._t(work, "work", 3 * self.ndofs), _stream_handle(stream)))
+            self._slots(field_slots), self._t(work, "work", 3 * self.ndofs), _stream_handle(stream)))
+
+    def _slots(self, slots):
+        return None if slots is None else self._t(slots, "field_slots", self.field_grad_size())
+
+    def field_grad_size(self):
+        n = C.c_int64()
+        _check(_lib.vfp_field_grad_size(self._ctx, C.byref(n)))
+        return n.value
+
+    def field_grad_stage(self, mu, fwd, cdt, slots, stream=None):
+        _check(_lib.vfp_field_grad_stage(self._ctx, self._t(mu, "mu"), self._t(fwd, "fwd"), float(cdt),
+                                         self._t(slots, "slots", self.field_grad_size()),
+                                         _stream_handle(stream)))
+
+    def field_grad_reduce(self, slots, g_u, g_dudx, g_dudt, g_uface, stream=None):
+        nq = self.wl.ncells_axis[0] * (self.wl.k + 1)
+        _check(_lib.vfp_field_grad_reduce(
+            self._ctx, self._t(slots, "slots", self.field_grad_size()), self._t(g_u, "g_u", nq),
+            self._t(g_dudx, "g_dudx", nq), self._t(g_dudt, "g_dudt", nq),
+            self._t(g_uface, "g_uface", self.wl.ncells_axis[0] + 1), _stream_handle(stream)))
+
+    def set_flow_planar(self, u, dudx, dudt, u_face):
+        """Replace the planar flow profile (host arrays at the x Gauss points
+        and x faces)."""
+        _check(_lib.vfp_set_flow_planar(self._ctx, _dptr(_f64(u)), _dptr(_f64(dudx)), _dptr(_f64(dudt)),
+                                        _dptr(_f64(u_face))))
 
     @property
     def ncells(self):
@@ -366,15 +397,38 @@ class _AdvanceFn:
     fn = None
 
 
-def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: int = None):
+def planar_shock_fields(op: "Operator", U0, r, w):
+    """The tanh shock U(x) = U0[(r+1)/2 - (r-1)/2 tanh(x/w)] (U0 the
+    downstream speed) at the library's x Gauss points and x faces, as
+    differentiable torch tensors (u, dU/dx, dU/dt = U dU/dx, u_face) of the
+    parameters (torch scalars on the GPU)."""
+    import torch
+    xv = torch.from_numpy(op.points(PTS_VOLUME, 0)).to(U0.device)
+    xf = torch.from_numpy(op.points(PTS_FACE, 0)).to(U0.device)
+
+    def prof(x):
+        t = torch.tanh(x / w)
+        U = U0 * ((r + 1) / 2 - (r - 1) / 2 * t)
+        dU = -U0 * (r - 1) / (2 * w) * (1 - t * t)
+        return U, dU
+    u, du = prof(xv)
+    uf, _ = prof(xf)
+    return u, du, u * du, uf
+
+
+def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: int = None, flow=None):
     """u_N = RK4^N(u0) with the scattering frequency nu_cell (one value per
-    cell) as a differentiable input: backward returns dJ/du0 and dJ/dnu_cell
-    from the checkpointed discrete adjoint of the library."""
+    cell) and, optionally, the planar flow flow = (u, dudx, dudt, u_face) as
+    differentiable inputs: backward returns their gradients from the
+    checkpointed discrete adjoint of the library (the flow sensitivities from
+    vfp_field_grad_*)."""
     import torch
     if _AdvanceFn.fn is None:
         class AdvanceFn(torch.autograd.Function):
             @staticmethod
-            def forward(ctx, u0, nu, op, dt, nsteps, seg):
+            def forward(ctx, u0, nu, u_q, du_q, a_q, u_f, op, dt, nsteps, seg, has_flow):
+                if has_flow:
+                    op.set_flow_planar(*(t.detach().cpu().numpy() for t in (u_q, du_q, a_q, u_f)))
                 op.set_scattering(nu.detach().cpu().numpy())
                 N = op.ndofs
                 nseg = -(-nsteps // seg)
@@ -382,8 +436,10 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
                 ckpt = torch.empty(max(nseg, 1) * N, dtype=torch.float64, device=u.device)
                 work = torch.empty(2 * N, dtype=torch.float64, device=u.device)
                 op.forward_checkpoints(u, dt, nsteps, seg, ckpt, work)
-                ctx.op, ctx.dt, ctx.nsteps, ctx.seg = op, dt, nsteps, seg
+                ctx.op, ctx.dt, ctx.nsteps, ctx.seg, ctx.has_flow = op, dt, nsteps, seg, has_flow
                 ctx.nu = nu.detach().cpu().numpy().copy()
+                ctx.flow = tuple(t.detach().cpu().numpy().copy() for t in (u_q, du_q, a_q, u_f)) \
+                    if has_flow else None
                 ctx.save_for_backward(ckpt)
                 return u
 
@@ -391,15 +447,31 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
             def backward(ctx, g):
                 (ckpt,) = ctx.saved_tensors
                 op, N = ctx.op, ctx.op.ndofs
+                if ctx.has_flow:
+                    op.set_flow_planar(*ctx.flow)
                 op.set_scattering(ctx.nu)
+                dev = g.device
                 lam = g.detach().to(torch.float64).contiguous().clone()
-                grad_nu = torch.zeros(op.ncells, dtype=torch.float64, device=lam.device)
+                grad_nu = torch.zeros(op.ncells, dtype=torch.float64, device=dev)
+                slots = torch.zeros(op.field_grad_size(), dtype=torch.float64, device=dev) \
+                    if ctx.has_flow else None
                 if ctx.nsteps > 0:
-                    tape = torch.empty(4 * min(ctx.seg, ctx.nsteps) * N, dtype=torch.float64,
-                                       device=lam.device)
-                    work = torch.empty(3 * N, dtype=torch.float64, device=lam.device)
-                    op.adjoint_checkpointed(ckpt, ctx.dt, ctx.nsteps, ctx.seg, tape, lam, grad_nu, work)
-                return lam, grad_nu, None, None, None, None
+                    tape = torch.empty(4 * min(ctx.seg, ctx.nsteps) * N, dtype=torch.float64, device=dev)
+                    work = torch.empty(3 * N, dtype=torch.float64, device=dev)
+                    op.adjoint_checkpointed(ckpt, ctx.dt, ctx.nsteps, ctx.seg, tape, lam, grad_nu, work,
+                                            field_slots=slots)
+                gf = (None, None, None, None)
+                if ctx.has_flow:
+                    nq = op.wl.ncells_axis[0] * (op.wl.k + 1)
+                    gu, gd, ga = (torch.empty(nq, dtype=torch.float64, device=dev) for _ in range(3))
+                    gfc = torch.empty(op.wl.ncells_axis[0] + 1, dtype=torch.float64, device=dev)
+                    op.field_grad_reduce(slots, gu, gd, ga, gfc)
+                    gf = (gu, gd, ga, gfc)
+                return (lam, grad_nu) + gf + (None, None, None, None, None)
         _AdvanceFn.fn = AdvanceFn
+    import torch as _t
     seg = checkpoint_segment(nsteps) if seg is None else int(seg)
-    return _AdvanceFn.fn.apply(u0, nu_cell, op, float(dt), int(nsteps), seg)
+    if flow is None:
+        z = _t.zeros(1, dtype=_t.float64, device=u0.device)
+        return _AdvanceFn.fn.apply(u0, nu_cell, z, z, z, z, op, float(dt), int(nsteps), seg, False)
+    return _AdvanceFn.fn.apply(u0, nu_cell, *flow, op, float(dt), int(nsteps), seg, True)

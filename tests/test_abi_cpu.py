@@ -66,9 +66,13 @@ def test_calls_out_of_order(lib):
     assert lib.vfp_mass(ctx, None, None, 1, None) == -4
     assert lib.vfp_adjoint_stage(ctx, None, None, None, 0.1, None, None, None, None) == -4
     assert lib.vfp_advance_tape(ctx, None, 0.1, 1, None, None) == -4
-    assert lib.vfp_adjoint_steps(ctx, None, None, 0.1, 1, None, None, None, None) == -4
+    assert lib.vfp_adjoint_steps(ctx, None, None, 0.1, 1, None, None, None, None, None) == -4
     assert lib.vfp_forward_checkpoints(ctx, None, 0.1, 1, 1, None, None, None) == -4
-    assert lib.vfp_adjoint_checkpointed(ctx, None, 0.1, 1, 1, None, None, None, None, None) == -4
+    assert lib.vfp_adjoint_checkpointed(ctx, None, 0.1, 1, 1, None, None, None, None, None, None) == -4
+    ns = C.c_int64()
+    assert lib.vfp_field_grad_size(ctx, C.byref(ns)) == -4
+    assert lib.vfp_field_grad_stage(ctx, None, None, 0.1, None, None) == -4
+    assert lib.vfp_field_grad_reduce(ctx, None, None, None, None, None, None) == -4
     # a batch needs ready contexts
     b = C.c_void_p()
     arr = (C.c_void_p * 1)(ctx.value)
