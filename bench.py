@@ -11,14 +11,15 @@ HBM roofline fraction (algorithmic bytes / measured launch time, against
 8 TB/s), and the CPU oracle's rate on a bounded sample of the same workload.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-adjoint] [--no-batch]
-                  [--batch-full] [--copy-probe]
+                  [--no-other] [--batch-full] [--copy-probe]
 
 It also reports the adjoint: a 1000-step forward run of the 512 x 64 shock
 and its checkpointed reverse pass (gradients w.r.t. the initial state and
 nu per cell), with the reverse / forward time ratio, and the batched path:
 512 small shock runs of mixed k and l_max advanced by one launch per stage
 and class against one run per launch sequence (--batch-full: the 256 runs
-of 128-1024 x 32-128 cells).
+of 128-1024 x 32-128 cells), and the stage throughput of the 3-D box
+(48^3, k=2, l_max=5) and the 1-D line (64 cells, k=1, l_max=3).
 """
 
 from __future__ import annotations
@@ -149,10 +150,32 @@ def adjoint_timing(steps=1000):
     t_full = timed(full)
     if not (torch.isfinite(lam).all() and torch.isfinite(gnu).all() and torch.isfinite(slots).all()):
         raise RuntimeError("adjoint produced non-finite values")
+    del tape, ckpt
+    torch.cuda.empty_cache()
+    # the same gradients from a full stage tape (4 vectors per step: 151 GB
+    # here, within one MI355X's HBM): the forward writes every stage output
+    # to its own slot (no extra traffic) and the reverse replays nothing
+    taped = {}
+    need = 4 * steps * N * 8
+    free, _ = torch.cuda.mem_get_info()
+    if need < free - (8 << 30):
+        full_tape = torch.empty(4 * steps * N, dtype=torch.float64, device=dev)
+        t_tf = timed(lambda: op.advance_tape(u0, dt, steps, full_tape))
+        mu = lam0.clone()
+        op.mass(mu, mu, inverse=True)
+        t_tr = timed(lambda: op.adjoint_steps(u0, full_tape, dt, steps, mu, gnu, work))
+        slots.zero_()
+        mu = lam0.clone()
+        op.mass(mu, mu, inverse=True)
+        t_trf = timed(lambda: op.adjoint_steps(u0, full_tape, dt, steps, mu, gnu, work, field_slots=slots))
+        del full_tape
+        taped = {"tape_GB": need / 1e9, "forward_taped_s": t_tf, "reverse_s": t_tr, "reverse_with_flow_s": t_trf,
+                 "reverse_over_forward": t_tr / t_fwd, "reverse_with_flow_over_forward": t_trf / t_fwd}
     return {"workload": wl.name, "ndofs": N, "steps": steps, "segment": seg,
             "forward_s": t_fwd, "forward_checkpointed_s": t_ck, "reverse_s": t_rev,
             "reverse_over_forward": t_rev / t_fwd,
             "reverse_with_flow_s": t_full, "reverse_with_flow_over_forward": t_full / t_fwd,
+            "full_tape": taped,
             "note": "reverse = replay of each segment into a stage tape + adjoint stages with the "
                     "fused dJ/dnu accumulation (dJ/du0, dJ/dnu for 32768 cells); with_flow adds the "
                     "planar-flow sensitivities that give dJ/d(r, w)"}
@@ -213,6 +236,49 @@ def batch_timing(full=False, steps=None):
             "classes": [{k: c[k] for k in ("k", "lmax", "runs", "tiles", "tile_map")} for c in cls]}
 
 
+def other_configs():
+    """The 3-D periodic box (48^3 cells, k=2, l_max=5, B with random Fourier
+    modes; 107,495,424 DoF) and the 1-D periodic line (64 cells, k=1,
+    l_max=3; 2,048 DoF): stage throughput, and for the box its HBM roofline
+    fraction (stage bytes: 22 B/DoF on average plus B at the volume points)."""
+    import numpy as np
+    import torch
+    from paper_2501_05110_amd import vfp, workloads as W
+
+    out = {}
+    stream = torch.cuda.current_stream()
+    for name, wl, steps in (("box3d_48_k2_lmax5", W.config3(), 20), ("line1d_64_k1_lmax3", W.config1(), 100)):
+        op = vfp.Operator(wl)
+        N = op.ndofs
+        dt = op.cfl_dt(wl.courant)
+        if "init" in wl.meta:
+            u = torch.from_numpy(np.ascontiguousarray(wl.meta["init"]).ravel()).cuda()
+        else:
+            u = torch.from_numpy(np.ascontiguousarray(W.nodal_state(wl, wl.meta["init_func"])).ravel()).cuda()
+        work = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+        op.advance(u, dt, 3, work)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        op.advance(u, dt, steps, work)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        secs = e0.elapsed_time(e1) / 1e3
+        if not torch.isfinite(u).all():
+            raise RuntimeError(f"{name}: state is not finite")
+        rec = {"ndofs": N, "steps": steps, "dofs_per_s": N * steps / secs, "us_per_step": secs / steps * 1e6}
+        if name.startswith("box"):
+            per_launch = secs / (4 * steps)
+            fields = 8 * wl.ncells * wl.n_basis * 3
+            bts = N * (16 + 24 * 3) / 4 + fields
+            rec.update({"us_per_launch": per_launch * 1e6, "bytes_per_launch": bts,
+                        "achieved_GBs": bts / per_launch / 1e9, "frac": bts / per_launch / 1e9 / HBM_PEAK_GBS,
+                        "kernel": "stage_kernel<3,2,5,false,false,false>"})
+        out[name] = rec
+        op.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -221,6 +287,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-other", action="store_true", help="skip the 3-D box and 1-D line legs")
     ap.add_argument("--batch-full", action="store_true",
                     help="also time the 256 mixed runs (about 2.3e9 DoF, 52 GB; minutes of set-up)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -309,6 +376,8 @@ def main():
         out["adjoint"] = adjoint_timing()
     if not args.no_batch:
         out["batch"] = batch_timing(full=False)
+    if not args.no_other:
+        out["other_configs"] = other_configs()
     if args.batch_full:
         out["batch_full"] = batch_timing(full=True)
     if not args.no_cpu:

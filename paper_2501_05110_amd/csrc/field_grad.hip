@@ -19,13 +19,18 @@
 //     a2 (A^xA^x)_t, a1 = -t_mom a / V_F, a2 = -t_mom U'; B_+ is differentiated
 //     on its spectral decomposition B = Q diag(l) Q^T (Daleckii-Krein):
 //       dB_+ = Q (Gamma o (Q^T dB Q)) Q^T,  Gamma_kl = (l_k^+ - l_l^+)/(l_k - l_l)
-//     (H(l_k) where l_k = l_l); where B is definite, dB_+ = dB or 0.
+//     (H(l_k) where l_k = l_l), tabulated on the host for the two directions
+//     dB = A^x, (A^xA^x)_t at every mixed-sign point; where B is definite,
+//     dB_+ = dB or 0.
 // On a face from T1 (below) to T2 (above) the pairing is  int_F (mu_2 - mu_1).J
 // (the trace of a cell outside the mesh counts as zero).
 //
-// Each cell accumulates into its own slots (no atomics): its volume points,
-// its lower x and ln p faces, and its upper faces where they are the
-// (non-periodic) end of the mesh.  fgrad_reduce sums the slots per x point.
+// Each cell accumulates into its own slots (no atomics): its x Gauss points
+// (summed over its p points), its lower x and ln p faces, and its upper faces
+// where they are the (non-periodic) end of the mesh.  All global loads are
+// issued first; the lanes of a cell exchange forward values through LDS for
+// the l-coupling and reduce once at the end.  fgrad_reduce sums the slots per
+// x point.
 #include "basis.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -38,9 +43,8 @@ constexpr int kFgThreads = 64;
 template <int K>
 struct GSlots {
   static constexpr int K1 = K + 1;
-  static constexpr int NB = K1 * K1;
-  static constexpr int VOL = 0;            // [NB][3]: U, U', a at each volume point
-  static constexpr int XF = 3 * NB;        // [2]: lower, upper x face
+  static constexpr int VOL = 0;            // [K1 x points][3]: U, U', a (summed over the p points)
+  static constexpr int XF = 3 * K1;        // [2]: lower, upper x face
   static constexpr int PF = XF + 2;        // [2 sides][K1 x points][2]: a, U'
   static constexpr int SIZE = PF + 4 * K1;
 };
@@ -56,11 +60,11 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
   constexpr int K1 = K + 1;
   constexpr int NB = K1 * K1;
   constexpr int CPB = (kFgThreads / N) > 0 ? kFgThreads / N : 1;
-  constexpr int NR = 3 * NB;                // reduction rows per cell
+  constexpr int XRW = 4 * K1;               // exchange rows per cell
   using CB = CBasis<K>;
   using S = GSlots<K>;
-  // per cell: f, mu, d_x mu, d_p mu at the Gauss points, then partial sums
-  __shared__ double lds[CPB * (4 * NB + NR) * N];
+  constexpr int NS = S::SIZE;               // partial-sum rows per cell
+  __shared__ double lds[CPB * (XRW + NS) * N];
 
   const int tid = threadIdx.x;
   const int cl = tid / N;
@@ -74,100 +78,29 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
   const int cell = act ? cell0 : 0;
   const int nx = M.n[0], np = M.n[1];
   const int ix = cell % nx, ip = cell / nx;
-  double* L = lds + (in_grp ? cl : 0) * (4 * NB + NR) * N;
-  double* Fq = L;
-  double* Mq = L + NB * N;
-  double* Mx = L + 2 * NB * N;
-  double* Mp = L + 3 * NB * N;
-  double* Rd = L + 4 * NB * N;
+  double* X = lds + (in_grp ? cl : 0) * (XRW + NS) * N;
+  double* Rd = X + XRW * N;
 
+  // ---- every global load first ---------------------------------------------
+  const size_t cbase = (size_t)cell * NB * N + r;
+  double w[NB], m[NB];
+#pragma unroll
+  for (int b = 0; b < NB; ++b) {
+    w[b] = fwd[cbase + (size_t)b * N];
+    m[b] = mu[cbase + (size_t)b * N];
+  }
   const double* xr = F.xrec + (size_t)ix * kRec;
   const double* pr = F.prec + (size_t)ip * kRec;
   const double s2hx = xr[11], s2hp = pr[14];
   const double jac = 1.0 / (s2hx * s2hp);
   const double t_adv = F.t_adv, t_mom = F.t_mom;
   const double gw[3] = {K == 1 ? 1.0 : 5.0 / 9.0, K == 1 ? 1.0 : 8.0 / 9.0, 5.0 / 9.0};
-
-  const size_t cbase = (size_t)cell * NB * N + r;
-  double w[NB], m[NB];
-#pragma unroll
-  for (int b = 0; b < NB; ++b) {
-    w[b] = act ? fwd[cbase + (size_t)b * N] : 0.0;
-    m[b] = act ? mu[cbase + (size_t)b * N] : 0.0;
-  }
   const int axc0 = T.ax_col[r], axc1 = T.ax_col[N + r];
   const double axv0 = T.ax_val[r], axv1 = T.ax_val[N + r];
   const int axxc0 = T.axx_col[r], axxc1 = T.axx_col[N + r];
   const double axxv0 = T.axx_val[r], axxv1 = T.axx_val[N + r], axxv2 = T.axx_val[2 * N + r];
   const double g1v0 = T.g1_val[r], g1v1 = T.g1_val[N + r];
   const double g2v0 = T.g2_val[r], g2v1 = T.g2_val[N + r], g2v2 = T.g2_val[2 * N + r];
-  double* out = slots + (size_t)cell * S::SIZE;
-
-  // reduce Rd[o][0..N) over the cell's lanes into out[base + o] (scaled)
-  auto reduce_rows = [&](int nrows, int base, const double* scale) {
-    __syncthreads();
-    if (act)
-      for (int o = r; o < nrows; o += N) {
-        double sum = 0.0;
-        for (int j = 0; j < N; ++j) sum += Rd[o * N + j];
-        out[base + o] += cdt * scale[o] * sum;
-      }
-    __syncthreads();
-  };
-
-  // ---- volume ------------------------------------------------------------
-#pragma unroll
-  for (int q1 = 0; q1 < K1; ++q1)
-#pragma unroll
-    for (int q0 = 0; q0 < K1; ++q0) {
-      double f = 0.0, a = 0.0, dx = 0.0, dp = 0.0;
-#pragma unroll
-      for (int j1 = 0; j1 < K1; ++j1)
-#pragma unroll
-        for (int j0 = 0; j0 < K1; ++j0) {
-          const int b = j0 + K1 * j1;
-          f = fma(CB::phi[q0][j0] * CB::phi[q1][j1], w[b], f);
-          a = fma(CB::phi[q0][j0] * CB::phi[q1][j1], m[b], a);
-          dx = fma(CB::dphi[q0][j0] * CB::phi[q1][j1], m[b], dx);
-          dp = fma(CB::phi[q0][j0] * CB::dphi[q1][j1], m[b], dp);
-        }
-      const int q = q0 + K1 * q1;
-      if (in_grp) {
-        Fq[q * N + r] = f;
-        Mq[q * N + r] = a;
-        Mx[q * N + r] = dx;
-        Mp[q * N + r] = dp;
-      }
-    }
-  __syncthreads();
-  double vscale[NR];
-#pragma unroll
-  for (int q1 = 0; q1 < K1; ++q1)
-#pragma unroll
-    for (int q0 = 0; q0 < K1; ++q0) {
-      const int q = q0 + K1 * q1;
-      const double* P = Fq + q * N;
-      const double f = P[r];
-      const double Axf = fma(axv0, P[axc0], axv1 * P[axc1]);
-      const double A2f = fma(axxv0, P[axxc0], fma(axxv1, f, axxv2 * P[axxc1]));
-      const double G1f = fma(g1v0, P[axc0], g1v1 * P[axc1]);
-      const double G2f = fma(g2v0, P[axxc0], fma(g2v1, f, g2v2 * P[axxc1]));
-      const double iV = pr[3 + q1], pid = pr[6 + q1];
-      const double mq = Mq[q * N + r], mx = Mx[q * N + r], mp = Mp[q * N + r];
-      const double pu = s2hx * t_adv * mx * f;
-      const double pdu = -mq * (t_mom * G2f - t_adv * f) - s2hp * t_mom * mp * A2f;
-      const double pa = -mq * t_mom * (iV * G1f - pid * Axf) - s2hp * t_mom * t_mom * mp * iV * Axf;
-      if (in_grp) {
-        Rd[(3 * q + 0) * N + r] = pu;
-        Rd[(3 * q + 1) * N + r] = pdu;
-        Rd[(3 * q + 2) * N + r] = pa;
-      }
-      const double wq = gw[q0] * gw[q1] * jac;
-      vscale[3 * q] = vscale[3 * q + 1] = vscale[3 * q + 2] = wq;
-    }
-  reduce_rows(NR, S::VOL, vscale);
-
-  // ---- x faces -------------------------------------------------------------
   int mem[LMAX + 1];
   double wcol[LMAX + 1], wrow[LMAX + 1];
 #pragma unroll
@@ -177,182 +110,217 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
     wrow[i] = T.w_row[i * N + r];
   }
   const double lam = T.lam[r];
-  for (int side = 0; side < 2; ++side) {
-    const int bc = side ? M.bc_hi[0] : M.bc_lo[0];
-    const bool valid = act && (side == 0 || (ix == nx - 1 && bc != 0));
-    int ni = side ? ix + 1 : ix - 1;
-    const bool inside = ni >= 0 && ni < nx;
-    const bool use_n = inside || bc == 0;
-    ni = (ni + nx) % nx;
-    const size_t nb0 = (size_t)(cell + (ni - ix)) * NB * N + r;
-    const int jo = side ? K : 0, jn = side ? 0 : K;   // own / neighbour node column
-    double pr_acc = 0.0;
-    for (int q1 = 0; q1 < K1; ++q1) {
-      double fo = 0.0, fn = 0.0, mo = 0.0, mn = 0.0;
+  int pcode[2][K1];
+#pragma unroll
+  for (int side = 0; side < 2; ++side)
+#pragma unroll
+    for (int q0 = 0; q0 < K1; ++q0) pcode[side][q0] = F.pf_code[(size_t)(ip + side) * (nx * K1) + ix * K1 + q0];
+
+  // this lane's share of every slot goes to row i of Rd; the volume rows are
+  // accumulated in registers first
+  double part[3 * K1];
+#pragma unroll
+  for (int i = 0; i < 3 * K1; ++i) part[i] = 0.0;
+
+  // ---- volume: sum factorisation along x, then one row of points at a time
+  double tw[NB], tm[NB], tx[NB];            // [q0 + K1 j1]
+#pragma unroll
+  for (int j1 = 0; j1 < K1; ++j1)
+#pragma unroll
+    for (int q0 = 0; q0 < K1; ++q0) {
+      double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+      for (int j0 = 0; j0 < K1; ++j0) {
+        a = fma(CB::phi[q0][j0], w[j0 + K1 * j1], a);
+        b = fma(CB::phi[q0][j0], m[j0 + K1 * j1], b);
+        c = fma(CB::dphi[q0][j0], m[j0 + K1 * j1], c);
+      }
+      tw[q0 + K1 * j1] = a;
+      tm[q0 + K1 * j1] = b;
+      tx[q0 + K1 * j1] = c;
+    }
+#pragma unroll
+  for (int q1 = 0; q1 < K1; ++q1) {
+    double fq[K1];
+#pragma unroll
+    for (int q0 = 0; q0 < K1; ++q0) {
+      double f = 0.0;
+#pragma unroll
+      for (int j1 = 0; j1 < K1; ++j1) f = fma(CB::phi[q1][j1], tw[q0 + K1 * j1], f);
+      fq[q0] = f;
+      if (in_grp) X[q0 * N + r] = f;
+    }
+    __syncthreads();
+    const double iV = pr[3 + q1], pid = pr[6 + q1];
+#pragma unroll
+    for (int q0 = 0; q0 < K1; ++q0) {
+      double mq = 0.0, mx = 0.0, mp = 0.0;
 #pragma unroll
       for (int j1 = 0; j1 < K1; ++j1) {
-        const double ph = CB::phi[q1][j1];
-        fo = fma(ph, w[jo + K1 * j1], fo);
-        mo = fma(ph, m[jo + K1 * j1], mo);
-        const double vf = (act && use_n) ? fwd[nb0 + (size_t)(jn + K1 * j1) * N] : 0.0;
-        const double vm = (act && use_n) ? mu[nb0 + (size_t)(jn + K1 * j1) * N] : 0.0;
-        fn = fma(ph, vf, fn);
-        mn = fma(ph, vm, mn);
+        mq = fma(CB::phi[q1][j1], tm[q0 + K1 * j1], mq);
+        mx = fma(CB::phi[q1][j1], tx[q0 + K1 * j1], mx);
+        mp = fma(CB::dphi[q1][j1], tm[q0 + K1 * j1], mp);
       }
-      if (!use_n) fn = (bc == 1) ? 0.0 : fo;   // exterior state of zero inflow / continuous
-      const double f1 = side ? fo : fn, f2 = side ? fn : fo;
-      const double m1 = side ? mo : mn, m2 = side ? mn : mo;
-      if (in_grp) {
-        Fq[r] = f1;
-        Fq[N + r] = f2;
-      }
-      __syncthreads();
-      double c1 = 0.0, c2 = 0.0;
-#pragma unroll
-      for (int j = 0; j <= LMAX; ++j) {
-        c1 = fma(wcol[j], Fq[mem[j]], c1);
-        c2 = fma(wcol[j], Fq[N + mem[j]], c2);
-      }
-      const double V = pr[0 + q1];
-      const double sp = xr[9 + side] + t_adv * lam * V;
-      const double h = heav(sp);
-      const double d = t_adv * (h * c1 + (1.0 - h) * c2);
-      __syncthreads();
-      if (in_grp) Fq[r] = d;
-      __syncthreads();
-      double dj = 0.0;
-#pragma unroll
-      for (int i = 0; i <= LMAX; ++i) dj = fma(wrow[i], Fq[mem[i]], dj);
-      __syncthreads();
-      pr_acc += gw[q1] * (m2 - m1) * dj;
-    }
-    if (in_grp) Rd[r] = valid ? pr_acc : 0.0;
-    const double one[1] = {1.0 / s2hp};
-    __syncthreads();
-    if (valid && r == 0) {
-      double sum = 0.0;
-      for (int j = 0; j < N; ++j) sum += Rd[j];
-      out[S::XF + side] += cdt * one[0] * sum;
+      const double* P = X + q0 * N;
+      const double f = fq[q0];
+      const double Axf = fma(axv0, P[axc0], axv1 * P[axc1]);
+      const double A2f = fma(axxv0, P[axxc0], fma(axxv1, f, axxv2 * P[axxc1]));
+      const double G1f = fma(g1v0, P[axc0], g1v1 * P[axc1]);
+      const double G2f = fma(g2v0, P[axxc0], fma(g2v1, f, g2v2 * P[axxc1]));
+      const double wq = gw[q0] * gw[q1] * jac;
+      part[S::VOL + 3 * q0 + 0] += wq * (s2hx * t_adv * mx * f);
+      part[S::VOL + 3 * q0 + 1] += wq * (-mq * (t_mom * G2f - t_adv * f) - s2hp * t_mom * mp * A2f);
+      part[S::VOL + 3 * q0 + 2] +=
+          wq * (-mq * t_mom * (iV * G1f - pid * Axf) - s2hp * t_mom * t_mom * mp * iV * Axf);
     }
     __syncthreads();
   }
 
-  // ---- ln p faces --------------------------------------------------------
-  // block position of this row: l - m, and the block size
-  int lrow = 0;
-  while ((lrow + 1) * (lrow + 1) <= r) ++lrow;
-  const int mrow = r - lrow * (lrow + 1) < 0 ? lrow * (lrow + 1) - r : r - lrow * (lrow + 1);
-  const int pos = lrow - mrow, bsz = LMAX - mrow + 1;
-  size_t eoff = 0;
-  for (int mm = 0; mm < mrow; ++mm) eoff += (size_t)(LMAX - mm + 1) * (LMAX - mm + 2);
-  const size_t eigsz = [] {
-    size_t e = 0;
-    for (int mm = 0; mm <= LMAX; ++mm) e += (size_t)(LMAX - mm + 1) * (LMAX - mm + 2);
-    return e;
-  }();
-  for (int side = 0; side < 2; ++side) {
-    const int bc = side ? M.bc_hi[1] : M.bc_lo[1];
-    const bool valid = act && (side == 0 || (ip == np - 1 && bc != 0));
-    int ni = side ? ip + 1 : ip - 1;
-    const bool inside = ni >= 0 && ni < np;
-    const bool use_n = inside || bc == 0;
-    ni = (ni + np) % np;
-    const size_t nb0 = (size_t)(cell + (ni - ip) * nx) * NB * N + r;
-    const int jo = side ? K : 0, jn = side ? 0 : K;
-    const int pf = ip + side;
-    const double tmv = pr[12 + side];                   // t_mom / V at this face
-    double acc_a[K1], acc_u[K1];
-    for (int q0 = 0; q0 < K1; ++q0) {
-      double fo = 0.0, fn = 0.0, mo = 0.0, mn = 0.0;
+  if (in_grp)
 #pragma unroll
-      for (int j0 = 0; j0 < K1; ++j0) {
-        const double ph = CB::phi[q0][j0];
-        fo = fma(ph, w[j0 + K1 * jo], fo);
-        mo = fma(ph, m[j0 + K1 * jo], mo);
-        const double vf = (act && use_n) ? fwd[nb0 + (size_t)(j0 + K1 * jn) * N] : 0.0;
-        const double vm = (act && use_n) ? mu[nb0 + (size_t)(j0 + K1 * jn) * N] : 0.0;
-        fn = fma(ph, vf, fn);
-        mn = fma(ph, vm, mn);
+    for (int i = 0; i < 3 * K1; ++i) Rd[(S::VOL + i) * N + r] = part[i];
+
+  // neighbour traces [axis][side][j]: forward and adjoint values
+  // neighbour traces [axis][side][j]: forward and adjoint values
+  double nf[2][2][K1], nm[2][2][K1];
+  bool use_n[2][2];
+#pragma unroll
+  for (int ax = 0; ax < 2; ++ax)
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int ia = ax ? ip : ix, na = ax ? np : nx, st = ax ? nx : 1;
+      int ni = side ? ia + 1 : ia - 1;
+      const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
+      use_n[ax][side] = (ni >= 0 && ni < na) || bc == 0;
+      ni = (ni + na) % na;
+      const size_t nb0 = (size_t)(cell + (ni - ia) * st) * NB * N + r;
+      const int jn = side ? 0 : K;
+#pragma unroll
+      for (int j = 0; j < K1; ++j) {
+        const int node = ax ? (j + K1 * jn) : (jn + K1 * j);
+        nf[ax][side][j] = fwd[nb0 + (size_t)node * N];
+        nm[ax][side][j] = mu[nb0 + (size_t)node * N];
       }
-      if (!use_n) fn = (bc == 1) ? 0.0 : fo;
-      const double f1 = side ? fo : fn, f2 = side ? fn : fo;
-      const double m1 = side ? mo : mn, m2 = side ? mn : mo;
-      if (in_grp) {
-        Fq[r] = f1;
-        Fq[N + r] = f2;
-        Fq[2 * N + r] = f1 - f2;
-      }
-      __syncthreads();
-      const int code = F.pf_code[(size_t)pf * (nx * K1) + ix * K1 + q0];
-      const double* Pu = (code == -1) ? Fq : Fq + N;     // the state dB multiplies
-      const double ax_u = fma(axv0, Pu[axc0], axv1 * Pu[axc1]);
-      const double axx_u = fma(axxv0, Pu[axxc0], fma(axxv1, Pu[r], axxv2 * Pu[axxc1]));
-      double ja = -t_mom * tmv * ax_u, ju = -t_mom * axx_u;
-      if (code >= 0) {
-        // Daleckii-Krein: row r of Q (Gamma o Q^T dB Q) Q^T (f1 - f2) for dB =
-        // A^x and (A^xA^x)_t restricted to the (m, s) block of row r
-        const double* eg = F.pf_eig + (size_t)code * eigsz + eoff;
-        const double* lamb = eg;                         // [bsz]
-        const double* Q = eg + bsz;                      // [bsz][bsz], column e = eigenvector e
-        double y[LMAX + 1], zA[LMAX + 1], zX[LMAX + 1];
-        for (int e = 0; e < bsz; ++e) {
-          double acc = 0.0;
-          for (int i = 0; i < bsz; ++i) acc = fma(Q[i * bsz + e], Fq[2 * N + mem[i]], acc);
-          y[e] = acc;
+    }
+
+  // ---- faces: this cell's lower faces, and its upper faces at the
+  // (non-periodic) end of the mesh; on a face from T1 (below) to T2 (above)
+  // the pairing is int_F (mu_2 - mu_1) . dJ, with the trace of a cell outside
+  // the mesh counted as zero
+#pragma unroll
+  for (int ax = 0; ax < 2; ++ax) {
+    const int ia = ax ? ip : ix, na = ax ? np : nx;
+    // f1, f2 rows of both sides: [side][f1 / f2][q] in X
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
+#pragma unroll
+      for (int q = 0; q < K1; ++q) {
+        double fo = 0.0, fn = 0.0;
+#pragma unroll
+        for (int j = 0; j < K1; ++j) {
+          const double ph = CB::phi[q][j];
+          const int node = ax ? (j + K1 * (side ? K : 0)) : ((side ? K : 0) + K1 * j);
+          fo = fma(ph, w[node], fo);
+          fn = fma(ph, nf[ax][side][j], fn);
         }
-        for (int k = 0; k < bsz; ++k) zA[k] = zX[k] = 0.0;
-        for (int l = 0; l < bsz; ++l) {
-          // v = dB q_l for both dB, in block coordinates
-          for (int i = 0; i < bsz; ++i) {
-            const int ri = mem[i];
-            const int c0 = T.ax_col[ri], c1 = T.ax_col[N + ri];
-            const double a0 = T.ax_val[ri], a1v = T.ax_val[N + ri];
-            const int x0 = T.axx_col[ri], x1 = T.axx_col[N + ri];
-            const double b0 = T.axx_val[ri], b1 = T.axx_val[N + ri], b2 = T.axx_val[2 * N + ri];
-            // block positions of the column entries (l +- 1, l +- 2 in the block)
-            double vA = 0.0, vX = b1 * Q[i * bsz + l];
-            if (c0 != ri && i + 1 < bsz) vA = fma(a0, Q[(i + 1) * bsz + l], vA);
-            if (c1 != ri && i - 1 >= 0) vA = fma(a1v, Q[(i - 1) * bsz + l], vA);
-            if (x0 != ri && i + 2 < bsz) vX = fma(b0, Q[(i + 2) * bsz + l], vX);
-            if (x1 != ri && i - 2 >= 0) vX = fma(b2, Q[(i - 2) * bsz + l], vX);
-            // D_kl = q_k . v for every k: accumulate Gamma_kl D_kl y_l into z_k
-            for (int k = 0; k < bsz; ++k) {
-              const double lk = lamb[k], ll = lamb[l];
-              const double dl = lk - ll;
-              const double gam = (fabs(dl) > 1e-14 * (fabs(lk) + fabs(ll)))
-                                     ? (fmax(lk, 0.0) - fmax(ll, 0.0)) / dl
-                                     : heav(lk);
-              zA[k] = fma(gam * Q[i * bsz + k] * vA, y[l], zA[k]);
-              zX[k] = fma(gam * Q[i * bsz + k] * vX, y[l], zX[k]);
+        if (!use_n[ax][side]) fn = (bc == 1) ? 0.0 : fo;   // exterior of zero inflow / continuous
+        if (in_grp) {
+          X[((side * 2 + 0) * K1 + q) * N + r] = side ? fo : fn;   // f1 (lower cell)
+          X[((side * 2 + 1) * K1 + q) * N + r] = side ? fn : fo;   // f2 (upper cell)
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
+      const bool valid = act && (side == 0 || (ia == na - 1 && bc != 0));
+      double dmu[K1];
+#pragma unroll
+      for (int q = 0; q < K1; ++q) {
+        double mo = 0.0, mn = 0.0;
+#pragma unroll
+        for (int j = 0; j < K1; ++j) {
+          const double ph = CB::phi[q][j];
+          const int node = ax ? (j + K1 * (side ? K : 0)) : ((side ? K : 0) + K1 * j);
+          mo = fma(ph, m[node], mo);
+          mn = fma(ph, nm[ax][side][j], mn);
+        }
+        if (!use_n[ax][side]) mn = 0.0;
+        dmu[q] = valid ? (side ? mn - mo : mo - mn) : 0.0;   // mu_2 - mu_1
+      }
+      const double* R1 = X + (side * 2 + 0) * K1 * N;
+      const double* R2 = X + (side * 2 + 1) * K1 * N;
+      if (ax == 0) {
+        // x face: dJ/dU_F = t_adv W (H(m) c1 + (1 - H(m)) c2), c = W^T f
+        double d[K1];
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+          double c1 = 0.0, c2 = 0.0;
+#pragma unroll
+          for (int j = 0; j <= LMAX; ++j) {
+            c1 = fma(wcol[j], R1[q * N + mem[j]], c1);
+            c2 = fma(wcol[j], R2[q * N + mem[j]], c2);
+          }
+          const double h = heav(xr[9 + side] + t_adv * lam * pr[0 + q]);
+          d[q] = t_adv * (h * c1 + (1.0 - h) * c2);
+        }
+        __syncthreads();
+        if (in_grp)
+#pragma unroll
+          for (int q = 0; q < K1; ++q) X[((side * 2 + 0) * K1 + q) * N + r] = d[q];
+        __syncthreads();
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+          double dj = 0.0;
+#pragma unroll
+          for (int i = 0; i <= LMAX; ++i) dj = fma(wrow[i], R1[q * N + mem[i]], dj);
+          acc = fma(gw[q] * dmu[q], dj, acc);
+        }
+        if (in_grp) Rd[(S::XF + side) * N + r] = acc / s2hp;
+      } else {
+        // ln p face: dJ = dB_+ (f1 - f2) + dB f2 (dB f1 where B >= 0)
+        const double tmv = pr[12 + side];     // t_mom / V at this face
+#pragma unroll
+        for (int q = 0; q < K1; ++q) {
+          const int code = pcode[side][q];
+          const double* Pu = (code == -1) ? R1 + q * N : R2 + q * N;
+          double ja = -t_mom * tmv * fma(axv0, Pu[axc0], axv1 * Pu[axc1]);
+          double ju = -t_mom * fma(axxv0, Pu[axxc0], fma(axxv1, Pu[r], axxv2 * Pu[axxc1]));
+          if (code >= 0) {
+            // dB_+ (f1 - f2) from the rows of the derivative tables of B_+
+            const double* ta = F.pf_dtab + ((size_t)code * 2 * N + r) * (LMAX + 1);
+            const double* tx = ta + (size_t)N * (LMAX + 1);
+            double dkA = 0.0, dkX = 0.0;
+#pragma unroll
+            for (int i = 0; i <= LMAX; ++i) {
+              const double dfi = R1[q * N + mem[i]] - R2[q * N + mem[i]];
+              dkA = fma(ta[i], dfi, dkA);
+              dkX = fma(tx[i], dfi, dkX);
             }
+            ja = fma(-t_mom * tmv, dkA, ja);
+            ju = fma(-t_mom, dkX, ju);
+          }
+          if (in_grp) {
+            Rd[(S::PF + side * 2 * K1 + 2 * q + 0) * N + r] = gw[q] * dmu[q] * ja / s2hx;
+            Rd[(S::PF + side * 2 * K1 + 2 * q + 1) * N + r] = gw[q] * dmu[q] * ju / s2hx;
           }
         }
-        double dkA = 0.0, dkX = 0.0;
-        for (int k = 0; k < bsz; ++k) {
-          dkA = fma(Q[pos * bsz + k], zA[k], dkA);
-          dkX = fma(Q[pos * bsz + k], zX[k], dkX);
-        }
-        ja = fma(-t_mom * tmv, dkA, ja);
-        ju = fma(-t_mom, dkX, ju);
       }
-      acc_a[q0] = gw[q0] * (m2 - m1) * ja;
-      acc_u[q0] = gw[q0] * (m2 - m1) * ju;
-      __syncthreads();
     }
-    if (in_grp)
-      for (int q0 = 0; q0 < K1; ++q0) {
-        Rd[(2 * q0 + 0) * N + r] = valid ? acc_a[q0] : 0.0;
-        Rd[(2 * q0 + 1) * N + r] = valid ? acc_u[q0] : 0.0;
-      }
-    __syncthreads();
-    if (valid)
-      for (int o = r; o < 2 * K1; o += N) {
-        double sum = 0.0;
-        for (int j = 0; j < N; ++j) sum += Rd[o * N + j];
-        out[S::PF + side * 2 * K1 + o] += cdt * sum / s2hx;
-      }
     __syncthreads();
   }
+
+  // ---- one reduction over the cell's lanes for every slot --------------------
+  __syncthreads();
+  if (act)
+    for (int o = r; o < NS; o += N) {
+      double sum = 0.0;
+      for (int j = 0; j < N; ++j) sum += Rd[o * N + j];
+      slots[(size_t)cell * NS + o] += cdt * sum;
+    }
 }
 
 // g_u, g_dudx, g_dudt at the nx (k+1) x Gauss points and g_uface at the nx+1
@@ -369,12 +337,9 @@ __global__ void fgrad_reduce_kernel(MeshArgs M, const double* __restrict__ slots
     double su = 0.0, sd = 0.0, sa = 0.0;
     for (int ip = 0; ip < np; ++ip) {
       const double* o = slots + (size_t)(ip * nx + ix) * S::SIZE;
-      for (int q1 = 0; q1 < K1; ++q1) {
-        const int q = q0 + K1 * q1;
-        su += o[S::VOL + 3 * q + 0];
-        sd += o[S::VOL + 3 * q + 1];
-        sa += o[S::VOL + 3 * q + 2];
-      }
+      su += o[S::VOL + 3 * q0 + 0];
+      sd += o[S::VOL + 3 * q0 + 1];
+      sa += o[S::VOL + 3 * q0 + 2];
       sa += o[S::PF + 2 * q0 + 0] + o[S::PF + 2 * K1 + 2 * q0 + 0];
       sd += o[S::PF + 2 * q0 + 1] + o[S::PF + 2 * K1 + 2 * q0 + 1];
     }

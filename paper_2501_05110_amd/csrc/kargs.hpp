@@ -78,7 +78,7 @@ struct FieldArgs {
   const int* pf_code;
   const double* pf_coded;   // the same codes as doubles (staged into LDS as is)
   const double* pf_tab;
-  const double* pf_eig;     // [code] per m block: eigenvalues, then eigenvectors (row-major)
+  const double* pf_dtab;    // [code][2][n][lmax+1] rows of dB_+ in the directions A^x, (A^xA^x)_t
   // packed per-cell-row scalars for the (x, ln p) kernel (kRec doubles each):
   // xrec[ix]: t_adv (2/h_x) U(x_q) [3], U'(x_q) [3], t_mom dU/dt(x_q) [3],
   //           t_adv U at the lo / hi face [2], 2/h_x, gradient flag

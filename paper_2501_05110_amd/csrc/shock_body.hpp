@@ -46,6 +46,12 @@ namespace shock {
 #ifndef VFP_SHOCK_WAVES
 #define VFP_SHOCK_WAVES 1
 #endif
+#ifndef VFP_NT_STORE
+#define VFP_NT_STORE 1
+#endif
+#ifndef VFP_NT_LOAD_U
+#define VFP_NT_LOAD_U 0
+#endif
 
 // per-cell scalar record in LDS (doubles): the packed x record of the cell's
 // x column, the packed p record of its p row, the p-face codes and nu
@@ -100,7 +106,8 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   constexpr int XR = (ADJ ? 3 : 2) * K1;   // exchange rows per cell
   using CB = CBasis<K>;
   static_assert(K1 <= 3, "basis tables");
-  __shared__ double shx[CPB * XR * N];
+  constexpr int XS = XR * N;           // per-cell exchange area
+  __shared__ double shx[CPB * XS];
   __shared__ double shs[CPB * S_STRIDE];
 
   const int tid = threadIdx.x;
@@ -116,7 +123,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   const int nx = M.n[0], np = M.n[1];
   const int ix = cell % nx, ip = cell / nx;
   const int clc = in_grp ? cl : 0;
-  double* X = shx + clc * XR * N;
+  double* X = shx + clc * XS;
   double* sc = shs + clc * S_STRIDE;
 
   // ---- issue every global load, in order of first use ------------------------
@@ -141,7 +148,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   const auto win = gp(A.st.w_in) + cbase;
   double w[NB];
 #pragma unroll
-  for (int b = 0; b < NB; ++b) w[b] = act ? win[(size_t)b * N] : 0.0;
+  for (int b = 0; b < NB; ++b) w[b] = win[(size_t)b * N];   // lanes past the end read cell 0
 
   // neighbour traces: tn[axis][side][j]; x faces carry nodes along p, p faces
   // nodes along x.  Boundary sides are resolved to 0 (zero inflow) or the own
@@ -162,7 +169,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
       for (int j = 0; j < K1; ++j) {
         const int node = ax ? (j + K1 * jn) : (jn + K1 * j);
-        tn[ax][side][j] = (act && use_n[ax][side]) ? nb0[(size_t)node * N] : 0.0;
+        tn[ax][side][j] = nb0[(size_t)node * N];   // a valid cell; unused where !use_n
       }
     }
 
@@ -360,12 +367,18 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   double uu[NB];
   const bool use_u = A.st.alpha != 0.0;
 #pragma unroll
-  for (int b = 0; b < NB; ++b) uu[b] = (act && use_u) ? gp(A.st.u)[cbase + (size_t)b * N] : 0.0;
+  for (int b = 0; b < NB; ++b) {
+#if VFP_NT_LOAD_U
+    uu[b] = use_u ? __builtin_nontemporal_load(&gp(A.st.u)[cbase + (size_t)b * N]) : 0.0;
+#else
+    uu[b] = use_u ? gp(A.st.u)[cbase + (size_t)b * N] : 0.0;
+#endif
+  }
   double ff[ADJ ? NB : 1];
   const bool use_g = ADJ && gp(A.adj.fwd) && gp(A.adj.grad_nu);
   if constexpr (ADJ) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) ff[b] = (act && use_g) ? gp(A.adj.fwd)[cbase + (size_t)b * N] : 0.0;
+    for (int b = 0; b < NB; ++b) ff[b] = use_g ? gp(A.adj.fwd)[cbase + (size_t)b * N] : 0.0;
   }
 
   // ---- volume, one row of Gauss points (fixed q1) at a time -----------------
@@ -632,7 +645,16 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   if (act) {
     const double al = A.st.alpha, be = A.st.beta;
 #pragma unroll
-    for (int b = 0; b < NB; ++b) gp(A.st.w_out)[cbase + (size_t)b * N] = fma(be, res[b], al * uu[b]);
+    for (int b = 0; b < NB; ++b) {
+      const double v = fma(be, res[b], al * uu[b]);
+#if VFP_NT_STORE
+      // the stage output is not read again in this launch: streaming stores
+      // keep it from displacing the neighbour traces in L2
+      __builtin_nontemporal_store(v, &gp(A.st.w_out)[cbase + (size_t)b * N]);
+#else
+      gp(A.st.w_out)[cbase + (size_t)b * N] = v;
+#endif
+    }
   }
 }
 

@@ -349,8 +349,16 @@ __device__ __forceinline__ void adj_flux_axis(const KernelArgs& A, const LaneRow
   contract_add<D, K, -1>(tmp, res, A.mesh.s2h[AX][ic[AX]]);
 }
 
+// At least two waves per SIMD: the 3-D, k = 2 instantiations otherwise take
+// every register for one wave (27 nodes per lane); the few spills cost less
+// than the lost latency hiding.
+#ifndef VFP_GENERAL_WAVES
+#define VFP_GENERAL_WAVES 2
+#endif
+
 template <int D, int K, int LMAX, bool MOM, bool XPROF, bool ADJ>
-__global__ __launch_bounds__(kThreads) void stage_kernel(KernelArgs A) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(VFP_GENERAL_WAVES)))
+void stage_kernel(KernelArgs A) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
   constexpr int NB = IPow<K1, D>::v;

@@ -191,7 +191,7 @@ struct vfp_ctx {
   // device data
   DevBuf d_s2h[3], d_u_vol, d_du_vol, d_a_vol, d_u_face;
   DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face;
-  DevBuf d_pf_code, d_pf_coded, d_pf_tab, d_pf_eig, d_Bpts, d_nu, d_src;
+  DevBuf d_pf_code, d_pf_coded, d_pf_tab, d_pf_dtab, d_Bpts, d_nu, d_src;
   DevBuf d_itab, d_dtab, d_xrec, d_prec;
   RowTables tab{};
   FieldArgs fld{};
@@ -549,14 +549,10 @@ int build_pface_data(vfp_ctx* c) {
     inv_v[f] = gam * c->mass / p;
   }
   const size_t rowsz = (size_t)n * (L + 1);
-  // eigen-data of a mixed point: per m block, eigenvalues then eigenvectors
-  // (row-major, column e = eigenvector e), for the field gradients
-  size_t eigsz = 0;
-  for (int m = 0; m <= L; ++m) eigsz += (size_t)(L - m + 1) * (L - m + 2);
   struct Part {
     std::vector<int> code_ix;            // [ix - lo][f]
     std::vector<double> tab;             // rows of mixed-sign points, in (ix, f) order
-    std::vector<double> eig;             // eigen-data of the same points
+    std::vector<double> dtab;            // rows of dB_+[A^x], dB_+[(A^xA^x)_t] of the same points
     double bmax = 0.0;
   };
   const int nth = std::max(1, std::min(host_threads(), nxp));
@@ -565,7 +561,7 @@ int build_pface_data(vfp_ctx* c) {
     const int lo = (int)((long long)nxp * t / nth), hi = (int)((long long)nxp * (t + 1) / nth);
     Part& P = parts[t];
     P.code_ix.assign((size_t)(hi - lo) * npf, -1);
-    std::vector<double> rows(rowsz);
+    std::vector<double> rows(rowsz), drows(rowsz);
     double a[kBlk][kBlk], v[kBlk][kBlk];
     for (int ix = lo; ix < hi; ++ix) {
       const double av = c->planar ? c->a_vol[ix] : 0.0;
@@ -613,11 +609,36 @@ int build_pface_data(vfp_ctx* c) {
           }
           cd = (int)(P.tab.size() / rowsz);     // local index, offset on merge
           P.tab.insert(P.tab.end(), rows.begin(), rows.end());
-          for (int m = 0; m <= L; ++m) {
-            const int bsz = L - m + 1;
-            for (int i = 0; i < bsz; ++i) P.eig.push_back(ev[m][i]);
-            for (int i = 0; i < bsz; ++i)
-              for (int e = 0; e < bsz; ++e) P.eig.push_back(vec[m][i][e]);
+          // derivatives of B_+ in the directions A^x and (A^xA^x)_t
+          // (Daleckii-Krein): Q (Gamma o Q^T dB Q) Q^T with
+          // Gamma_kl = (l_k^+ - l_l^+) / (l_k - l_l), H(l_k) where equal
+          for (int dir = 0; dir < 2; ++dir) {
+            std::fill(drows.begin(), drows.end(), 0.0);
+            for (int m = 0; m <= L; ++m) {
+              const int bsz = L - m + 1;
+              const double* db = (dir == 0 ? ab.data() : xb.data()) + (size_t)m * kBlk * kBlk;
+              double D[kBlk][kBlk];
+              for (int k = 0; k < bsz; ++k)
+                for (int l = 0; l < bsz; ++l) {
+                  double acc = 0.0;
+                  for (int i = 0; i < bsz; ++i)
+                    for (int j = 0; j < bsz; ++j) acc += vec[m][i][k] * db[i * kBlk + j] * vec[m][j][l];
+                  const double lk = ev[m][k], ll = ev[m][l], dl = lk - ll;
+                  const double gam = std::fabs(dl) > 1e-14 * (std::fabs(lk) + std::fabs(ll))
+                                         ? (std::max(lk, 0.0) - std::max(ll, 0.0)) / dl
+                                         : (lk > 0 ? 1.0 : (lk < 0 ? 0.0 : 0.5));
+                  D[k][l] = gam * acc;
+                }
+              for (int i = 0; i < bsz; ++i)
+                for (int j = 0; j < bsz; ++j) {
+                  double acc = 0.0;
+                  for (int k = 0; k < bsz; ++k)
+                    for (int l = 0; l < bsz; ++l) acc += vec[m][i][k] * D[k][l] * vec[m][j][l];
+                  for (int s = 0; s <= (m ? 1 : 0); ++s)
+                    drows[(size_t)lms_index(m + i, m, s) * (L + 1) + j] = acc;
+                }
+            }
+            P.dtab.insert(P.dtab.end(), drows.begin(), drows.end());
           }
         }
         P.code_ix[(size_t)(ix - lo) * npf + f] = cd;
@@ -632,7 +653,7 @@ int build_pface_data(vfp_ctx* c) {
     for (auto& x : th) x.join();
   }
   std::vector<int> code((size_t)nxp * npf, -1);
-  std::vector<double> tab, eig;
+  std::vector<double> tab, dtab;
   c->beta_pmax = 0.0;
   for (int t = 0; t < nth; ++t) {
     const int lo = (int)((long long)nxp * t / nth), hi = (int)((long long)nxp * (t + 1) / nth);
@@ -644,7 +665,7 @@ int build_pface_data(vfp_ctx* c) {
         code[(size_t)f * nxp + ix] = cd >= 0 ? cd + off : cd;
       }
     tab.insert(tab.end(), P.tab.begin(), P.tab.end());
-    eig.insert(eig.end(), P.eig.begin(), P.eig.end());
+    dtab.insert(dtab.end(), P.dtab.begin(), P.dtab.end());
     c->beta_pmax = std::max(c->beta_pmax, P.bmax);
   }
   if (int e = upload_vec(c->d_pf_code, code)) return e;
@@ -652,8 +673,8 @@ int build_pface_data(vfp_ctx* c) {
   if (int e = upload_vec(c->d_pf_coded, coded)) return e;
   if (tab.empty()) tab.assign(rowsz, 0.0);
   if (int e = upload_vec(c->d_pf_tab, tab)) return e;
-  if (eig.empty()) eig.assign(eigsz, 0.0);
-  if (int e = upload_vec(c->d_pf_eig, eig)) return e;
+  if (dtab.empty()) dtab.assign(2 * rowsz, 0.0);
+  if (int e = upload_vec(c->d_pf_dtab, dtab)) return e;
   return VFP_OK;
 }
 
@@ -764,7 +785,7 @@ int refresh(vfp_ctx* c, unsigned what) {
   F.xrec = c->d_xrec.as<double>();
   F.prec = c->d_prec.as<double>();
   F.pf_tab = c->d_pf_tab.as<double>();
-  F.pf_eig = c->d_pf_eig.as<double>();
+  F.pf_dtab = c->d_pf_dtab.as<double>();
   for (int i = 0; i < 3; ++i) F.B[i] = c->B[i];
   F.B_pts = c->have_Bpts ? c->d_Bpts.as<double>() : nullptr;
   F.nu0 = c->nu0;

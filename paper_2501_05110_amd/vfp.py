@@ -419,9 +419,11 @@ def planar_shock_fields(op: "Operator", U0, r, w):
 def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: int = None, flow=None):
     """u_N = RK4^N(u0) with the scattering frequency nu_cell (one value per
     cell) and, optionally, the planar flow flow = (u, dudx, dudt, u_face) as
-    differentiable inputs: backward returns their gradients from the
-    checkpointed discrete adjoint of the library (the flow sensitivities from
-    vfp_field_grad_*)."""
+    differentiable inputs: backward returns their gradients from the discrete
+    adjoint of the library (the flow sensitivities from vfp_field_grad_*).
+    seg: steps per checkpoint segment (default ceil(sqrt(nsteps))); with
+    seg >= nsteps the forward keeps the whole stage tape (4 nsteps vectors)
+    and the reverse pass replays nothing."""
     import torch
     if _AdvanceFn.fn is None:
         class AdvanceFn(torch.autograd.Function):
@@ -431,11 +433,18 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
                     op.set_flow_planar(*(t.detach().cpu().numpy() for t in (u_q, du_q, a_q, u_f)))
                 op.set_scattering(nu.detach().cpu().numpy())
                 N = op.ndofs
-                nseg = -(-nsteps // seg)
                 u = u0.detach().clone().contiguous()
-                ckpt = torch.empty(max(nseg, 1) * N, dtype=torch.float64, device=u.device)
-                work = torch.empty(2 * N, dtype=torch.float64, device=u.device)
-                op.forward_checkpoints(u, dt, nsteps, seg, ckpt, work)
+                if seg >= nsteps and nsteps > 0:
+                    # whole stage tape: slot 4 nsteps - 1 is the final state
+                    ckpt = torch.empty((4 * nsteps + 1) * N, dtype=torch.float64, device=u.device)
+                    ckpt[:N].copy_(u)
+                    op.advance_tape(ckpt[:N], dt, nsteps, ckpt[N:])
+                    u = ckpt[4 * nsteps * N:].clone()
+                else:
+                    nseg = -(-nsteps // seg)
+                    ckpt = torch.empty(max(nseg, 1) * N, dtype=torch.float64, device=u.device)
+                    work = torch.empty(2 * N, dtype=torch.float64, device=u.device)
+                    op.forward_checkpoints(u, dt, nsteps, seg, ckpt, work)
                 ctx.op, ctx.dt, ctx.nsteps, ctx.seg, ctx.has_flow = op, dt, nsteps, seg, has_flow
                 ctx.nu = nu.detach().cpu().numpy().copy()
                 ctx.flow = tuple(t.detach().cpu().numpy().copy() for t in (u_q, du_q, a_q, u_f)) \
@@ -455,7 +464,13 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
                 grad_nu = torch.zeros(op.ncells, dtype=torch.float64, device=dev)
                 slots = torch.zeros(op.field_grad_size(), dtype=torch.float64, device=dev) \
                     if ctx.has_flow else None
-                if ctx.nsteps > 0:
+                if ctx.nsteps > 0 and ctx.seg >= ctx.nsteps:
+                    work = torch.empty(3 * N, dtype=torch.float64, device=dev)
+                    op.mass(lam, lam, inverse=True)
+                    op.adjoint_steps(ckpt[:N], ckpt[N:], ctx.dt, ctx.nsteps, lam, grad_nu, work,
+                                     field_slots=slots)
+                    op.mass(lam, lam, inverse=False)
+                elif ctx.nsteps > 0:
                     tape = torch.empty(4 * min(ctx.seg, ctx.nsteps) * N, dtype=torch.float64, device=dev)
                     work = torch.empty(3 * N, dtype=torch.float64, device=dev)
                     op.adjoint_checkpointed(ckpt, ctx.dt, ctx.nsteps, ctx.seg, tape, lam, grad_nu, work,

@@ -183,6 +183,14 @@ def test_autograd_function(lib, cuda):
     uN = vfp.advance_with_grad(op, u0, tnu, dt, n, seg=5)
     loss = 0.5 * ((uN[tsel] - torch.from_numpy(target).cuda()) ** 2).sum()
     loss.backward()
+    # the whole-tape form (seg >= n) gives the same gradients
+    u0b = torch.from_numpy(z0).cuda().requires_grad_(True)
+    tnub = torch.from_numpy(nu.copy()).cuda().requires_grad_(True)
+    uNb = vfp.advance_with_grad(op, u0b, tnub, dt, n, seg=n)
+    (0.5 * ((uNb[tsel] - torch.from_numpy(target).cuda()) ** 2).sum()).backward()
+    assert torch.equal(uNb, uN)
+    assert rel_inf(u0b.grad.cpu().numpy(), u0.grad.cpu().numpy()) <= 1e-14
+    assert rel_inf(tnub.grad.cpu().numpy(), tnu.grad.cpu().numpy()) <= 1e-14
     S = dg.assemble(wl)
     zN = dg.rk4(S, z0, dt, n)
     gN = np.zeros(wl.ndofs)
