@@ -14,8 +14,10 @@ HBM roofline fraction (algorithmic bytes / measured launch time, against
                   [--no-other] [--batch-full] [--copy-probe]
 
 It also reports the adjoint: a 1000-step forward run of the 512 x 64 shock
-and its checkpointed reverse pass (gradients w.r.t. the initial state and
-nu per cell), with the reverse / forward time ratio, and the batched path:
+and its reverse pass (gradients w.r.t. the initial state and nu per cell,
+and with the flow sensitivities for the shock profile), from sqrt(N)
+checkpoints and from the whole stage tape (151 GB here; the default where
+it fits), with the reverse / forward time ratios, and the batched path:
 512 small shock runs of mixed k and l_max advanced by one launch per stage
 and class against one run per launch sequence (--batch-full: the 256 runs
 of 128-1024 x 32-128 cells), and the stage throughput of the 3-D box
@@ -171,7 +173,15 @@ def adjoint_timing(steps=1000):
         del full_tape
         taped = {"tape_GB": need / 1e9, "forward_taped_s": t_tf, "reverse_s": t_tr, "reverse_with_flow_s": t_trf,
                  "reverse_over_forward": t_tr / t_fwd, "reverse_with_flow_over_forward": t_trf / t_fwd}
-    return {"workload": wl.name, "ndofs": N, "steps": steps, "segment": seg,
+    # the mode a reverse pass takes by default on this GPU (advance_with_grad)
+    default_mode = "full_tape" if vfp.grad_segment(op, steps, dev) >= steps else "checkpointed"
+    if default_mode == "full_tape" and taped:
+        dflt = {"mode": default_mode, "reverse_over_forward": taped["reverse_over_forward"],
+                "reverse_with_flow_over_forward": taped["reverse_with_flow_over_forward"]}
+    else:
+        dflt = {"mode": "checkpointed", "reverse_over_forward": t_rev / t_fwd,
+                "reverse_with_flow_over_forward": t_full / t_fwd}
+    return {"workload": wl.name, "ndofs": N, "steps": steps, "segment": seg, "default": dflt,
             "forward_s": t_fwd, "forward_checkpointed_s": t_ck, "reverse_s": t_rev,
             "reverse_over_forward": t_rev / t_fwd,
             "reverse_with_flow_s": t_full, "reverse_with_flow_over_forward": t_full / t_fwd,

@@ -40,6 +40,15 @@ namespace {
 
 constexpr int kFgThreads = 64;
 
+// The workgroup is one wavefront: LDS operations of a wavefront complete in
+// order, so ordering the exchanges needs only a wavefront-scope fence (no
+// wait for outstanding global loads, as a workgroup barrier would imply).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int K>
 struct GSlots {
   static constexpr int K1 = K + 1;
@@ -122,44 +131,43 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
 #pragma unroll
   for (int i = 0; i < 3 * K1; ++i) part[i] = 0.0;
 
-  // ---- volume: sum factorisation along x, then one row of points at a time
-  double tw[NB], tm[NB], tx[NB];            // [q0 + K1 j1]
-#pragma unroll
-  for (int j1 = 0; j1 < K1; ++j1)
-#pragma unroll
-    for (int q0 = 0; q0 < K1; ++q0) {
-      double a = 0.0, b = 0.0, c = 0.0;
-#pragma unroll
-      for (int j0 = 0; j0 < K1; ++j0) {
-        a = fma(CB::phi[q0][j0], w[j0 + K1 * j1], a);
-        b = fma(CB::phi[q0][j0], m[j0 + K1 * j1], b);
-        c = fma(CB::dphi[q0][j0], m[j0 + K1 * j1], c);
-      }
-      tw[q0 + K1 * j1] = a;
-      tm[q0 + K1 * j1] = b;
-      tx[q0 + K1 * j1] = c;
-    }
+  // ---- volume, one row of Gauss points (fixed q1) at a time: interpolate
+  // along ln p first (K1 values per row), then along x
 #pragma unroll
   for (int q1 = 0; q1 < K1; ++q1) {
+    double wy[K1], my[K1], mdy[K1];
+#pragma unroll
+    for (int j0 = 0; j0 < K1; ++j0) {
+      double a = 0.0, b = 0.0, c = 0.0;
+#pragma unroll
+      for (int j1 = 0; j1 < K1; ++j1) {
+        a = fma(CB::phi[q1][j1], w[j0 + K1 * j1], a);
+        b = fma(CB::phi[q1][j1], m[j0 + K1 * j1], b);
+        c = fma(CB::dphi[q1][j1], m[j0 + K1 * j1], c);
+      }
+      wy[j0] = a;
+      my[j0] = b;
+      mdy[j0] = c;
+    }
     double fq[K1];
 #pragma unroll
     for (int q0 = 0; q0 < K1; ++q0) {
       double f = 0.0;
 #pragma unroll
-      for (int j1 = 0; j1 < K1; ++j1) f = fma(CB::phi[q1][j1], tw[q0 + K1 * j1], f);
+      for (int j0 = 0; j0 < K1; ++j0) f = fma(CB::phi[q0][j0], wy[j0], f);
       fq[q0] = f;
       if (in_grp) X[q0 * N + r] = f;
     }
-    __syncthreads();
+    wave_sync();
     const double iV = pr[3 + q1], pid = pr[6 + q1];
 #pragma unroll
     for (int q0 = 0; q0 < K1; ++q0) {
       double mq = 0.0, mx = 0.0, mp = 0.0;
 #pragma unroll
-      for (int j1 = 0; j1 < K1; ++j1) {
-        mq = fma(CB::phi[q1][j1], tm[q0 + K1 * j1], mq);
-        mx = fma(CB::phi[q1][j1], tx[q0 + K1 * j1], mx);
-        mp = fma(CB::dphi[q1][j1], tm[q0 + K1 * j1], mp);
+      for (int j0 = 0; j0 < K1; ++j0) {
+        mq = fma(CB::phi[q0][j0], my[j0], mq);
+        mx = fma(CB::dphi[q0][j0], my[j0], mx);
+        mp = fma(CB::phi[q0][j0], mdy[j0], mp);
       }
       const double* P = X + q0 * N;
       const double f = fq[q0];
@@ -173,7 +181,7 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
       part[S::VOL + 3 * q0 + 2] +=
           wq * (-mq * t_mom * (iV * G1f - pid * Axf) - s2hp * t_mom * t_mom * mp * iV * Axf);
     }
-    __syncthreads();
+    wave_sync();
   }
 
   if (in_grp)
@@ -231,7 +239,7 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
         }
       }
     }
-    __syncthreads();
+    wave_sync();
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
@@ -266,11 +274,11 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
           const double h = heav(xr[9 + side] + t_adv * lam * pr[0 + q]);
           d[q] = t_adv * (h * c1 + (1.0 - h) * c2);
         }
-        __syncthreads();
+        wave_sync();
         if (in_grp)
 #pragma unroll
           for (int q = 0; q < K1; ++q) X[((side * 2 + 0) * K1 + q) * N + r] = d[q];
-        __syncthreads();
+        wave_sync();
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < K1; ++q) {
@@ -310,11 +318,11 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
         }
       }
     }
-    __syncthreads();
+    wave_sync();
   }
 
   // ---- one reduction over the cell's lanes for every slot --------------------
-  __syncthreads();
+  wave_sync();
   if (act)
     for (int o = r; o < NS; o += N) {
       double sum = 0.0;

@@ -391,6 +391,17 @@ def checkpoint_segment(nsteps: int) -> int:
     return max(1, int(math.ceil(math.sqrt(max(nsteps, 1)))))
 
 
+def grad_segment(op: "Operator", nsteps: int, device=None, reserve: int = 16 << 30) -> int:
+    """Steps per checkpoint segment for a reverse pass on `device`: the whole
+    stage tape (nsteps, no replay) when its 4 nsteps + 1 state vectors fit in
+    the device's free memory with `reserve` bytes to spare, else sqrt(N)
+    checkpointing (one replay of the forward run)."""
+    import torch
+    need = (4 * max(nsteps, 1) + 1) * op.ndofs * 8
+    free, _ = torch.cuda.mem_get_info(device)
+    return max(nsteps, 1) if need + reserve <= free else checkpoint_segment(nsteps)
+
+
 class _AdvanceFn:
     """Namespace for the autograd function (built lazily so that importing
     this module does not need torch)."""
@@ -421,9 +432,10 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
     cell) and, optionally, the planar flow flow = (u, dudx, dudt, u_face) as
     differentiable inputs: backward returns their gradients from the discrete
     adjoint of the library (the flow sensitivities from vfp_field_grad_*).
-    seg: steps per checkpoint segment (default ceil(sqrt(nsteps))); with
-    seg >= nsteps the forward keeps the whole stage tape (4 nsteps vectors)
-    and the reverse pass replays nothing."""
+    seg: steps per checkpoint segment; with seg >= nsteps the forward keeps
+    the whole stage tape (4 nsteps vectors) and the reverse pass replays
+    nothing.  Default: the whole tape when it fits in free device memory,
+    else ceil(sqrt(nsteps)) (grad_segment)."""
     import torch
     if _AdvanceFn.fn is None:
         class AdvanceFn(torch.autograd.Function):
@@ -485,7 +497,7 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
                 return (lam, grad_nu) + gf + (None, None, None, None, None)
         _AdvanceFn.fn = AdvanceFn
     import torch as _t
-    seg = checkpoint_segment(nsteps) if seg is None else int(seg)
+    seg = grad_segment(op, nsteps, u0.device) if seg is None else int(seg)
     if flow is None:
         z = _t.zeros(1, dtype=_t.float64, device=u0.device)
         return _AdvanceFn.fn.apply(u0, nu_cell, z, z, z, z, op, float(dt), int(nsteps), seg, False)

@@ -5,8 +5,9 @@
   central differences of the oracle's forward run with that one flow value
   perturbed (the oracle samples the flow callable at the same points).
 * dJ/d(r, w) (and dJ/dnu per cell) through advance_with_grad and
-  planar_shock_fields, against central differences of the oracle in seeded
-  directions of (nu, r, w) -- 1e-6 relative.
+  planar_shock_fields, against central differences of the oracle in 16 seeded
+  directions of (nu, r, w) -- 1e-6 relative -- with nu perturbed in log space
+  and no upwind decision reversed between the two sides of a difference.
 The sampled points include ones inside the shock, where the ln p face
 matrix is indefinite (the spectral-derivative branch).
 """
@@ -38,6 +39,24 @@ def _perturbed(base, which, x0, h):
         return U, dU, a
     flow.kind = base.kind
     return flow
+
+
+def _upwind_signs(wl):
+    """Signs of the eigenvalues of n.beta at every face point of every cell
+    (0 where an eigenvalue vanishes to rounding): the upwind decisions."""
+    g = dg.Grid(wl)
+    out = []
+    for c in range(g.ncells):
+        idx = g.cell_multi(c)
+        for a in range(g.d):
+            for side in (0, 1):
+                _, _, eta, _ = g.face_tables(a, side)
+                XF, pF = g.points(idx, eta)
+                beta, _ = g.coefficients(c, XF, pF)
+                lam = np.linalg.eigvalsh(beta[a])            # [point, n]
+                tol = 1e-12 * max(1.0, float(np.abs(lam).max()))
+                out.append(np.where(np.abs(lam) <= tol, 0.0, np.sign(lam)).ravel())
+    return np.concatenate(out)
 
 
 def _oracle_J(wl, z0, dt, n, g):
@@ -132,7 +151,7 @@ def test_profile_and_nu_gradient_directions(lib, cuda):
     loss = 0.5 * ((uN[tsel] - ttarget) ** 2).sum()
     loss.backward()
     g_nu, g_r, g_w = tnu.grad.cpu().numpy(), float(tr.grad), float(tw.grad)
-    _say(f"[profile] J={float(loss):.6e} dJ/dr={g_r:+.6e} dJ/dw={g_w:+.6e} |dJ/dnu|={np.abs(g_nu).max():.3e}")
+    _say(f"[profile] J={float(loss.detach()):.6e} dJ/dr={g_r:+.6e} dJ/dw={g_w:+.6e} |dJ/dnu|={np.abs(g_nu).max():.3e}")
 
     def J(nu, r, w):
         # the profile (r, w) changes; the injection keeps its width (the
@@ -141,14 +160,25 @@ def test_profile_and_nu_gradient_directions(lib, cuda):
         zN = dg.rk4(dg.assemble(wl2), z0, dt, n).reshape(wl.shape)
         return 0.5 * float(np.sum((zN[sel] - target) ** 2))
 
+    # 16 directions; every fourth leaves out nu, r or w in turn.  nu moves in
+    # log space (nu exp(+-h d) = nu (1 +- h d) to first order, d scaled per
+    # cell), so the directional derivative is g_nu . (nu d).
     rng = np.random.default_rng(33)
     h = 1e-5
-    for d in range(4):
-        dnu = nu0 * rng.standard_normal(nu0.shape) * (d != 0)
-        dr = r0 * rng.standard_normal() * (d != 1)
-        dw = w0 * rng.standard_normal() * (d != 2)
-        fd = (J(nu0 + h * dnu, r0 + h * dr, w0 + h * dw) - J(nu0 - h * dnu, r0 - h * dr, w0 - h * dw)) / (2 * h)
-        ad = float(g_nu @ dnu) + g_r * dr + g_w * dw
+    for d in range(16):
+        dl = rng.standard_normal(nu0.shape) * (d % 4 != 0)
+        dr = r0 * rng.standard_normal() * (d % 4 != 1)
+        dw = w0 * rng.standard_normal() * (d % 4 != 2)
+        nup, num = nu0 * np.exp(h * dl), nu0 * np.exp(-h * dl)
+        pp, pm = (r0 + h * dr, w0 + h * dw), (r0 - h * dr, w0 - h * dw)
+        # the two sides of the difference take the same upwind decisions: no
+        # eigenvalue of n.beta changes sign (one that reaches 0 exactly, where
+        # the tanh tail rounds to 0, multiplies a zero matrix and does not count)
+        sp_ = _upwind_signs(replace(wl, flow=W.shock_flow(U0, *pp)))
+        sm_ = _upwind_signs(replace(wl, flow=W.shock_flow(U0, *pm)))
+        assert not np.any(sp_ * sm_ < 0), f"direction {d}: an upwind decision flips"
+        fd = (J(nup, *pp) - J(num, *pm)) / (2 * h)
+        ad = float(g_nu @ (nu0 * dl)) + g_r * dr + g_w * dw
         err = abs(fd - ad) / max(abs(fd), 1e-30)
         _say(f"   direction {d}: adjoint={ad:+.10e} fd={fd:+.10e} rel={err:.2e}")
         assert err <= FD_TOL, (d, ad, fd)
