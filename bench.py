@@ -11,7 +11,7 @@ HBM roofline fraction (algorithmic bytes / measured launch time, against
 8 TB/s), and the CPU oracle's rate on a bounded sample of the same workload.
 
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-adjoint] [--no-batch]
-                  [--no-other] [--batch-full] [--copy-probe]
+                  [--no-other] [--no-theta] [--batch-full] [--copy-probe]
 
 It also reports the adjoint: a 1000-step forward run of the 512 x 64 shock
 and its reverse pass (gradients w.r.t. the initial state and nu per cell,
@@ -21,7 +21,9 @@ it fits), with the reverse / forward time ratios, and the batched path:
 512 small shock runs of mixed k and l_max advanced by one launch per stage
 and class against one run per launch sequence (--batch-full: the 256 runs
 of 128-1024 x 32-128 cells), and the stage throughput of the 3-D box
-(48^3, k=2, l_max=5) and the 1-D line (64 cells, k=1, l_max=3).
+(48^3, k=2, l_max=5) and the 1-D line (64 cells, k=1, l_max=3), and
+Theta-method steps (Crank-Nicolson, backward Euler) of the 512 x 64 shock at
+10 times the explicit time step.
 """
 
 from __future__ import annotations
@@ -246,6 +248,48 @@ def batch_timing(full=False, steps=None):
             "classes": [{k: c[k] for k in ("k", "lmax", "runs", "tiles", "tile_map")} for c in cls]}
 
 
+def theta_timing(steps=5, cfl_mult=10.0):
+    """Theta-method steps (Crank-Nicolson and backward Euler) of the 512 x 64
+    shock, k=2, l_max=3, at 10 times the explicit time step: restarted GMRES
+    (30 vectors, relative residual 1e-10) whose operator is the fused stage
+    kernel; against the explicit Runge-Kutta run over the same time."""
+    import numpy as np
+    import torch
+    from paper_2501_05110_amd import vfp, workloads as W
+
+    wl = W.config5(steps=steps)
+    op = vfp.Operator(wl)
+    N = op.ndofs
+    dt_exp = op.cfl_dt(wl.courant)
+    dt = cfl_mult * dt_exp
+    dev = torch.device("cuda:0")
+    u0 = torch.from_numpy(np.ascontiguousarray(wl.meta["init"]).ravel()).to(dev)
+    work = torch.empty(op.theta_work_size(30), dtype=torch.float64, device=dev)
+    res = {"workload": wl.name, "ndofs": N, "steps": steps, "dt_over_explicit": cfl_mult}
+    for name, theta in (("crank_nicolson", 0.5), ("backward_euler", 1.0)):
+        u = u0.clone()
+        op.theta_advance(u, dt, 1, theta=theta, tol=1e-10, restart=30, work=work)   # warm-up
+        u.copy_(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = op.theta_advance(u, dt, steps, theta=theta, tol=1e-10, restart=30, work=work)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        if not (st["converged"] and torch.isfinite(u).all()):
+            raise RuntimeError(f"Theta-method {name} did not converge: {st}")
+        res[name] = {"s_per_step": t / steps, "iterations_per_step": st["iterations"] / steps,
+                     "residual": st["residual"]}
+    u = u0.clone()
+    w2 = torch.empty(2 * N, dtype=torch.float64, device=dev)
+    op.advance(u, dt_exp, 5, w2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op.advance(u, dt_exp, int(cfl_mult) * steps, w2)
+    torch.cuda.synchronize()
+    res["explicit_rk4_s_per_equal_time"] = (time.perf_counter() - t0) / steps
+    return res
+
+
 def other_configs():
     """The 3-D periodic box (48^3 cells, k=2, l_max=5, B with random Fourier
     modes; 107,495,424 DoF) and the 1-D periodic line (64 cells, k=1,
@@ -298,6 +342,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the 3-D box and 1-D line legs")
+    ap.add_argument("--no-theta", action="store_true", help="skip the Theta-method (implicit) leg")
     ap.add_argument("--batch-full", action="store_true",
                     help="also time the 256 mixed runs (about 2.3e9 DoF, 52 GB; minutes of set-up)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -388,6 +433,8 @@ def main():
         out["batch"] = batch_timing(full=False)
     if not args.no_other:
         out["other_configs"] = other_configs()
+    if not args.no_theta:
+        out["theta"] = theta_timing()
     if args.batch_full:
         out["batch_full"] = batch_timing(full=True)
     if not args.no_cpu:

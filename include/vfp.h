@@ -270,6 +270,48 @@ int vfp_field_grad_stage(vfp_ctx* ctx, const double* mu, const double* fwd, doub
 int vfp_field_grad_reduce(vfp_ctx* ctx, const double* slots, double* g_u, double* g_dudx, double* g_dudt,
                           double* g_uface, void* stream);
 
+/* --------------------------------------------------- implicit time steps
+ *
+ * The Theta-method of eq. theta-method: each step solves the linear system
+ * of eq. system-matrix-rhs,
+ *     (M + dt Theta D) zeta^n = (M - dt (1 - Theta) D) zeta^{n-1} + dt h,
+ * (fields, and so D and h, constant in time), Theta in [0, 1]: 0 forward
+ * Euler, 1/2 Crank-Nicolson, 1 backward Euler.  The library solves the same
+ * system multiplied by the block-diagonal M^{-1} (exact per cell),
+ *     (I - dt Theta L0) zeta^n = zeta^{n-1} + dt (1 - Theta) L(zeta^{n-1}) + dt Theta M^{-1} h,
+ * with L0 = L without the source, by restarted GMRES (classical
+ * Gram-Schmidt applied twice per Krylov vector) whose operator is the fused
+ * stage kernel; the iterate starts at zeta^{n-1}.  A step is accepted when
+ * the true residual norm is at most tol times the right-hand side's
+ * (Euclidean norms).
+ */
+typedef struct vfp_theta_opts {
+  double theta;       /* in [0, 1]                                            */
+  double tol;         /* relative residual, > 0                               */
+  int restart;        /* Krylov vectors per cycle, 1 .. 64                    */
+  int max_iters;      /* Krylov iterations per step, >= 1                     */
+} vfp_theta_opts;
+
+typedef struct vfp_theta_stats {
+  int64_t iterations; /* Krylov iterations over all steps                     */
+  double residual;    /* largest final relative residual over the steps       */
+  int converged;      /* 1 if every step met tol within max_iters             */
+} vfp_theta_stats;
+
+/* Doubles of device work space for vfp_theta_advance with `restart` vectors:
+ * (restart + 4) ndofs plus a fixed reduction area. */
+int vfp_theta_work_size(const vfp_ctx* ctx, int restart, int64_t* n);
+
+/* Advance u (device, ndofs doubles, in place) by nsteps Theta-method steps.
+ * work: device, at least vfp_theta_work_size doubles (work_len), disjoint
+ * from u.  Unlike the other compute calls this one synchronises `stream`
+ * once per Krylov iteration (the Hessenberg least-squares problem is solved
+ * on the host).  stats (host, may be NULL) reports the iterations and
+ * residuals; a step that does not reach tol within max_iters keeps its last
+ * iterate, the run continues, and stats->converged is 0. */
+int vfp_theta_advance(vfp_ctx* ctx, double* u, double dt, int64_t nsteps, const vfp_theta_opts* opts,
+                      double* work, int64_t work_len, vfp_theta_stats* stats, void* stream);
+
 /* ------------------------------------------------------------------ batches
  *
  * Many independent runs (each its own context: mesh, l_max, k, fields, time

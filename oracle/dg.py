@@ -19,7 +19,8 @@ This is the plain definition of the semi-discrete operator of Sec. 3:
 * advection matrices and reaction matrix of eq. definitions-advection-reaction-eq
   with the momentum axis taken as ln p (beta^{ln p} = beta^p / p) -- a reading of
   "momentum terms adapted accordingly" (Sec. 4, term list);
-* time stepping: classical RK4 on dzeta/dt = M^{-1}(h - D zeta).
+* time stepping: classical RK4 on dzeta/dt = M^{-1}(h - D zeta), and the
+  Theta-method of eq. theta-method / eq. system-matrix-rhs by sparse LU.
 
 Nothing is blocked, fused or reordered; per-cell loops are plain Python.
 """
@@ -472,6 +473,21 @@ def rk4_gradient(sysm: System, zeta0, dt, nsteps, dJ_dzN, dsys=None, with_source
         znew += apply_adjoint(sysm, kb1)
         zbar = znew
     return zbar, gnu
+
+
+def theta_step(sysm: System, zeta, dt, theta, nsteps=1):
+    """Theta-method (eq. theta-method) with time-independent D and h: each
+    step solves the linear system of eq. system-matrix-rhs,
+        (M + dt theta D) zeta^n = (M - dt (1 - theta) D) zeta^{n-1} + dt h,
+    by a sparse LU factorisation of its matrix (direct, so the result is the
+    system's exact solution up to rounding)."""
+    z = np.asarray(zeta, float).ravel().copy()
+    lhs = (sysm.M + (dt * theta) * sysm.D).tocsc()
+    rhs_op = sysm.M - (dt * (1.0 - theta)) * sysm.D
+    lu = spla.splu(lhs)
+    for _ in range(nsteps):
+        z = lu.solve(rhs_op @ z + dt * sysm.h)
+    return z
 
 
 def steady_state(sysm: System):

@@ -23,7 +23,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object
 # packed FP32 instructions stay disabled in every HIP translation unit
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-ffp-contract=fast"]
-SOURCES = ["shtab.cpp", "vfp.cpp", "stage.hip", "stage_shock.hip", "stage_batch.hip", "field_grad.hip"]
+SOURCES = ["shtab.cpp", "vfp.cpp", "stage.hip", "stage_shock.hip", "stage_batch.hip", "field_grad.hip",
+           "krylov.hip"]
 
 
 def _hipcc():

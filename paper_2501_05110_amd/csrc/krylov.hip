@@ -1,0 +1,122 @@
+// Vector kernels of the restarted GMRES that solves the Theta-method system
+// (eq. system-matrix-rhs) for the implicit time step.  The operator of that
+// system is applied by the fused stage kernels; these kernels provide the
+// Krylov-basis arithmetic: several dot products against one vector in one
+// pass, the matching multi-vector update, and plain linear combinations.
+// Reductions are two-stage (fixed partial layout, then one block per result)
+// so that every result is reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+
+namespace vfp {
+namespace {
+
+constexpr int kKryThreads = 256;
+constexpr int kDotChunk = 8;          // basis vectors per block row of a multi-dot
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+// partial[j][blockIdx.x] = sum over this block's elements of V_j . w, for the
+// kDotChunk vectors j = blockIdx.y kDotChunk + c < k
+__global__ __launch_bounds__(kKryThreads) void mdot_partial_kernel(const double* __restrict__ V, int64_t ldv,
+                                                                    int k, const double* __restrict__ w,
+                                                                    int64_t n, double* __restrict__ partial) {
+  const int j0 = blockIdx.y * kDotChunk;
+  double acc[kDotChunk];
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) acc[c] = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; i < n; i += stride) {
+    const double wi = w[i];
+#pragma unroll
+    for (int c = 0; c < kDotChunk; ++c)
+      if (j0 + c < k) acc[c] = fma(V[(int64_t)(j0 + c) * ldv + i], wi, acc[c]);
+  }
+  __shared__ double red[kDotChunk][kKryThreads / 64];
+  const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
+#pragma unroll
+  for (int c = 0; c < kDotChunk; ++c) {
+    const double s = wave_sum(acc[c]);
+    if (lane == 0) red[c][wave] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kDotChunk && j0 + (int)threadIdx.x < k) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kKryThreads / 64; ++q) s += red[threadIdx.x][q];
+    partial[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// out[j] = sum_b partial[j][b]  (one block per j)
+__global__ __launch_bounds__(kKryThreads) void mdot_final_kernel(const double* __restrict__ partial, int nblk,
+                                                                  double* __restrict__ out) {
+  const int j = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nblk; b += kKryThreads) s += partial[(int64_t)j * nblk + b];
+  __shared__ double red[kKryThreads / 64];
+  s = wave_sum(s);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < kKryThreads / 64; ++q) t += red[q];
+    out[j] = t;
+  }
+}
+
+// w += sign * sum_{j<k} coef[j] V_j
+__global__ __launch_bounds__(kKryThreads) void maxpy_kernel(double* __restrict__ w, const double* __restrict__ V,
+                                                             int64_t ldv, int k, const double* __restrict__ coef,
+                                                             double sign, int64_t n) {
+  __shared__ double cs[kKryMaxVectors];
+  for (int j = threadIdx.x; j < k; j += kKryThreads) cs[j] = sign * coef[j];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; i < n; i += stride) {
+    double acc = w[i];
+    for (int j = 0; j < k; ++j) acc = fma(cs[j], V[(int64_t)j * ldv + i], acc);
+    w[i] = acc;
+  }
+}
+
+// out = a x + b y  (out may alias x or y)
+__global__ __launch_bounds__(kKryThreads) void lincomb_kernel(double* out, double a, const double* x, double b,
+                                                               const double* y, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; i < n; i += stride)
+    out[i] = (b == 0.0) ? a * x[i] : fma(a, x[i], b * y[i]);
+}
+
+int grid_for(int64_t n) {
+  const int64_t g = (n + kKryThreads - 1) / kKryThreads;
+  return (int)(g < 1 ? 1 : (g > kKryBlocks ? kKryBlocks : g));
+}
+
+}  // namespace
+
+void kry_mdot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial, double* out,
+              hipStream_t s) {
+  if (k <= 0) return;
+  const dim3 grid(kKryBlocks, (k + kDotChunk - 1) / kDotChunk);
+  hipLaunchKernelGGL(mdot_partial_kernel, grid, dim3(kKryThreads), 0, s, V, ldv, k, w, n, partial);
+  hipLaunchKernelGGL(mdot_final_kernel, dim3(k), dim3(kKryThreads), 0, s, partial, kKryBlocks, out);
+}
+
+void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coef, double sign, int64_t n,
+               hipStream_t s) {
+  if (k <= 0) return;
+  hipLaunchKernelGGL(maxpy_kernel, dim3(grid_for(n)), dim3(kKryThreads), 0, s, w, V, ldv, k, coef, sign, n);
+}
+
+void kry_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for(n)), dim3(kKryThreads), 0, s, out, a, x, b, y ? y : x, n);
+}
+
+}  // namespace vfp

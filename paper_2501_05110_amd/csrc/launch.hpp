@@ -45,6 +45,18 @@ FieldGradLauncher find_field_grad_launcher(int k, int lmax);
 FieldGradReduce find_field_grad_reduce(int k);
 int field_grad_slots_per_cell(int k);
 
+// Krylov-basis vector arithmetic (restarted GMRES of the Theta-method).
+// Vectors j of a basis are V + j ldv.  kry_mdot: out[j] = V_j . w for j < k
+// (partial: kKryMaxVectors * kKryBlocks doubles of scratch); kry_maxpy:
+// w += sign sum_j coef[j] V_j (coef on the device); kry_lincomb: out = a x + b y.
+constexpr int kKryMaxVectors = 72;
+constexpr int kKryBlocks = 1024;
+void kry_mdot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial, double* out,
+              hipStream_t s);
+void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coef, double sign, int64_t n,
+               hipStream_t s);
+void kry_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t s);
+
 hipError_t upload_basis(const Basis1D* b);
 
 int stage_cells_per_block(int lmax);

@@ -1445,6 +1445,204 @@ int vfp_adjoint_checkpointed(vfp_ctx* c, const double* ckpt, double dt, int64_t 
 
 }  // extern "C"
 
+// ====================================================== Theta-method steps
+
+namespace {
+
+// Work layout (doubles): V [(m+1) N] Krylov basis, w [N], b [N] right-hand
+// side, s [N] = M^{-1} h, partial [kKryMaxVectors kKryBlocks], dots
+// [3 kKryMaxVectors].
+struct ThetaWork {
+  double *V, *w, *b, *s, *partial, *d1, *d2, *d3;
+};
+
+int64_t theta_work_len(int64_t N, int m) {
+  return (int64_t)(m + 4) * N + (int64_t)kKryMaxVectors * kKryBlocks + 3 * kKryMaxVectors;
+}
+
+ThetaWork theta_split(double* work, int64_t N, int m) {
+  ThetaWork t;
+  t.V = work;
+  t.w = t.V + (int64_t)(m + 1) * N;
+  t.b = t.w + N;
+  t.s = t.b + N;
+  t.partial = t.s + N;
+  t.d1 = t.partial + (int64_t)kKryMaxVectors * kKryBlocks;
+  t.d2 = t.d1 + kKryMaxVectors;
+  t.d3 = t.d2 + kKryMaxVectors;
+  return t;
+}
+
+// device -> host copy of n doubles, then wait for the stream
+int fetch(double* host, const double* dev, int n, hipStream_t st) {
+  HIP_TRY(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  return VFP_OK;
+}
+
+// w = A x = x - dt Theta L0(x): the stage kernel with u = w_in = x
+int theta_op(vfp_ctx* c, const double* x, double* w, double dt, double theta, void* stream) {
+  return launch(c, x, x, w, 1.0, -dt * theta, 0, stream);
+}
+
+// One Theta step in place on u by restarted GMRES (iterate from u).
+// it: Krylov iterations (accumulated); res: final true relative residual.
+int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const ThetaWork& t, int64_t N,
+               bool have_s, void* stream, int64_t& it, double& res, bool& conv) {
+  hipStream_t st = (hipStream_t)stream;
+  const int m = o.restart;
+  const double th = o.theta;
+  // right-hand side b = u + dt (1 - Theta) L(u) + dt Theta M^{-1} h
+  if (th < 1.0) {
+    if (int e = launch(c, u, u, t.b, 1.0, dt * (1.0 - th), 1, stream)) return e;
+    if (have_s && th > 0.0) kry_lincomb(t.b, dt * th, t.s, 1.0, t.b, N, st);
+  } else if (have_s) {
+    kry_lincomb(t.b, 1.0, u, dt, t.s, N, st);
+  } else {
+    HIP_TRY(hipMemcpyAsync(t.b, u, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+  }
+  conv = false;
+  if (th == 0.0) {   // forward Euler: the system matrix is I
+    HIP_TRY(hipMemcpyAsync(u, t.b, N * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipGetLastError());
+    res = 0.0;
+    conv = true;
+    return VFP_OK;
+  }
+  double bn2 = 0.0;
+  kry_mdot(t.b, N, 1, t.b, N, t.partial, t.d3, st);
+  if (int e = fetch(&bn2, t.d3, 1, st)) return e;
+  const double bn = std::sqrt(bn2);
+  if (bn == 0.0) {
+    kry_lincomb(u, 0.0, u, 0.0, nullptr, N, st);
+    HIP_TRY(hipGetLastError());
+    res = 0.0;
+    conv = true;
+    return VFP_OK;
+  }
+  std::vector<double> H((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m), hb(3 * kKryMaxVectors);
+  int64_t used = 0;
+  for (;;) {
+    // true residual r = b - A u into V_0
+    if (int e = theta_op(c, u, t.w, dt, th, stream)) return e;
+    kry_lincomb(t.V, 1.0, t.b, -1.0, t.w, N, st);
+    kry_mdot(t.V, N, 1, t.V, N, t.partial, t.d3, st);
+    double rn2 = 0.0;
+    if (int e = fetch(&rn2, t.d3, 1, st)) return e;
+    const double beta = std::sqrt(rn2);
+    res = beta / bn;
+    if (!std::isfinite(res)) return fail(VFP_EDEVICE, "non-finite residual in the Theta step");
+    if (res <= o.tol) {
+      conv = true;
+      break;
+    }
+    if (used >= o.max_iters) break;
+    kry_lincomb(t.V, 1.0 / beta, t.V, 0.0, nullptr, N, st);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int j = 0;
+    while (j < m && used < o.max_iters) {
+      // w = A V_j, orthogonalised against V_0..V_j twice
+      if (int e = theta_op(c, t.V + (int64_t)j * N, t.w, dt, th, stream)) return e;
+      kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d1, st);
+      kry_maxpy(t.w, t.V, N, j + 1, t.d1, -1.0, N, st);
+      kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d2, st);
+      kry_maxpy(t.w, t.V, N, j + 1, t.d2, -1.0, N, st);
+      kry_mdot(t.w, N, 1, t.w, N, t.partial, t.d3, st);
+      if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st)) return e;
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i] + hb[kKryMaxVectors + i];
+      const double hn = std::sqrt(std::max(hb[2 * kKryMaxVectors], 0.0));
+      H[(size_t)(j + 1) * m + j] = hn;
+      ++used;
+      // previous Givens rotations, then the one that removes H[j+1][j]
+      for (int i = 0; i < j; ++i) {
+        const double a = H[(size_t)i * m + j], b = H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = cs[i] * a + sn[i] * b;
+        H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * b;
+      }
+      const double a = H[(size_t)j * m + j], b = H[(size_t)(j + 1) * m + j];
+      const double rr = std::hypot(a, b);
+      cs[j] = rr == 0.0 ? 1.0 : a / rr;
+      sn[j] = rr == 0.0 ? 0.0 : b / rr;
+      H[(size_t)j * m + j] = rr;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++j;
+      if (std::fabs(g[j]) <= o.tol * bn || hn == 0.0) break;
+      if (j < m) kry_lincomb(t.V + (int64_t)j * N, 1.0 / hn, t.w, 0.0, nullptr, N, st);
+    }
+    // y = H^{-1} g (upper triangular), u += V y
+    for (int i = j - 1; i >= 0; --i) {
+      double acc = g[i];
+      for (int l = i + 1; l < j; ++l) acc -= H[(size_t)i * m + l] * y[l];
+      const double d = H[(size_t)i * m + i];
+      y[i] = d != 0.0 ? acc / d : 0.0;
+    }
+    HIP_TRY(hipMemcpyAsync(t.d1, y.data(), j * sizeof(double), hipMemcpyHostToDevice, st));
+    kry_maxpy(u, t.V, N, j, t.d1, 1.0, N, st);
+    HIP_TRY(hipGetLastError());
+  }
+  it += used;
+  return VFP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int vfp_theta_work_size(const vfp_ctx* c, int restart, int64_t* n) {
+  if (!c || !n) return fail(VFP_EINVAL, "null argument");
+  if (restart < 1 || restart > 64) return fail(VFP_EINVAL, "restart must be in 1..64");
+  int64_t N = 0;
+  if (int e = vfp_ndofs(c, &N)) return e;
+  *n = theta_work_len(N, restart);
+  return VFP_OK;
+}
+
+int vfp_theta_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, const vfp_theta_opts* o, double* work,
+                      int64_t work_len, vfp_theta_stats* stats, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!u || !work || !o) return fail(VFP_EINVAL, "null argument");
+  if (!(o->theta >= 0.0 && o->theta <= 1.0)) return fail(VFP_EINVAL, "theta must be in [0, 1]");
+  if (!(o->tol > 0.0)) return fail(VFP_EINVAL, "tol must be positive");
+  if (o->restart < 1 || o->restart > 64) return fail(VFP_EINVAL, "restart must be in 1..64");
+  if (o->max_iters < 1) return fail(VFP_EINVAL, "max_iters must be >= 1");
+  if (nsteps < 0 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  const int64_t need = theta_work_len(N, o->restart);
+  if (work_len < need) return fail(VFP_EINVAL, "work holds %lld doubles, %lld needed", (long long)work_len,
+                                   (long long)need);
+  if (overlaps(u, N, work, need)) return fail(VFP_EINVAL, "work overlaps u");
+  const ThetaWork t = theta_split(work, N, o->restart);
+  hipStream_t st = (hipStream_t)stream;
+  const bool have_s = (c->terms & VFP_TERM_SOURCE) && c->have_src && o->theta > 0.0;
+  if (have_s) {
+    // s = M^{-1} h = L(0)
+    HIP_TRY(hipMemsetAsync(t.w, 0, N * sizeof(double), st));
+    if (int e = launch(c, t.w, nullptr, t.s, 0.0, 1.0, 1, stream)) return e;
+  }
+  int64_t it = 0;
+  double worst = 0.0;
+  bool all = true;
+  for (int64_t n = 0; n < nsteps; ++n) {
+    double res = 0.0;
+    bool conv = false;
+    if (int e = theta_step(c, u, dt, *o, t, N, have_s, stream, it, res, conv)) return e;
+    worst = std::max(worst, res);
+    all = all && conv;
+  }
+  if (stats) {
+    stats->iterations = it;
+    stats->residual = worst;
+    stats->converged = all ? 1 : 0;
+  }
+  return VFP_OK;
+}
+
+}  // extern "C"
+
 // ================================================================= batches
 
 struct vfp_batch {

@@ -28,6 +28,16 @@ class VFPError(RuntimeError):
     pass
 
 
+class ThetaOpts(C.Structure):
+    """vfp_theta_opts"""
+    _fields_ = [("theta", C.c_double), ("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int)]
+
+
+class ThetaStats(C.Structure):
+    """vfp_theta_stats"""
+    _fields_ = [("iterations", C.c_int64), ("residual", C.c_double), ("converged", C.c_int)]
+
+
 def load(path: str = None):
     """Load the built library (never builds it)."""
     global _lib
@@ -70,6 +80,8 @@ def load(path: str = None):
         "vfp_field_grad_size": (I, [P, C.POINTER(L)]),
         "vfp_field_grad_stage": (I, [P, P, P, D, P, P]),
         "vfp_field_grad_reduce": (I, [P, P, P, P, P, P, P]),
+        "vfp_theta_work_size": (I, [P, I, C.POINTER(L)]),
+        "vfp_theta_advance": (I, [P, P, D, L, C.POINTER(ThetaOpts), P, L, C.POINTER(ThetaStats), P]),
         "vfp_batch_create": (I, [C.POINTER(P), C.POINTER(P), I, U]),
         "vfp_batch_destroy": (None, [P]),
         "vfp_batch_bind": (I, [P, C.POINTER(P), C.POINTER(P), dp]),
@@ -95,7 +107,8 @@ def exported_symbols():
             "vfp_adjoint_steps", "vfp_forward_checkpoints", "vfp_adjoint_checkpointed",
             "vfp_batch_create", "vfp_batch_destroy", "vfp_batch_bind", "vfp_batch_advance",
             "vfp_batch_autotune", "vfp_batch_nclasses", "vfp_batch_class_info",
-            "vfp_field_grad_size", "vfp_field_grad_stage", "vfp_field_grad_reduce"]
+            "vfp_field_grad_size", "vfp_field_grad_stage", "vfp_field_grad_reduce",
+            "vfp_theta_work_size", "vfp_theta_advance"]
 
 
 def _check(rc):
@@ -310,6 +323,27 @@ class Operator:
             self._ctx, self._t(slots, "slots", self.field_grad_size()), self._t(g_u, "g_u", nq),
             self._t(g_dudx, "g_dudx", nq), self._t(g_dudt, "g_dudt", nq),
             self._t(g_uface, "g_uface", self.wl.ncells_axis[0] + 1), _stream_handle(stream)))
+
+    def theta_work_size(self, restart=30):
+        n = C.c_int64()
+        _check(_lib.vfp_theta_work_size(self._ctx, int(restart), C.byref(n)))
+        return n.value
+
+    def theta_advance(self, u, dt, nsteps, theta=0.5, tol=1e-12, restart=30, max_iters=1000, work=None,
+                      stream=None):
+        """nsteps Theta-method steps in place on u (vfp_theta_advance);
+        returns {"iterations", "residual", "converged"}.  work: device
+        tensor of >= theta_work_size(restart) doubles (allocated if None)."""
+        import torch
+        need = self.theta_work_size(restart)
+        if work is None:
+            work = torch.empty(need, dtype=torch.float64, device=u.device)
+        opts = ThetaOpts(float(theta), float(tol), int(restart), int(max_iters))
+        st = ThetaStats()
+        _check(_lib.vfp_theta_advance(self._ctx, self._t(u, "u"), float(dt), int(nsteps), C.byref(opts),
+                                      self._t(work, "work", need), int(work.numel()), C.byref(st),
+                                      _stream_handle(stream)))
+        return {"iterations": int(st.iterations), "residual": float(st.residual), "converged": bool(st.converged)}
 
     def set_flow_planar(self, u, dudx, dudt, u_face):
         """Replace the planar flow profile (host arrays at the x Gauss points
