@@ -270,6 +270,27 @@ int vfp_field_grad_stage(vfp_ctx* ctx, const double* mu, const double* fwd, doub
 int vfp_field_grad_reduce(vfp_ctx* ctx, const double* slots, double* g_u, double* g_dudx, double* g_dudt,
                           double* g_uface, void* stream);
 
+/* ------------------------------------------------------ reconstruction
+ *
+ * The distribution function from its coefficients (eq. spherical-harmonic-exp):
+ * f(x, p, theta, phi) = sum_lms f_lms(x, p) Y_lms(theta, phi), with the real
+ * spherical harmonics of App. A (eq. spherical-harmonics,
+ * eq. normalisation-spherical-harmonics, Condon-Shortley phase inside P_l^m
+ * as in eq. associated-legendre-polynomials), theta measured from the x axis
+ * and phi about it: p/p = (cos theta, sin theta cos phi, sin theta sin phi).
+ */
+
+/* Host only: Y[d n + lms] = Y_lms(theta[d], phi[d]) for d < ndir,
+ * n = (lmax+1)^2, 0 <= lmax <= 7 (host arrays). */
+int vfp_sh_eval(int lmax, int64_t ndir, const double* theta, const double* phi, double* Y);
+
+/* f at every basis node of every cell in ndir directions:
+ * out[row ndir + d] = sum_lms zeta[row n + lms] Y[d n + lms], row = cell nb + basis
+ * (nb = (k+1)^naxes).  zeta (ndofs doubles), Y (ndir n doubles, e.g. from
+ * vfp_sh_eval) and out (ncells nb ndir doubles) are device arrays. */
+int vfp_reconstruct(const vfp_ctx* ctx, const double* zeta, const double* Y, int64_t ndir, double* out,
+                    void* stream);
+
 /* --------------------------------------------------- implicit time steps
  *
  * The Theta-method of eq. theta-method: each step solves the linear system

@@ -78,6 +78,22 @@ def real_sph_harm(lmax: int, pts):
     return out
 
 
+def directions(theta, phi):
+    """Unit vectors (3, N) for polar angle theta from the x axis and azimuth
+    phi about it (Sec. 1)."""
+    theta = np.asarray(theta, float).ravel()
+    phi = np.asarray(phi, float).ravel()
+    return np.stack([np.cos(theta), np.sin(theta) * np.cos(phi), np.sin(theta) * np.sin(phi)])
+
+
+def reconstruct(zeta, lmax: int, theta, phi):
+    """f(node, d) = sum_lms zeta[node, lms] Y_lms(theta_d, phi_d)
+    (eq. spherical-harmonic-exp): array (rows, ndir)."""
+    n = (lmax + 1) ** 2
+    Z = np.asarray(zeta, float).reshape(-1, n)
+    return Z @ real_sph_harm(lmax, directions(theta, phi))
+
+
 def real_sph_harm_grad(lmax: int, pts):
     """Cartesian gradient (3, n, N) of the polynomial extension used above.
 

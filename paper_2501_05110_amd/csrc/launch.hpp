@@ -57,6 +57,11 @@ void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coe
                hipStream_t s);
 void kry_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t s);
 
+// out[row][d] = sum_j zeta[row][j] Y[d][j] for rows x ndir outputs, n <= 64.
+void launch_reconstruct(const double* zeta, int64_t rows, int n, const double* Y, int64_t ndir, double* out,
+                        hipStream_t s);
+int reconstruct_max_lms();
+
 hipError_t upload_basis(const Basis1D* b);
 
 int stage_cells_per_block(int lmax);

@@ -215,4 +215,40 @@ ShMatrices build_sh_matrices(int lmax) {
   return S;
 }
 
+// Real spherical harmonics of App. A: Y_lms = N_lm P_l^m(cos theta)
+// (cos m phi | sin m phi), eq. spherical-harmonics with the normalisation of
+// eq. normalisation-spherical-harmonics and the Condon-Shortley phase inside
+// P_l^m (eq. associated-legendre-polynomials).  P_l^m by the standard
+// recurrences in l at fixed m, started from P_m^m = (-1)^m (2m-1)!! sin^m theta.
+void real_sh_dir(int lmax, double theta, double phi, double* Y) {
+  const double x = std::cos(theta), st = std::sin(theta);
+  const int n = (lmax + 1) * (lmax + 1);
+  for (int j = 0; j < n; ++j) Y[j] = 0.0;
+  double pmm = 1.0;                                   // P_m^m
+  for (int m = 0; m <= lmax; ++m) {
+    if (m > 0) pmm *= -(2.0 * m - 1.0) * st;
+    double plm2 = 0.0, plm1 = pmm;                    // P_{l-2}^m, P_{l-1}^m
+    for (int l = m; l <= lmax; ++l) {
+      double p;
+      if (l == m) {
+        p = pmm;
+      } else if (l == m + 1) {
+        p = x * (2.0 * m + 1.0) * pmm;
+      } else {
+        p = ((2.0 * l - 1.0) * x * plm1 - (l + m - 1.0) * plm2) / (l - m);
+      }
+      if (l > m) {
+        plm2 = plm1;
+        plm1 = p;
+      }
+      // N_lm^2 = (2l+1)/(2 pi (1 + delta_m0)) (l-m)!/(l+m)!
+      double ratio = 1.0;
+      for (int q = l - m + 1; q <= l + m; ++q) ratio /= q;
+      const double nlm = std::sqrt((2.0 * l + 1.0) / (2.0 * M_PI * (m == 0 ? 2.0 : 1.0)) * ratio);
+      Y[lms_index(l, m, 0)] = nlm * p * std::cos(m * phi);
+      if (m > 0) Y[lms_index(l, m, 1)] = nlm * p * std::sin(m * phi);
+    }
+  }
+}
+
 }  // namespace vfp

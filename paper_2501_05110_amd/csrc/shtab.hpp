@@ -39,4 +39,8 @@ struct ShMatrices {
 // products at l_max+1 then truncated.
 ShMatrices build_sh_matrices(int lmax);
 
+// Y[lms] = Y_lms(theta, phi) for lms < (lmax+1)^2 (App. A; theta from the x
+// axis, phi about it).
+void real_sh_dir(int lmax, double theta, double phi, double* Y);
+
 }  // namespace vfp

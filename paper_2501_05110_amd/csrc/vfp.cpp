@@ -1591,6 +1591,31 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
 
 extern "C" {
 
+int vfp_sh_eval(int lmax, int64_t ndir, const double* theta, const double* phi, double* Y) {
+  if (lmax < 0 || lmax > 7) return fail(VFP_EINVAL, "lmax must be in 0..7");
+  if (ndir < 0 || (ndir > 0 && (!theta || !phi || !Y))) return fail(VFP_EINVAL, "bad direction arrays");
+  const int n = (lmax + 1) * (lmax + 1);
+  for (int64_t d = 0; d < ndir; ++d) real_sh_dir(lmax, theta[d], phi[d], Y + d * n);
+  return VFP_OK;
+}
+
+int vfp_reconstruct(const vfp_ctx* c, const double* zeta, const double* Y, int64_t ndir, double* out,
+                    void* stream) {
+  if (!c || !c->mesh_set) return fail(VFP_ESTATE, "context without a mesh");
+  if (!zeta || !Y || !out) return fail(VFP_EINVAL, "null pointer");
+  if (ndir < 1) return fail(VFP_EINVAL, "ndir must be >= 1");
+  const int n = c->n;
+  if (n > reconstruct_max_lms()) return fail(VFP_EUNSUPPORTED, "lmax too large for vfp_reconstruct");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  const int64_t rows = N / n;
+  if ((ndir + 31) / 32 > 65535) return fail(VFP_EINVAL, "ndir too large");
+  if (overlaps(zeta, N, out, rows * ndir)) return fail(VFP_EINVAL, "out overlaps zeta");
+  launch_reconstruct(zeta, rows, n, Y, ndir, out, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  return VFP_OK;
+}
+
 int vfp_theta_work_size(const vfp_ctx* c, int restart, int64_t* n) {
   if (!c || !n) return fail(VFP_EINVAL, "null argument");
   if (restart < 1 || restart > 64) return fail(VFP_EINVAL, "restart must be in 1..64");

@@ -80,6 +80,8 @@ def load(path: str = None):
         "vfp_field_grad_size": (I, [P, C.POINTER(L)]),
         "vfp_field_grad_stage": (I, [P, P, P, D, P, P]),
         "vfp_field_grad_reduce": (I, [P, P, P, P, P, P, P]),
+        "vfp_sh_eval": (I, [I, L, dp, dp, dp]),
+        "vfp_reconstruct": (I, [P, P, P, L, P, P]),
         "vfp_theta_work_size": (I, [P, I, C.POINTER(L)]),
         "vfp_theta_advance": (I, [P, P, D, L, C.POINTER(ThetaOpts), P, L, C.POINTER(ThetaStats), P]),
         "vfp_batch_create": (I, [C.POINTER(P), C.POINTER(P), I, U]),
@@ -108,7 +110,7 @@ def exported_symbols():
             "vfp_batch_create", "vfp_batch_destroy", "vfp_batch_bind", "vfp_batch_advance",
             "vfp_batch_autotune", "vfp_batch_nclasses", "vfp_batch_class_info",
             "vfp_field_grad_size", "vfp_field_grad_stage", "vfp_field_grad_reduce",
-            "vfp_theta_work_size", "vfp_theta_advance"]
+            "vfp_theta_work_size", "vfp_theta_advance", "vfp_sh_eval", "vfp_reconstruct"]
 
 
 def _check(rc):
@@ -324,6 +326,14 @@ class Operator:
             self._t(g_dudx, "g_dudx", nq), self._t(g_dudt, "g_dudt", nq),
             self._t(g_uface, "g_uface", self.wl.ncells_axis[0] + 1), _stream_handle(stream)))
 
+    def reconstruct(self, zeta, Y, out, stream=None):
+        """out[row, d] = sum_lms zeta[row, lms] Y[d, lms] at every basis node
+        (vfp_reconstruct); Y: device table (ndir, n), e.g. from sh_eval."""
+        ndir = Y.numel() // self.wl.n_lms
+        rows = self.ndofs // self.wl.n_lms
+        _check(_lib.vfp_reconstruct(self._ctx, self._t(zeta, "zeta"), self._t(Y, "Y", ndir * self.wl.n_lms),
+                                    int(ndir), self._t(out, "out", rows * ndir), _stream_handle(stream)))
+
     def theta_work_size(self, restart=30):
         n = C.c_int64()
         _check(_lib.vfp_theta_work_size(self._ctx, int(restart), C.byref(n)))
@@ -418,6 +428,20 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def sh_eval(lmax: int, theta, phi):
+    """Y[d, lms] = Y_lms(theta[d], phi[d]) from the library's host routine
+    (vfp_sh_eval), as a numpy array (ndir, (lmax+1)^2)."""
+    import numpy as np
+    load()
+    th = np.ascontiguousarray(theta, dtype=np.float64).ravel()
+    ph = np.ascontiguousarray(phi, dtype=np.float64).ravel()
+    if th.shape != ph.shape:
+        raise VFPError("theta and phi must have the same length")
+    Y = np.zeros((th.size, (lmax + 1) ** 2))
+    _check(_lib.vfp_sh_eval(int(lmax), th.size, _dptr(th), _dptr(ph), _dptr(Y)))
+    return Y
 
 
 def checkpoint_segment(nsteps: int) -> int:

@@ -1,0 +1,35 @@
+"""vfp_reconstruct (f at every basis node in given directions) against the
+oracle's sum over the coefficients; ragged row and direction tiles."""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sh
+from paper_2501_05110_amd import workloads as W
+
+from gpu_cases import _say, rel_inf, shock
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("wl_args,ndir", [((13, 9, 2, 1), 50), ((9, 5, 2, 7), 33), ((11, 6, 1, 5), 1)])
+def test_reconstruct_parity(lib, cuda, wl_args, ndir):
+    import torch
+    from paper_2501_05110_amd import vfp
+    wl = shock(*wl_args)
+    op = vfp.Operator(wl)
+    rng = np.random.default_rng(12)
+    th, ph = np.arccos(rng.uniform(-1, 1, ndir)), rng.uniform(0, 2 * math.pi, ndir)
+    z = W.random_state(wl, 3)
+    Y = torch.from_numpy(vfp.sh_eval(wl.lmax, th, ph)).cuda()
+    rows = wl.ndofs // wl.n_lms
+    out = torch.empty(rows * ndir, dtype=torch.float64, device="cuda")
+    op.reconstruct(torch.from_numpy(z.ravel()).cuda(), Y, out)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().reshape(rows, ndir)
+    want = sh.reconstruct(z, wl.lmax, th, ph)
+    err = rel_inf(got, want)
+    _say(f"[reconstruct] {wl.name} rows={rows} ndir={ndir} rel_inf={err:.2e}")
+    assert err <= 1e-13

@@ -1,0 +1,91 @@
+"""Real spherical harmonics and the reconstruction of f (App. A).
+
+Pins: the paper's table of Y_lms for l <= 2 (Tab. real-spherical-harmonics),
+the addition theorem sum_{m,s} Y_lms^2 = (2l+1)/(4 pi), orthonormality on a
+sphere quadrature exact to the product degree, and f = a + b cos(theta)
+from its two coefficients.  Both the oracle's harmonics and the library's
+host routine (vfp_sh_eval, no GPU needed) are checked.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sh
+
+
+def _dirs(n=40, seed=3):
+    rng = np.random.default_rng(seed)
+    return np.arccos(rng.uniform(-1, 1, n)), rng.uniform(0, 2 * math.pi, n)
+
+
+def _paper_table(theta, phi):
+    """Tab. real-spherical-harmonics, keyed by (l, m, s)."""
+    c, s_ = np.cos(theta), np.sin(theta)
+    r3, r5, r15 = math.sqrt(3 / (4 * math.pi)), math.sqrt(5 / math.pi), math.sqrt(15 / math.pi)
+    return {
+        (0, 0, 0): np.full_like(theta, math.sqrt(1 / (4 * math.pi))),
+        (1, 0, 0): r3 * c,
+        (1, 1, 0): -r3 * s_ * np.cos(phi),
+        (1, 1, 1): -r3 * s_ * np.sin(phi),
+        (2, 0, 0): 0.25 * r5 * (3 * c ** 2 - 1),
+        (2, 1, 0): -0.5 * r15 * s_ * c * np.cos(phi),
+        (2, 1, 1): -0.5 * r15 * s_ * c * np.sin(phi),
+        (2, 2, 0): 0.25 * r15 * s_ ** 2 * np.cos(2 * phi),
+        (2, 2, 1): 0.25 * r15 * s_ ** 2 * np.sin(2 * phi),
+    }
+
+
+def _oracle_Y(lmax, th, ph):
+    return sh.real_sph_harm(lmax, sh.directions(th, ph)).T
+
+
+def _library_Y(lmax, th, ph):
+    from paper_2501_05110_amd import vfp
+    return vfp.sh_eval(lmax, th, ph)
+
+
+@pytest.mark.parametrize("evaluate", [_oracle_Y, _library_Y], ids=["oracle", "library"])
+def test_paper_table(evaluate):
+    th, ph = _dirs()
+    Y = evaluate(2, th, ph)
+    for (l, m, s), want in _paper_table(th, ph).items():
+        np.testing.assert_allclose(Y[:, sh.lms_index(l, m, s)], want, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("evaluate", [_oracle_Y, _library_Y], ids=["oracle", "library"])
+def test_addition_theorem(evaluate):
+    th, ph = _dirs(60, 5)
+    Y = evaluate(7, th, ph)
+    for l in range(8):
+        idx = [sh.lms_index(l, m, s) for m in range(l + 1) for s in ((0,) if m == 0 else (0, 1))]
+        np.testing.assert_allclose((Y[:, idx] ** 2).sum(axis=1), (2 * l + 1) / (4 * math.pi), rtol=1e-13)
+
+
+def test_library_orthonormal_and_equal_to_oracle():
+    pts, wts = sh.sphere_quadrature(16)
+    th = np.arccos(np.clip(pts[0], -1, 1))
+    ph = np.arctan2(pts[2], pts[1])
+    Y = _library_Y(7, th, ph)
+    G = Y.T @ (wts[:, None] * Y)
+    np.testing.assert_allclose(G, np.eye(64), atol=1e-13)
+    np.testing.assert_allclose(Y, _oracle_Y(7, th, ph), atol=1e-13)
+
+
+def test_reconstruct_dipole():
+    """f = a + b cos(theta): f000 = a sqrt(4 pi), f100 = b sqrt(4 pi / 3)."""
+    a, b = 0.7, -1.3
+    z = np.zeros((3, 4))
+    z[:, 0] = a * math.sqrt(4 * math.pi) * np.array([1.0, 2.0, 3.0])
+    z[:, sh.lms_index(1, 0, 0)] = b * math.sqrt(4 * math.pi / 3) * np.array([1.0, 2.0, 3.0])
+    th, ph = _dirs(17, 8)
+    f = sh.reconstruct(z, 1, th, ph)
+    want = np.array([1.0, 2.0, 3.0])[:, None] * (a + b * np.cos(th))[None, :]
+    np.testing.assert_allclose(f, want, atol=1e-14)
+
+
+def test_library_rejects_lmax_8():
+    from paper_2501_05110_amd import vfp
+    with pytest.raises(vfp.VFPError):
+        vfp.sh_eval(8, [0.1], [0.2])
