@@ -301,7 +301,8 @@ int vfp_reconstruct(const vfp_ctx* ctx, const double* zeta, const double* Y, int
  * system multiplied by the block-diagonal M^{-1} (exact per cell),
  *     (I - dt Theta L0) zeta^n = zeta^{n-1} + dt (1 - Theta) L(zeta^{n-1}) + dt Theta M^{-1} h,
  * with L0 = L without the source, by restarted GMRES (classical
- * Gram-Schmidt applied twice per Krylov vector) whose operator is the fused
+ * Gram-Schmidt, repeated for a Krylov vector where the first pass removes
+ * more than half of its squared norm) whose operator is the fused
  * stage kernel; the iterate starts at zeta^{n-1}.  A step is accepted when
  * the true residual norm is at most tol times the right-hand side's
  * (Euclidean norms).

@@ -1542,16 +1542,26 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
     g[0] = beta;
     int j = 0;
     while (j < m && used < o.max_iters) {
-      // w = A V_j, orthogonalised against V_0..V_j twice
+      // w = A V_j, orthogonalised against V_0..V_j by classical Gram-Schmidt;
+      // a second pass only where the first removed most of w (the criterion
+      // of Daniel, Gragg, Kaufman and Stewart: |w_new| < |w_old| / sqrt 2)
       if (int e = theta_op(c, t.V + (int64_t)j * N, t.w, dt, th, stream)) return e;
       kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d1, st);
-      kry_maxpy(t.w, t.V, N, j + 1, t.d1, -1.0, N, st);
-      kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d2, st);
-      kry_maxpy(t.w, t.V, N, j + 1, t.d2, -1.0, N, st);
       kry_mdot(t.w, N, 1, t.w, N, t.partial, t.d3, st);
+      kry_maxpy(t.w, t.V, N, j + 1, t.d1, -1.0, N, st);
+      kry_mdot(t.w, N, 1, t.w, N, t.partial, t.d3 + 1, st);
       if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st)) return e;
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i] + hb[kKryMaxVectors + i];
-      const double hn = std::sqrt(std::max(hb[2 * kKryMaxVectors], 0.0));
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i];
+      double hn2 = hb[2 * kKryMaxVectors + 1];
+      if (hn2 < 0.5 * hb[2 * kKryMaxVectors]) {
+        kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d2, st);
+        kry_maxpy(t.w, t.V, N, j + 1, t.d2, -1.0, N, st);
+        kry_mdot(t.w, N, 1, t.w, N, t.partial, t.d3 + 2, st);
+        if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st)) return e;
+        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hb[kKryMaxVectors + i];
+        hn2 = hb[2 * kKryMaxVectors + 2];
+      }
+      const double hn = std::sqrt(std::max(hn2, 0.0));
       H[(size_t)(j + 1) * m + j] = hn;
       ++used;
       // previous Givens rotations, then the one that removes H[j+1][j]
