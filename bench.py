@@ -112,6 +112,8 @@ def adjoint_timing(steps=1000):
     op = vfp.Operator(wl)
     N = op.ndofs
     dt = op.cfl_dt(wl.courant)
+    # the mode a reverse pass takes by default on this GPU (advance_with_grad)
+    default_mode = "full_tape" if vfp.grad_segment(op, steps, torch.device("cuda:0")) >= steps else "checkpointed"
     seg = vfp.checkpoint_segment(steps)
     nseg = -(-steps // seg)
     dev = torch.device("cuda:0")
@@ -175,8 +177,6 @@ def adjoint_timing(steps=1000):
         del full_tape
         taped = {"tape_GB": need / 1e9, "forward_taped_s": t_tf, "reverse_s": t_tr, "reverse_with_flow_s": t_trf,
                  "reverse_over_forward": t_tr / t_fwd, "reverse_with_flow_over_forward": t_trf / t_fwd}
-    # the mode a reverse pass takes by default on this GPU (advance_with_grad)
-    default_mode = "full_tape" if vfp.grad_segment(op, steps, dev) >= steps else "checkpointed"
     if default_mode == "full_tape" and taped:
         dflt = {"mode": default_mode, "reverse_over_forward": taped["reverse_over_forward"],
                 "reverse_with_flow_over_forward": taped["reverse_with_flow_over_forward"]}

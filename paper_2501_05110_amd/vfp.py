@@ -457,6 +457,8 @@ def grad_segment(op: "Operator", nsteps: int, device=None, reserve: int = 16 << 
     import torch
     need = (4 * max(nsteps, 1) + 1) * op.ndofs * 8
     free, _ = torch.cuda.mem_get_info(device)
+    # memory torch's caching allocator holds but does not use is free to it
+    free += torch.cuda.memory_reserved(device) - torch.cuda.memory_allocated(device)
     return max(nsteps, 1) if need + reserve <= free else checkpoint_segment(nsteps)
 
 
