@@ -54,6 +54,22 @@ def cube(n=(5, 4, 3), lmax=5, k=2):
     return W.config3(n, lmax=lmax, k=k)
 
 
+def box_mixed(lmax=3, k=2):
+    """Three spatial axes with every boundary kind, a uniform flow, a uniform
+    B, scattering per cell and a source: the branches of the 3-D kernel that
+    the periodic box does not reach."""
+    n = (6, 5, 4)
+    nodes = (np.linspace(-1.0, 1.0, n[0] + 1), np.linspace(0.0, 1.5, n[1] + 1) ** 1.2,
+             np.linspace(-0.5, 0.7, n[2] + 1))
+    nu = 0.2 + np.random.default_rng(41).uniform(0.0, 1.0, int(np.prod(n)))
+    return W.Workload(
+        name="box_mixed", lmax=lmax, k=k, axes=("x", "y", "z"), nodes=nodes,
+        bc=((W.ZERO_INFLOW, W.CONTINUOUS), (W.PERIODIC, W.PERIODIC), (W.CONTINUOUS, W.ZERO_INFLOW)),
+        terms=frozenset({W.ADVECTION, W.ROTATION, W.COLLISION, W.SOURCE}), p_fixed=1.3,
+        flow=W.uniform_flow([0.1, -0.05, 0.02]), magnetic=W.uniform_field((0.3, -0.6, 1.1)), nu=nu,
+        source=lambda X, p: np.exp(-(X[0] ** 2 + (X[2] - 0.1) ** 2)))
+
+
 CASES = {
     "c1": lambda: W.config1(),
     "shock_k2_l3": lambda: shock(25, 11, 2, 3),
@@ -66,4 +82,6 @@ CASES = {
     "planar1d": lambda: planar1d(),
     "cube_k2_l5": lambda: cube(),
     "cube_k1_l3": lambda: cube((4, 3, 5), 3, 1),
+    "box_mixed_k2_l3": lambda: box_mixed(),
+    "box_mixed_k1_l7": lambda: box_mixed(7, 1),
 }
