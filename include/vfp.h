@@ -88,13 +88,17 @@ const char* vfp_last_error(void);
 
 /* Create a context.
  *   lmax       expansion degree l_max, 1..7 (n = (l_max+1)^2 coefficients)
- *   k          DG degree, 1 or 2
+ *   k          DG degree 1..5 (Gauss-Lobatto nodes, eq. lagrange-polynomial);
+ *              k <= 3 with two axes and k <= 2 with three.  The (x, ln p)
+ *              kernels, the adjoint, the mass and the flow-sensitivity calls
+ *              are built for k <= 2 (VFP_EUNSUPPORTED above)
  *   naxes      1..3 axes of the reduced phase space (Sec. 4 term list: at most
  *              three; with VFP_AXIS_LNP at most two spatial axes)
  *   axis_kinds naxes kinds; spatial axes in x, y, z order, VFP_AXIS_LNP last
  *   term_mask  OR of VFP_TERM_*
  *   mass, charge  particle mass m > 0 and charge q in code units
- * Errors: VFP_EINVAL for any value outside these ranges. */
+ * Errors: VFP_EINVAL for any value outside these ranges; VFP_EUNSUPPORTED
+ * for k above the limit of the number of axes. */
 int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
                unsigned term_mask, double mass, double charge);
 

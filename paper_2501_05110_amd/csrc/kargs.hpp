@@ -6,21 +6,23 @@ namespace vfp {
 
 constexpr int kMaxLmax = 7;
 constexpr int kMaxN = (kMaxLmax + 1) * (kMaxLmax + 1);
-constexpr int kMaxK = 2;
+constexpr int kMaxK = 5;           // general kernels: k <= 5 on one axis, 3 on two, 2 on three
+constexpr int kMaxK1 = kMaxK + 1;
 constexpr int kMaxUniSlots = 24;   // max non-zeros per row of a uniform-axis face matrix
 constexpr int kRec = 16;           // doubles per packed x / p scalar record
 
 // One-dimensional basis data for degree K on the reference interval [-1,1]:
 // Gauss-Lobatto Lagrange basis l_j, (K+1)-point Gauss rule (g_q, w_q), and
-// the 1-D mass matrix M1_ij = sum_q w_q l_i(g_q) l_j(g_q) (exact).
+// the 1-D mass matrix M1_ij = sum_q w_q l_i(g_q) l_j(g_q) (exact).  Entries
+// beyond K+1 are zero.
 struct Basis1D {
-  double phi[3][3];    // phi[q][j]  = l_j(g_q)
-  double tst[3][3];    // tst[i][q]  = sum_j (M1^{-1})_ij l_j(g_q) w_q
-  double dtst[3][3];   // dtst[i][q] = sum_j (M1^{-1})_ij l_j'(g_q) w_q
-  double lift[2][3];   // lift[side][i] = (M1^{-1})_{i, 0 or K}
-  double dphi[3][3];   // dphi[q][j] = l_j'(g_q)
-  double mass[3][3];   // M1
-  double imass[3][3];  // M1^{-1}
+  double phi[kMaxK1][kMaxK1];    // phi[q][j]  = l_j(g_q)
+  double tst[kMaxK1][kMaxK1];    // tst[i][q]  = sum_j (M1^{-1})_ij l_j(g_q) w_q
+  double dtst[kMaxK1][kMaxK1];   // dtst[i][q] = sum_j (M1^{-1})_ij l_j'(g_q) w_q
+  double lift[2][kMaxK1];        // lift[side][i] = (M1^{-1})_{i, 0 or K}
+  double dphi[kMaxK1][kMaxK1];   // dphi[q][j] = l_j'(g_q)
+  double mass[kMaxK1][kMaxK1];   // M1
+  double imass[kMaxK1][kMaxK1];  // M1^{-1}
 };
 
 // Per-row (lms) sparse rows of the spherical-harmonic matrices, stored

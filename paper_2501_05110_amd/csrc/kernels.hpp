@@ -42,7 +42,7 @@ struct IPow<B, 0> { static constexpr int v = 1; };
 // Apply a (K1 x K1) matrix M along axis AX of a D-dimensional tensor with K1
 // points per axis: out[.., q, ..] = sum_j M[q][j] in[.., j, ..].
 template <int D, int K1, int AX>
-__device__ __forceinline__ void sweep(const double* in, double* out, const double (&M)[3][3]) {
+__device__ __forceinline__ void sweep(const double* in, double* out, const double (&M)[kMaxK1][kMaxK1]) {
   constexpr int NB = IPow<K1, D>::v;
   constexpr int st = IPow<K1, AX>::v;
 #pragma unroll
@@ -128,7 +128,7 @@ __device__ __forceinline__ void ref_mass(double* v) {
   constexpr int K1 = K + 1;
   constexpr int NB = IPow<K1, D>::v;
   const Basis1D& bs = c_basis[K - 1];
-  const double(&Mm)[3][3] = INV ? bs.imass : bs.mass;
+  const double(&Mm)[kMaxK1][kMaxK1] = INV ? bs.imass : bs.mass;
   double t[NB];
   sweep<D, K1, 0>(v, t, Mm);
   if constexpr (D == 1) {

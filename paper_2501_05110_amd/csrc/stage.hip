@@ -561,10 +561,20 @@ StageLauncher pick_lmax(int lmax) {
   }
 }
 
+// Degrees above 2 are built for the forward operator only: up to k = 5 on
+// one axis and k = 3 on two (the lane's (k+1)^D nodal values stay in
+// registers).
 template <int D, bool MOM, bool XPROF, bool ADJ>
 StageLauncher pick_k(int k, int lmax) {
   if (k == 1) return pick_lmax<D, 1, MOM, XPROF, ADJ>(lmax);
   if (k == 2) return pick_lmax<D, 2, MOM, XPROF, ADJ>(lmax);
+  if constexpr (!ADJ && D <= 2) {
+    if (k == 3) return pick_lmax<D, 3, MOM, XPROF, ADJ>(lmax);
+  }
+  if constexpr (!ADJ && D == 1) {
+    if (k == 4) return pick_lmax<D, 4, MOM, XPROF, ADJ>(lmax);
+    if (k == 5) return pick_lmax<D, 5, MOM, XPROF, ADJ>(lmax);
+  }
   return nullptr;
 }
 

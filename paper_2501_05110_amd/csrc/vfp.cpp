@@ -73,22 +73,76 @@ int upload(DevBuf& b, const void* host, size_t bytes) {
 template <class T>
 int upload_vec(DevBuf& b, const std::vector<T>& v) { return upload(b, v.data(), v.size() * sizeof(T)); }
 
+// Legendre polynomial P_n(x) and its derivative by the three-term recurrence
+// (the derivative from P_n' = n (x P_n - P_{n-1}) / (x^2 - 1), |x| < 1).
+void legendre(int n, double x, double& p, double& dp) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    p = 1.0;
+    dp = 0.0;
+    return;
+  }
+  for (int l = 2; l <= n; ++l) {
+    const double p2 = ((2.0 * l - 1.0) * x * p1 - (l - 1.0) * p0) / l;
+    p0 = p1;
+    p1 = p2;
+  }
+  p = p1;
+  dp = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+// q-point Gauss-Legendre rule: the roots of P_q by Newton's method from the
+// Chebyshev guesses, weights 2 / ((1 - x^2) P_q'(x)^2).
+void gauss_rule(int q, std::vector<double>& x, std::vector<double>& w) {
+  x.assign(q, 0.0);
+  w.assign(q, 0.0);
+  for (int i = 0; i < q; ++i) {
+    double t = -std::cos(M_PI * (i + 0.75) / (q + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(q, t, p, dp);
+      const double dt = p / dp;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    double p, dp;
+    legendre(q, t, p, dp);
+    x[i] = std::fabs(t) < 1e-15 ? 0.0 : t;
+    w[i] = 2.0 / ((1.0 - t * t) * dp * dp);
+  }
+}
+
+// k+1 Gauss-Lobatto nodes: -1, 1 and the roots of P_k' by Newton's method
+// (P_k'' = (2 x P_k' - k (k+1) P_k) / (1 - x^2)) from the Chebyshev-Lobatto
+// points; for k <= 2 these are the equidistant nodes.
+std::vector<double> lobatto_nodes(int k) {
+  std::vector<double> x(k + 1);
+  x[0] = -1.0;
+  x[k] = 1.0;
+  for (int i = 1; i < k; ++i) {
+    double t = -std::cos(M_PI * i / k);
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(k, t, p, dp);
+      const double d2 = (2.0 * t * dp - k * (k + 1.0) * p) / (1.0 - t * t);
+      const double dt = dp / d2;
+      t -= dt;
+      if (std::fabs(dt) < 1e-16) break;
+    }
+    x[i] = std::fabs(t) < 1e-15 ? 0.0 : t;
+  }
+  return x;
+}
+
 // 1-D basis data for degree k (Gauss-Lobatto Lagrange basis, (k+1)-point
 // Gauss rule) computed in double precision.
 Basis1D make_basis(int k) {
   Basis1D B;
   std::memset(&B, 0, sizeof B);
   const int K1 = k + 1;
-  std::vector<double> nodes, g, w;
-  if (k == 1) {
-    nodes = {-1.0, 1.0};
-    g = {-1.0 / std::sqrt(3.0), 1.0 / std::sqrt(3.0)};
-    w = {1.0, 1.0};
-  } else {
-    nodes = {-1.0, 0.0, 1.0};
-    g = {-std::sqrt(0.6), 0.0, std::sqrt(0.6)};
-    w = {5.0 / 9.0, 8.0 / 9.0, 5.0 / 9.0};
-  }
+  const std::vector<double> nodes = lobatto_nodes(k);
+  std::vector<double> g, w;
+  gauss_rule(K1, g, w);
   auto lag = [&](int j, double x) {
     double v = 1.0;
     for (int m = 0; m < K1; ++m)
@@ -106,12 +160,12 @@ Basis1D make_basis(int k) {
     }
     return d;
   };
-  double M1[3][3] = {}, Mi[3][3] = {};
+  double M1[kMaxK1][kMaxK1] = {}, Mi[kMaxK1][kMaxK1] = {};
   for (int i = 0; i < K1; ++i)
     for (int j = 0; j < K1; ++j)
       for (int q = 0; q < K1; ++q) M1[i][j] += w[q] * lag(i, g[q]) * lag(j, g[q]);
   // invert the small SPD matrix by Gauss-Jordan
-  double a[3][6] = {};
+  double a[kMaxK1][2 * kMaxK1] = {};
   for (int i = 0; i < K1; ++i) {
     for (int j = 0; j < K1; ++j) a[i][j] = M1[i][j];
     a[i][K1 + i] = 1.0;
@@ -154,8 +208,9 @@ Basis1D make_basis(int k) {
 }
 
 std::vector<double> gauss_points(int k) {
-  if (k == 1) return {-1.0 / std::sqrt(3.0), 1.0 / std::sqrt(3.0)};
-  return {-std::sqrt(0.6), 0.0, std::sqrt(0.6)};
+  std::vector<double> g, w;
+  gauss_rule(k + 1, g, w);
+  return g;
 }
 
 bool g_basis_ready[64] = {};
@@ -689,7 +744,8 @@ int ensure_device(vfp_ctx* c) {
   HIP_TRY(hipGetDevice(&dev));
   if (dev < 0 || dev >= 64) return fail(VFP_EDEVICE, "device ordinal %d", dev);
   if (!g_basis_ready[dev]) {
-    Basis1D b[kMaxK] = {make_basis(1), make_basis(2)};
+    Basis1D b[kMaxK];
+    for (int k = 1; k <= kMaxK; ++k) b[k - 1] = make_basis(k);
     HIP_TRY(upload_basis(b));
     g_basis_ready[dev] = true;
   }
@@ -699,7 +755,9 @@ int ensure_device(vfp_ctx* c) {
 
 // Packed per-x-cell and per-p-cell scalar records (see FieldArgs::xrec).
 int build_records(vfp_ctx* c) {
-  if (!c->mom || !c->mesh_set) return VFP_OK;
+  // the records hold three Gauss points per axis; the (x, ln p) kernels
+  // that read them exist for k <= 2
+  if (!c->mom || !c->mesh_set || c->k > 2) return VFP_OK;
   const int K1 = c->K1, nxc = c->ncell[0], pa = c->naxes - 1, npc = c->ncell[pa];
   const double ta = (c->terms & VFP_TERM_ADVECTION) ? 1.0 : 0.0;
   const double tm = (c->terms & VFP_TERM_MOMENTUM) ? 1.0 : 0.0;
@@ -859,6 +917,8 @@ int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
   }
   if (mom && nsp > 2) return fail(VFP_EINVAL, "at most two spatial axes with a ln p axis");
   if (nsp == 0) return fail(VFP_EINVAL, "at least one spatial axis is required");
+  if ((naxes == 3 && k > 2) || (naxes == 2 && k > 3))
+    return fail(VFP_EUNSUPPORTED, "k=%d is built for at most %d axes", k, k > 3 ? 1 : 2);
   vfp_ctx* c = new (std::nothrow) vfp_ctx();
   if (!c) return fail(VFP_ENOMEM, "context allocation");
   c->lmax = lmax;

@@ -70,6 +70,29 @@ def box_mixed(lmax=3, k=2):
         source=lambda X, p: np.exp(-(X[0] ** 2 + (X[2] - 0.1) ** 2)))
 
 
+def line(k, lmax=3, n=23):
+    """1-D x with a planar flow and zero-inflow / continuous ends."""
+    return W.Workload(
+        name=f"line_k{k}_l{lmax}", lmax=lmax, k=k, axes=("x",), nodes=(np.linspace(-3, 3, n + 1) ** 1.0,),
+        bc=((W.ZERO_INFLOW, W.CONTINUOUS),),
+        terms=frozenset({W.ADVECTION, W.ROTATION, W.COLLISION}), p_fixed=2.0,
+        flow=W.shock_flow(0.1, 4.0, 0.3), magnetic=W.uniform_field((0.5, 0.2, 0.0)), nu=0.4)
+
+
+# degrees above 2 (forward operator, general kernels): k <= 5 on one axis,
+# k = 3 on two
+HIGH_K_CASES = {
+    "line_k3_l3": lambda: line(3),
+    "line_k4_l5": lambda: line(4, 5, 17),
+    "line_k5_l7": lambda: line(5, 7, 13),
+    "line_k5_periodic_l3": lambda: W.Workload(
+        name="line_k5_periodic", lmax=3, k=5, axes=("x",), nodes=(W.uniform_nodes(-0.5, 0.5, 19),),
+        bc=((W.PERIODIC, W.PERIODIC),), terms=frozenset({W.ADVECTION, W.ROTATION, W.COLLISION}),
+        p_fixed=3 ** 0.5, flow=W.zero_flow, magnetic=W.uniform_field((0.0, 0.0, 1.0)), nu=1.0),
+    "uniform2d_k3_l3": lambda: uniform2d(3, 3),
+    "shock_k3_l3": lambda: shock(11, 6, 3, 3),
+}
+
 CASES = {
     "c1": lambda: W.config1(),
     "shock_k2_l3": lambda: shock(25, 11, 2, 3),

@@ -37,7 +37,7 @@ def _create(lib, lmax=3, k=2, axes=(0, 3), mask=31, mass=1.0, charge=1.0):
 
 
 @pytest.mark.parametrize("kw,needle", [
-    (dict(lmax=0), "lmax"), (dict(lmax=8), "lmax"), (dict(k=0), "k="), (dict(k=3), "k="),
+    (dict(lmax=0), "lmax"), (dict(lmax=8), "lmax"), (dict(k=0), "k="), (dict(k=6), "k="),
     (dict(axes=()), "naxes"), (dict(axes=(0, 1, 2, 3)), "naxes"), (dict(axes=(3, 0)), "ln p"),
     (dict(axes=(1,)), "x, y, z"), (dict(axes=(0, 1, 2, 3)[:3] + ()), None),
     (dict(mass=0.0), "mass"), (dict(mask=64), "term"), (dict(axes=(3,)), "spatial"),
@@ -50,6 +50,16 @@ def test_create_validation(lib, kw, needle):
         return
     assert rc == -1
     assert needle in lib.vfp_last_error().decode()
+
+
+@pytest.mark.parametrize("k,axes,rc_want", [
+    (5, (0,), 0), (3, (0, 3), 0), (3, (0, 1), 0), (4, (0, 3), -5), (3, (0, 1, 2), -5), (2, (0, 1, 2), 0)])
+def test_create_degree_per_axes(lib, k, axes, rc_want):
+    """k <= 5 on one axis, 3 on two, 2 on three (VFP_EUNSUPPORTED beyond)."""
+    rc, ctx = _create(lib, k=k, axes=axes)
+    assert rc == rc_want, lib.vfp_last_error().decode()
+    if rc == 0:
+        lib.vfp_destroy(ctx)
 
 
 def test_calls_out_of_order(lib):

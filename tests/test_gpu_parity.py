@@ -13,7 +13,7 @@ import pytest
 from oracle import dg
 from paper_2501_05110_amd import workloads as W
 
-from gpu_cases import APPLY_TOL, CASES, STEPS_TOL, _say, cube, gpu_apply, rel_inf, shock
+from gpu_cases import APPLY_TOL, CASES, HIGH_K_CASES, STEPS_TOL, _say, cube, gpu_apply, rel_inf, shock
 
 pytestmark = pytest.mark.gpu
 
@@ -125,3 +125,79 @@ def test_full_size_sampled_rows(lib, cuda, name):
     err = rel_inf(got[cells], want[cells])
     _say(f"   sampled {len(cells)} cells rel_inf={err:.3e}")
     assert err <= APPLY_TOL
+
+
+@pytest.mark.parametrize("name", list(HIGH_K_CASES))
+def test_high_degree_parity(lib, cuda, name):
+    """k = 3..5 (Gauss-Lobatto nodes): one apply with and without the source
+    at 1e-12, and 100 steps at 1e-10, against the oracle."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = HIGH_K_CASES[name]()
+    _say(f"[high-k] {name}: k={wl.k} cells={wl.ncells_axis} ndofs={wl.ndofs}")
+    op = Operator(wl)
+    S = dg.assemble(wl)
+    z = W.random_state(wl, 19)
+    for ws in (True, False):
+        err = rel_inf(gpu_apply(op, z, ws), dg.apply(S, z, ws))
+        _say(f"   apply with_source={ws} rel_inf={err:.3e}")
+        assert err <= APPLY_TOL, (name, ws, err)
+    dt = 0.5 * op.cfl_dt(0.2) / (wl.k * wl.k)
+    u = torch.from_numpy(z.ravel().copy()).cuda()
+    work = torch.empty(2 * wl.ndofs, dtype=torch.float64, device="cuda")
+    op.advance(u, dt, 100, work)
+    torch.cuda.synchronize()
+    want = dg.rk4(S, z, dt, 100)
+    err = rel_inf(u.cpu().numpy(), want)
+    _say(f"   100 steps rel_inf={err:.3e}")
+    assert err <= STEPS_TOL, (name, err)
+
+
+def test_high_degree_adjoint_unsupported(lib, cuda):
+    """The adjoint calls are built for k <= 2: k = 3 fails cleanly."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator, VFPError
+    op = Operator(HIGH_K_CASES["line_k3_l3"]())
+    x = torch.zeros(op.ndofs, dtype=torch.float64, device="cuda")
+    y = torch.empty_like(x)
+    with pytest.raises(VFPError):
+        op.apply_adjoint(x, y)
+    with pytest.raises(VFPError):
+        op.mass(x, y)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5])
+def test_convergence_study_on_gpu(lib, cuda, k):
+    """Fig. 3 right on the library: the setup of Sec. 4.1 (l_max = 1, B along
+    z, gamma = 2, L = 20 periodic), advanced by the GPU to t = 10/omega; the
+    error of f000 against the closed form converges as dx^(k+1)."""
+    import math
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    from test_oracle_dg import _CONV, _convergence_exact
+    L, gam = 20.0, 2.0
+    p = math.sqrt(gam * gam - 1)
+    w = 2 * math.pi / gam
+    exact = _convergence_exact(L, p / gam, w, 2.0, 1.0)
+    tF = 10.0 / w
+    grids, dtn = _CONV[k]
+    errs = []
+    for nc in grids:
+        wl = W.Workload(name="conv", lmax=1, k=k, axes=("x",),
+                        nodes=(W.uniform_nodes(0.0, L, nc),), bc=((W.PERIODIC, W.PERIODIC),),
+                        terms=frozenset({W.ADVECTION, W.ROTATION}), p_fixed=p,
+                        magnetic=W.uniform_field((0, 0, 2 * math.pi)))
+        op = Operator(wl)
+        nsteps = int(round(tF / dtn))
+        u = torch.from_numpy(dg.project(wl, exact(0.0)).ravel().copy()).cuda()
+        work = torch.empty(2 * wl.ndofs, dtype=torch.float64, device="cuda")
+        op.advance(u, tF / nsteps, nsteps, work)
+        torch.cuda.synchronize()
+        z = u.cpu().numpy().reshape(wl.shape)
+        z[:, :, 1:] = 0
+        only000 = lambda X, p_, f=exact(tF): f(X, p_) * np.array([1, 0, 0, 0])[:, None]
+        errs.append(dg.l2_error(wl, z, only000))
+        op.close()
+    lsq = -np.polyfit(np.log2(grids), np.log2(errs), 1)[0]
+    _say(f"[convergence] k={k} errors={['%.3e' % e for e in errs]} order={lsq:.2f}")
+    assert lsq > k + 1 - 0.2, (errs, lsq)
