@@ -62,6 +62,11 @@ extern "C" {
 #define VFP_AXIS_Y   1
 #define VFP_AXIS_Z   2
 #define VFP_AXIS_LNP 3        /* logarithmic momentum; must be the last axis */
+#define VFP_AXIS_P   4        /* momentum magnitude p > 0 itself (Sec. 4: p or ln p);
+                                 must be the last axis.  beta^p = -gamma m dU_a/dt A^a
+                                 - p dU_b/dx^a (A^a A^b)_t (eq. definitions-advection-
+                                 reaction-eq); the (x, ln p) specialisation and the
+                                 flow-sensitivity calls need VFP_AXIS_LNP */
 
 /* term switches (eq. vfp-terms-names) */
 #define VFP_TERM_ADVECTION 1u  /* (U^a 1 + V A^a) d_a f                       */

@@ -101,7 +101,8 @@ def point_terms(phys: Physics, axes, X, p, flow, magnetic, nu):
     """beta^alpha (d, N, n, n), R (N, n, n) and div(beta) (N, n, n) at N points.
 
     X: (3, N) spatial coordinates; p: (N,) momentum magnitudes; nu: (N,).
-    Eq. definitions-advection-reaction-eq, with d/dp replaced by d/d ln p.
+    Eq. definitions-advection-reaction-eq on a "p" axis; on an "lnp" axis
+    d/dp is replaced by d/d ln p.
     """
     S = sh.system_matrices(phys.lmax)
     n = S["n"]
@@ -135,6 +136,19 @@ def point_terms(phys: Physics, axes, X, p, flow, magnetic, nu):
                 # d(gamma m/p)/d ln p = -m/(gamma p)
                 for aa in range(3):
                     div += (m_ / (gam * p) * a[aa])[:, None, None] * A[aa]
+        elif name == "p":
+            if "momentum" in on:
+                # beta^p = -gamma m dU_a/dt A^a - p dU_b/dx^a (A^a A^b)_t
+                # (eq. definitions-advection-reaction-eq, the fourth component)
+                for aa in range(3):
+                    beta[ax] -= (gam * m_ * a[aa])[:, None, None] * A[aa]
+                    for bb in range(3):
+                        beta[ax] -= (p * dU[aa, bb])[:, None, None] * AA[aa, bb]
+                # d/dp of beta^p, with d(gamma m)/dp = p/(gamma m) = V
+                for aa in range(3):
+                    div -= (V * a[aa])[:, None, None] * A[aa]
+                    for bb in range(3):
+                        div -= dU[aa, bb][:, None, None] * AA[aa, bb]
         else:
             raise ValueError(name)
     if "momentum" in on:
@@ -226,8 +240,10 @@ class Grid:
             xi = lo + (1.0 + eta[a]) * (hi - lo) / 2.0
             if name in SPATIAL:
                 X[SPATIAL[name]] = xi
-            else:
+            elif name == "lnp":
                 p = np.exp(xi)
+            else:
+                p = xi
         return X, p
 
     def widths(self, idx):

@@ -70,9 +70,15 @@ struct FieldArgs {
   // momentum axis profiles (ln p): at volume points [Np (k+1)] and faces [Np+1]
   const double* V_vol;
   const double* iV_vol;   // 1/V
-  const double* idiv_vol; // m/(gamma p)
+  const double* idiv_vol; // -div beta holds -dU/dt idiv A^x: m/(gamma p) (ln p) or -V (linear p)
   const double* ig_vol;   // q/(gamma m)
-  const double* iV_face;  // 1/V at p faces
+  const double* iV_face;  // coefficient of dU/dt in beta^p at p faces: 1/V (ln p) or gamma m (p)
+  // along the momentum axis beta^p = -t_mom (dU/dt ca A^x + U' cu (A^x A^x)_t):
+  // ln p: ca = 1/V, cu = 1; linear p: ca = gamma m, cu = p
+  const double* ca_vol;   // [Np (k+1)]
+  const double* cu_vol;
+  const double* cu_face;  // [Np + 1]
+  double t_divu;          // 1 on a linear p axis: -div beta holds + U' (A^x A^x)_t
   double V0, iV0, ig0;    // fixed-momentum values
   // p-face upwind data: code per (p face, x point) stored [pf][x point]:
   // -1 beta>=0, -2 beta<=0, >= 0 index into pf_tab ([code][n][lmax+1] rows of

@@ -108,6 +108,7 @@ __device__ __forceinline__ double om_apply(const LaneRows<LMAX>& R, int c, const
 
 struct PointScalars {
   double V, iV, idiv, ig;   // momentum-dependent
+  double ca, cu;            // beta^p = -(a ca A^x + U' cu (A^x A^x)_t) along the momentum axis
   double U, dU, a;          // planar flow (x)
 };
 
@@ -122,11 +123,14 @@ __device__ __forceinline__ PointScalars point_scalars(const FieldArgs& F, const 
     s.iV = F.iV_vol[ip];
     s.idiv = F.idiv_vol[ip];
     s.ig = F.ig_vol[ip];
+    s.ca = F.ca_vol[ip];
+    s.cu = F.cu_vol[ip];
   } else {
     s.V = F.V0;
     s.iV = F.iV0;
     s.idiv = 0.0;
     s.ig = F.ig0;
+    s.ca = s.cu = 0.0;
   }
   if constexpr (XPROF) {
     const int ix = ic[0] * K1 + q % K1;
@@ -255,7 +259,7 @@ __device__ __forceinline__ void face_axis(const KernelArgs& A, const LaneRows<LM
       for (int fi = 0; fi < NF; ++fi) {
         const int ix = ic[0] * K1 + fi % K1;
         const double a1 = -F.t_mom * F.a_vol[ix] * iVf;
-        const double a2 = -F.t_mom * F.du_vol[ix];
+        const double a2 = -F.t_mom * F.du_vol[ix] * F.cu_face[pf];
         const int code = F.pf_code[(size_t)pf * (M.n[0] * K1) + ix];
         const double* P1 = shc + fi * N;
         const double* P2 = shc + (NF + fi) * N;
@@ -340,7 +344,7 @@ __device__ __forceinline__ void adj_flux_axis(const KernelArgs& A, const LaneRow
     if constexpr (IS_P) {
       const double Axf = R.axv[0] * P[R.axc[0]] + R.axv[1] * P[R.axc[1]];
       const double A2f = R.axxv[0] * P[R.axxc[0]] + R.axxv[1] * dq[q] + R.axxv[2] * P[R.axxc[1]];
-      tmp[q] = -F.t_mom * (s.a * s.iV * Axf + s.dU * A2f);
+      tmp[q] = -F.t_mom * (s.a * s.ca * Axf + s.dU * s.cu * A2f);
     } else {
       const double Uc = (AX == 0) ? s.U : F.U[AX];
       tmp[q] = F.t_adv * (Uc * dq[q] + s.V * dir_apply<LMAX>(R, AX, P));
@@ -428,8 +432,14 @@ void stage_kernel(KernelArgs A) {
           const double G1t = R.g1tv[0] * fxp + R.g1tv[1] * fxm;
           const double G2t = R.g2tv[0] * fpp + R.g2tv[1] * f + R.g2tv[2] * fmm;
           g += F.t_mom * (s.a * s.iV * G1t + s.dU * G2t - s.a * s.idiv * Axf);
+          // (A^x A^x)_t is symmetric: the linear-p term is its own transpose
+          if (F.t_divu != 0.0)
+            g += F.t_mom * F.t_divu * s.dU * (R.axxv[0] * fpp + R.axxv[1] * f + R.axxv[2] * fmm);
         } else {
           g += F.t_mom * (s.a * s.iV * G1f + s.dU * G2f - s.a * s.idiv * Axf);
+          // linear p: -div beta also holds + U' (A^x A^x)_t
+          if (F.t_divu != 0.0)
+            g += F.t_mom * F.t_divu * s.dU * (R.axxv[0] * fpp + R.axxv[1] * f + R.axxv[2] * fmm);
         }
       }
       if constexpr (XPROF) g -= F.t_adv * s.dU * f;
@@ -475,7 +485,7 @@ void stage_kernel(KernelArgs A) {
           const PointScalars s = point_scalars<D, K, MOM, XPROF>(F, ic, q);
           const double Axf = R.axv[0] * P[R.axc[0]] + R.axv[1] * P[R.axc[1]];
           const double A2f = R.axxv[0] * P[R.axxc[0]] + R.axxv[1] * fq[q] + R.axxv[2] * P[R.axxc[1]];
-          tmp[q] = -F.t_mom * (s.a * s.iV * Axf + s.dU * A2f);
+          tmp[q] = -F.t_mom * (s.a * s.ca * Axf + s.dU * s.cu * A2f);
         }
         contract_add<D, K, D - 1>(tmp, res, M.s2h[D - 1][ic[D - 1]]);
       }

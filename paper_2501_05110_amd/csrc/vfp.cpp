@@ -223,6 +223,7 @@ struct vfp_ctx {
   unsigned terms = 0;
   double mass = 1.0, charge = 1.0;
   bool mom = false;
+  bool linp = false;        // the momentum axis is p itself (else ln p)
   int nspace = 0;
   int device = -1;
   ShMatrices S;
@@ -245,7 +246,7 @@ struct vfp_ctx {
 
   // device data
   DevBuf d_s2h[3], d_u_vol, d_du_vol, d_a_vol, d_u_face;
-  DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face;
+  DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face, d_ca_vol, d_cu_vol, d_cu_face;
   DevBuf d_pf_code, d_pf_coded, d_pf_tab, d_pf_dtab, d_Bpts, d_nu, d_src;
   DevBuf d_itab, d_dtab, d_xrec, d_prec;
   RowTables tab{};
@@ -502,25 +503,38 @@ int build_momentum_data(vfp_ctx* c) {
   const int np = c->ncell[pa];
   const std::vector<double>& nd = c->nodes[pa];
   std::vector<double> g = gauss_points(c->k);
+  // beta^p along the axis xi (ln p or p): -(dU/dt ca A^x + U' cu (A^x A^x)_t)
+  // with ca = gamma m / p, cu = 1 on ln p (beta^{ln p} = beta^p / p) and
+  // ca = gamma m, cu = p on p; -div beta holds -dU/dt idiv A^x with
+  // idiv = m/(gamma p) (ln p) or -V (p; d(gamma m)/dp = V), and on p also
+  // + U' (A^x A^x)_t (FieldArgs::t_divu)
   std::vector<double> V(np * K1), iV(np * K1), idiv(np * K1), ig(np * K1), iVf(np + 1);
+  std::vector<double> ca(np * K1), cu(np * K1), cuf(np + 1);
   c->vmax = 0.0;
   for (int i = 0; i < np; ++i)
     for (int q = 0; q < K1; ++q) {
-      double lp = nd[i] + (1.0 + g[q]) * 0.5 * (nd[i + 1] - nd[i]);
-      double p = std::exp(lp);
+      double xi = nd[i] + (1.0 + g[q]) * 0.5 * (nd[i + 1] - nd[i]);
+      double p = c->linp ? xi : std::exp(xi);
       double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
-      V[i * K1 + q] = p / (gam * c->mass);
-      iV[i * K1 + q] = gam * c->mass / p;
-      idiv[i * K1 + q] = c->mass / (gam * p);
-      ig[i * K1 + q] = c->charge / (gam * c->mass);
-      c->vmax = std::max(c->vmax, V[i * K1 + q]);
+      const int j = i * K1 + q;
+      V[j] = p / (gam * c->mass);
+      iV[j] = gam * c->mass / p;
+      idiv[j] = c->linp ? -V[j] : c->mass / (gam * p);
+      ig[j] = c->charge / (gam * c->mass);
+      ca[j] = c->linp ? gam * c->mass : iV[j];
+      cu[j] = c->linp ? p : 1.0;
+      c->vmax = std::max(c->vmax, V[j]);
     }
   for (int f = 0; f <= np; ++f) {
-    double p = std::exp(nd[f]);
+    double p = c->linp ? nd[f] : std::exp(nd[f]);
     double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
-    iVf[f] = gam * c->mass / p;
+    iVf[f] = c->linp ? gam * c->mass : gam * c->mass / p;
+    cuf[f] = c->linp ? p : 1.0;
     c->vmax = std::max(c->vmax, p / (gam * c->mass));
   }
+  if (int e = upload_vec(c->d_ca_vol, ca)) return e;
+  if (int e = upload_vec(c->d_cu_vol, cu)) return e;
+  if (int e = upload_vec(c->d_cu_face, cuf)) return e;
   if (int e = upload_vec(c->d_V_vol, V)) return e;
   if (int e = upload_vec(c->d_iV_vol, iV)) return e;
   if (int e = upload_vec(c->d_idiv_vol, idiv)) return e;
@@ -597,11 +611,13 @@ int build_pface_data(vfp_ctx* c) {
         ab[((size_t)m * kBlk + i) * kBlk + j] = c->S.A[0](ri, rj);
         xb[((size_t)m * kBlk + i) * kBlk + j] = c->S.AXX(ri, rj);
       }
-  std::vector<double> inv_v(npf);
+  // coefficients of dU/dt and U' in beta^p at each p face (see build_momentum_data)
+  std::vector<double> inv_v(npf), cu_f(npf);
   for (int f = 0; f < npf; ++f) {
-    const double p = std::exp(nd[f]);
+    const double p = c->linp ? nd[f] : std::exp(nd[f]);
     const double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
-    inv_v[f] = gam * c->mass / p;
+    inv_v[f] = c->linp ? gam * c->mass : gam * c->mass / p;
+    cu_f[f] = c->linp ? p : 1.0;
   }
   const size_t rowsz = (size_t)n * (L + 1);
   struct Part {
@@ -622,7 +638,7 @@ int build_pface_data(vfp_ctx* c) {
       const double av = c->planar ? c->a_vol[ix] : 0.0;
       const double du = c->planar ? c->du_vol[ix] : 0.0;
       for (int f = 0; f < npf; ++f) {
-        const double a1 = -tm * av * inv_v[f], a2 = -tm * du;
+        const double a1 = -tm * av * inv_v[f], a2 = -tm * du * cu_f[f];
         if (a1 == 0.0 && a2 == 0.0) continue;       // beta = 0: code -1
         double bnorm = 0.0;
         double ev[kBlk][kBlk];                       // eigenvalues per block
@@ -757,7 +773,7 @@ int ensure_device(vfp_ctx* c) {
 int build_records(vfp_ctx* c) {
   // the records hold three Gauss points per axis; the (x, ln p) kernels
   // that read them exist for k <= 2
-  if (!c->mom || !c->mesh_set || c->k > 2) return VFP_OK;
+  if (!c->mom || !c->mesh_set || c->k > 2 || c->linp) return VFP_OK;
   const int K1 = c->K1, nxc = c->ncell[0], pa = c->naxes - 1, npc = c->ncell[pa];
   const double ta = (c->terms & VFP_TERM_ADVECTION) ? 1.0 : 0.0;
   const double tm = (c->terms & VFP_TERM_MOMENTUM) ? 1.0 : 0.0;
@@ -830,6 +846,10 @@ int refresh(vfp_ctx* c, unsigned what) {
   F.idiv_vol = c->d_idiv_vol.as<double>();
   F.ig_vol = c->d_ig_vol.as<double>();
   F.iV_face = c->d_iV_face.as<double>();
+  F.ca_vol = c->d_ca_vol.as<double>();
+  F.cu_vol = c->d_cu_vol.as<double>();
+  F.cu_face = c->d_cu_face.as<double>();
+  F.t_divu = c->linp ? 1.0 : 0.0;
   if (!c->mom) {
     double p = c->p_fixed;
     double gam = std::sqrt(1.0 + (p / c->mass) * (p / c->mass));
@@ -860,14 +880,15 @@ int refresh(vfp_ctx* c, unsigned what) {
   }
   c->launcher = nullptr;
   c->shock = false;
-  if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general) {
+  // the (x, ln p) specialisation is built for a ln p axis
+  const bool shock_ok = c->naxes == 2 && c->mom && !c->linp && c->planar && !c->have_Bpts && !c->force_general;
+  if (shock_ok) {
     c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot);
     c->shock = c->launcher != nullptr;
   }
   if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
   c->adj_launcher = nullptr;
-  if (c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general)
-    c->adj_launcher = find_shock_adjoint_launcher(c->k, c->lmax, c->tab.nrot);
+  if (shock_ok) c->adj_launcher = find_shock_adjoint_launcher(c->k, c->lmax, c->tab.nrot);
   if (!c->adj_launcher) c->adj_launcher = find_adjoint_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
   c->mass_launcher = find_mass_launcher(c->naxes, c->k);
   return VFP_OK;
@@ -905,8 +926,8 @@ int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
   bool mom = false;
   for (int a = 0; a < naxes; ++a) {
     int kd = axis_kinds[a];
-    if (kd == VFP_AXIS_LNP) {
-      if (a != naxes - 1) return fail(VFP_EINVAL, "the ln p axis must be the last axis");
+    if (kd == VFP_AXIS_LNP || kd == VFP_AXIS_P) {
+      if (a != naxes - 1) return fail(VFP_EINVAL, "the ln p (or p) axis must be the last axis");
       mom = true;
     } else if (kd >= VFP_AXIS_X && kd <= VFP_AXIS_Z) {
       if (kd != a) return fail(VFP_EINVAL, "spatial axes must be x, y, z in order");
@@ -935,6 +956,7 @@ int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
   c->mass = mass;
   c->charge = charge;
   c->mom = mom;
+  c->linp = mom && axis_kinds[naxes - 1] == VFP_AXIS_P;
   c->nspace = nsp;
   {
     const char* kv = std::getenv("VFP_KERNEL");
@@ -965,6 +987,8 @@ int vfp_set_mesh(vfp_ctx* c, const int* ncells, const double* const* nodes, cons
     for (int i = 0; i < ncells[a]; ++i)
       if (!(nodes[a][i + 1] > nodes[a][i]) || !std::isfinite(nodes[a][i + 1]))
         return fail(VFP_EINVAL, "nodes[%d] not strictly increasing at %d", a, i);
+    if (c->linp && a == c->naxes - 1 && !(nodes[a][0] > 0.0))
+      return fail(VFP_EINVAL, "the p axis must start above p = 0");
     for (int lohi = 0; lohi < 2; ++lohi) {
       int b = lohi ? bc_hi[a] : bc_lo[a];
       if (b < 0 || b > 2) return fail(VFP_EINVAL, "bc kind %d unknown", b);
@@ -1363,7 +1387,7 @@ int vfp_advance_tape(vfp_ctx* c, const double* u0, double dt, int64_t nsteps, do
 }
 
 static int field_grad_ready(const vfp_ctx* c) {
-  if (!(c->naxes == 2 && c->mom && c->planar))
+  if (!(c->naxes == 2 && c->mom && !c->linp && c->planar))
     return fail(VFP_EUNSUPPORTED, "field gradients need an (x, ln p) context with a planar flow");
   return VFP_OK;
 }

@@ -16,7 +16,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libvfp.so")
 
-AXIS = {"x": 0, "y": 1, "z": 2, "lnp": 3}
+AXIS = {"x": 0, "y": 1, "z": 2, "lnp": 3, "p": 4}
 TERM = {"advection": 1, "momentum": 2, "rotation": 4, "collision": 8, "source": 16}
 BC = {"periodic": 0, "zero_inflow": 1, "continuous": 2}
 PTS_VOLUME, PTS_FACE, PTS_NODE = 0, 1, 2
@@ -153,7 +153,7 @@ class Operator:
         lo = (C.c_int * d)(*[BC[b[0]] for b in wl.bc])
         hi = (C.c_int * d)(*[BC[b[1]] for b in wl.bc])
         _check(lib.vfp_set_mesh(self._ctx, nc, nptr, lo, hi))
-        self.mom = "lnp" in wl.axes
+        self.mom = "lnp" in wl.axes or "p" in wl.axes
         if not self.mom:
             _check(lib.vfp_set_momentum(self._ctx, float(wl.p_fixed)))
         self._set_fields()
@@ -186,6 +186,8 @@ class Operator:
             v = coords[a][cell_idx[a][:, None], q_idx[a][None, :]].ravel()
             if name == "lnp":
                 p = np.exp(v)
+            elif name == "p":
+                p = v
             else:
                 X[AXIS[name]] = v
         return X, p

@@ -245,14 +245,20 @@ def config1(ncells=64):
 
 def shock_workload(name, nx, np_, k, lmax, U0=0.1, r=4.0, L=10.0, w_frac=0.01,
                    nu0=1.0, lnp=(0.0, 10.0), seed=2, steps=2000, Q=0.1,
-                   lnp_inj=0.5, sigma_lnp=1.0 / 8, init=True):
+                   lnp_inj=0.5, sigma_lnp=1.0 / 8, init=True, paxis="lnp"):
+    """paxis: "lnp" (cells uniform in ln p over `lnp`) or "p" (the momentum
+    axis is p itself, cells uniform in p over exp(lnp))."""
     w = w_frac * L
     xn = uniform_nodes(-L, L, nx)
-    pn = uniform_nodes(lnp[0], lnp[1], np_)
-    pc = np.exp(0.5 * (pn[:-1] + pn[1:]))
+    if paxis == "lnp":
+        pn = uniform_nodes(lnp[0], lnp[1], np_)
+        pc = np.exp(0.5 * (pn[:-1] + pn[1:]))
+    else:
+        pn = uniform_nodes(math.exp(lnp[0]), math.exp(lnp[1]), np_)
+        pc = 0.5 * (pn[:-1] + pn[1:])
     nu_cell = np.repeat((nu0 * pc ** (-1.0 / 3.0))[:, None], nx, axis=1).ravel()
     wl = Workload(
-        name=name, lmax=lmax, k=k, axes=("x", "lnp"), nodes=(xn, pn),
+        name=name, lmax=lmax, k=k, axes=("x", paxis), nodes=(xn, pn),
         bc=((ZERO_INFLOW, CONTINUOUS), (ZERO_INFLOW, ZERO_INFLOW)),
         terms=frozenset({ADVECTION, MOMENTUM, ROTATION, COLLISION, SOURCE}),
         flow=shock_flow(U0, r, w), magnetic=uniform_field((1.0, 0.0, 0.0)),

@@ -93,6 +93,13 @@ HIGH_K_CASES = {
     "shock_k3_l3": lambda: shock(11, 6, 3, 3),
 }
 
+# momentum axis p itself (general kernels, forward and adjoint)
+P_AXIS_CASES = {
+    "shock_p_k2_l3": lambda: shock(13, 7, 2, 3, paxis="p", lnp=(-1.0, 2.5)),
+    "shock_p_k1_l5": lambda: shock(10, 6, 1, 5, paxis="p", lnp=(-1.0, 2.5)),
+    "shock_p_k3_l1": lambda: shock(9, 5, 3, 1, paxis="p", lnp=(-1.0, 2.5)),
+}
+
 CASES = {
     "c1": lambda: W.config1(),
     "shock_k2_l3": lambda: shock(25, 11, 2, 3),

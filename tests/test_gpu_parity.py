@@ -13,7 +13,7 @@ import pytest
 from oracle import dg
 from paper_2501_05110_amd import workloads as W
 
-from gpu_cases import APPLY_TOL, CASES, HIGH_K_CASES, STEPS_TOL, _say, cube, gpu_apply, rel_inf, shock
+from gpu_cases import APPLY_TOL, CASES, HIGH_K_CASES, P_AXIS_CASES, STEPS_TOL, _say, cube, gpu_apply, rel_inf, shock
 
 pytestmark = pytest.mark.gpu
 
@@ -201,3 +201,38 @@ def test_convergence_study_on_gpu(lib, cuda, k):
     lsq = -np.polyfit(np.log2(grids), np.log2(errs), 1)[0]
     _say(f"[convergence] k={k} errors={['%.3e' % e for e in errs]} order={lsq:.2f}")
     assert lsq > k + 1 - 0.2, (errs, lsq)
+
+
+@pytest.mark.parametrize("name", list(P_AXIS_CASES))
+def test_p_axis_parity(lib, cuda, name):
+    """A linear momentum axis p (beta^p and its divergence of
+    eq. definitions-advection-reaction-eq): apply with and without the source,
+    100 steps, and (k <= 2) the adjoint apply, against the oracle."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator, VFPError
+    wl = P_AXIS_CASES[name]()
+    _say(f"[p-axis] {name}: k={wl.k} cells={wl.ncells_axis} ndofs={wl.ndofs}")
+    op = Operator(wl)
+    S = dg.assemble(wl)
+    z = W.random_state(wl, 23)
+    for ws in (True, False):
+        err = rel_inf(gpu_apply(op, z, ws), dg.apply(S, z, ws))
+        _say(f"   apply with_source={ws} rel_inf={err:.3e}")
+        assert err <= APPLY_TOL, (name, ws, err)
+    dt = op.cfl_dt(0.2) / wl.k
+    u = torch.from_numpy(z.ravel().copy()).cuda()
+    work = torch.empty(2 * wl.ndofs, dtype=torch.float64, device="cuda")
+    op.advance(u, dt, 100, work)
+    torch.cuda.synchronize()
+    err = rel_inf(u.cpu().numpy(), dg.rk4(S, z, dt, 100))
+    _say(f"   100 steps rel_inf={err:.3e}")
+    assert err <= STEPS_TOL, (name, err)
+    y = torch.empty_like(u)
+    if wl.k <= 2:
+        op.apply_adjoint(torch.from_numpy(z.ravel().copy()).cuda(), y)
+        torch.cuda.synchronize()
+        err = rel_inf(y.cpu().numpy(), dg.apply_adjoint(S, z.ravel()))
+        _say(f"   apply_adjoint rel_inf={err:.3e}")
+        assert err <= APPLY_TOL, (name, err)
+        with pytest.raises(VFPError):
+            op.field_grad_size()

@@ -175,6 +175,26 @@ def test_adjoint_identity():
     assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + 1)
 
 
+def test_p_divergence_matches_finite_difference():
+    """On a linear p axis the divergence term equals d beta^p / dp (finite
+    differences of the advection matrix along p)."""
+    lmax = 3
+    phys = dg.Physics(lmax, frozenset({W.MOMENTUM}))
+    flow = W.shock_flow(0.1, 4.0, 0.3)
+    X = np.array([[0.05], [0.0], [0.0]])
+    p0 = 1.7
+    hs = 1e-5
+    b = [dg.point_coefficients(phys, ("x", "p"), X, np.array([p0 + s]), flow, None,
+                               np.zeros(1))[0][1, 0] for s in (-hs, hs)]
+    fd = (b[1] - b[0]) / (2 * hs)
+    div = dg.point_terms(phys, ("x", "p"), X, np.array([p0]), flow, None, np.zeros(1))[2][0]
+    np.testing.assert_allclose(div, fd, atol=1e-8)
+    # and beta^p = p beta^{ln p} (the ln p axis divides the momentum flux by p)
+    blin = dg.point_coefficients(phys, ("x", "p"), X, np.array([p0]), flow, None, np.zeros(1))[0][1, 0]
+    blog = dg.point_coefficients(phys, ("x", "lnp"), X, np.array([p0]), flow, None, np.zeros(1))[0][1, 0]
+    np.testing.assert_allclose(blin, p0 * blog, atol=1e-14)
+
+
 def test_lnp_divergence_matches_finite_difference():
     """The ln-p divergence term equals d beta^{ln p} / d ln p (finite
     differences of the advection matrix along ln p)."""
@@ -257,9 +277,10 @@ def test_convergence_study_spatial_order(k):
 # ------------------------------------------------- manufactured solution --
 
 @pytest.mark.slow
+@pytest.mark.parametrize("axis", ["lnp", "p"])
 @pytest.mark.parametrize("k", [1, 2])
-def test_manufactured_momentum_terms(k):
-    """Variable coefficients with all terms on (tanh flow, ln-p axis):
+def test_manufactured_momentum_terms(k, axis):
+    """Variable coefficients with all terms on (tanh flow, ln-p or p axis):
     choose a smooth bump f*, set s = beta.grad f* + R f*, solve D zeta = h and
     check ||zeta - Pi f*|| converges at order >= k+1-0.3."""
     lmax = 2
@@ -282,16 +303,19 @@ def test_manufactured_momentum_terms(k):
             if ax == 0:
                 Xp[0] += h
                 Xm[0] -= h
-            else:
+            elif axis == "lnp":
                 pp = p * math.exp(h)
                 pm = p * math.exp(-h)
+            else:
+                pp = p + h
+                pm = p - h
             out.append((fstar(Xp, pp) - fstar(Xm, pm)) / (2 * h))
         return out
 
     def source(X, p):
         # strong form beta . grad f* + R f*, with beta and R from the oracle's
         # coefficient evaluation (pinned separately); div(beta) is not used
-        beta, R, _ = dg.point_terms(phys, ("x", "lnp"), X, p, flow, Bf, np.full(X.shape[1], 0.5))
+        beta, R, _ = dg.point_terms(phys, ("x", axis), X, p, flow, Bf, np.full(X.shape[1], 0.5))
         gx, gp = grad(X, p)
         f = fstar(X, p)
         return (np.einsum("qij,jq->iq", beta[0], gx) + np.einsum("qij,jq->iq", beta[1], gp)
@@ -301,9 +325,14 @@ def test_manufactured_momentum_terms(k):
     # "continuous" condition is pinned by the uniform-state and DSA tests; it
     # adds a boundary error mode that hides the interior order.)
     errs = []
-    for nc in ((12, 24, 48) if k == 1 else (8, 16, 32)):
-        wl = W.Workload(name="mms", lmax=lmax, k=k, axes=("x", "lnp"),
-                        nodes=(W.uniform_nodes(-3, 3, nc), W.uniform_nodes(-1.0, 3.0, nc)),
+    # on a p axis the bump (centred at ln p = 1) is narrow at small p: a wider
+    # p range keeps f* ~ 1e-5 at the ends, and finer grids reach the order
+    grids = (12, 24, 48) if (k == 1 or axis == "p") else (8, 16, 32)
+    for nc in grids:
+        pn = (W.uniform_nodes(-1.0, 3.0, nc) if axis == "lnp"
+              else W.uniform_nodes(0.3, 15.0, nc))
+        wl = W.Workload(name="mms", lmax=lmax, k=k, axes=("x", axis),
+                        nodes=(W.uniform_nodes(-3, 3, nc), pn),
                         bc=((W.ZERO_INFLOW, W.ZERO_INFLOW), (W.ZERO_INFLOW, W.ZERO_INFLOW)),
                         terms=phys.terms, flow=flow, magnetic=Bf, nu=0.5)
         S = dg.assemble(wl)
