@@ -23,7 +23,9 @@ and class against one run per launch sequence (--batch-full: the 256 runs
 of 128-1024 x 32-128 cells), and the stage throughput of the 3-D box
 (48^3, k=2, l_max=5) and the 1-D line (64 cells, k=1, l_max=3), and
 Theta-method steps (Crank-Nicolson, backward Euler) of the 512 x 64 shock at
-10 times the explicit time step.
+10 times the explicit time step, and (with the other configurations) the
+reconstruction of f in 64 directions, a k = 5 line and the shock on a linear
+p axis.
 """
 
 from __future__ import annotations
@@ -248,6 +250,76 @@ def batch_timing(full=False, steps=None):
             "classes": [{k: c[k] for k in ("k", "lmax", "runs", "tiles", "tile_map")} for c in cls]}
 
 
+def extension_timing():
+    """The rows beyond the explicit (x, ln p) path, each with its HBM roofline
+    fraction (algorithmic bytes per launch / launch time / 8 TB/s):
+    * reconstruction of f in 64 directions from the 1024 x 128 shock state
+      (reads the state and the table, writes rows x 64 values);
+    * a 1-D line at k = 5 (8192 cells, l_max = 7) and the 512 x 64 shock on a
+      linear p axis (k = 2, l_max = 3), both on the general kernels: stage
+      launches, 16 B/DoF for the first stage and 24 B/DoF for the others."""
+    import math
+    import numpy as np
+    import torch
+    from paper_2501_05110_amd import vfp, workloads as W
+
+    out = {}
+    stream = torch.cuda.current_stream()
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / reps
+
+    wl = W.config2(steps=1)
+    op = vfp.Operator(wl)
+    ndir = 64
+    g = np.random.default_rng(11)
+    th, ph = np.arccos(g.uniform(-1, 1, ndir)), g.uniform(0, 2 * math.pi, ndir)
+    Y = torch.from_numpy(vfp.sh_eval(wl.lmax, th, ph)).cuda()
+    z = torch.from_numpy(np.ascontiguousarray(wl.meta["init"]).ravel()).cuda()
+    rows = op.ndofs // wl.n_lms
+    f = torch.empty(rows * ndir, dtype=torch.float64, device="cuda")
+    t = timed(lambda: op.reconstruct(z, Y, f), 20)
+    bts = 8 * (op.ndofs + Y.numel() + rows * ndir)
+    out["reconstruct_shock2d_1024x128_64dirs"] = {
+        "us_per_launch": t * 1e6, "bytes_per_launch": bts, "achieved_GBs": bts / t / 1e9,
+        "frac": bts / t / 1e9 / HBM_PEAK_GBS}
+    op.close()
+    del f, z
+
+    cases = (
+        ("line1d_8192_k5_lmax7", W.Workload(
+            name="line_k5", lmax=7, k=5, axes=("x",), nodes=(W.uniform_nodes(-10.0, 10.0, 8192),),
+            bc=((W.PERIODIC, W.PERIODIC),), terms=frozenset({W.ADVECTION, W.ROTATION, W.COLLISION}),
+            p_fixed=math.sqrt(3.0), flow=W.zero_flow, magnetic=W.uniform_field((0.0, 0.0, 1.0)), nu=1.0)),
+        ("shock2d_x_p_512x64_k2_lmax3", W.shock_workload("shock_p", 512, 64, 2, 3, paxis="p",
+                                                         lnp=(-1.0, 2.5), init=False)),
+    )
+    for name, wl in cases:
+        op = vfp.Operator(wl)
+        N = op.ndofs
+        u = torch.from_numpy(W.random_state(wl, 5, 1e-3).ravel()).cuda()
+        work = torch.empty(2 * N, dtype=torch.float64, device="cuda")
+        dt = op.cfl_dt(0.2) / wl.k
+        steps = 20
+        t = timed(lambda: op.advance(u, dt, steps, work), 1) / steps
+        bts = N * (16 + 3 * 24) / 4
+        out[name] = {"ndofs": N, "dofs_per_s": N / t, "us_per_launch": t / 4 * 1e6,
+                     "bytes_per_launch": bts, "achieved_GBs": bts / (t / 4) / 1e9,
+                     "frac": bts / (t / 4) / 1e9 / HBM_PEAK_GBS}
+        if not torch.isfinite(u).all():
+            raise RuntimeError(f"{name}: state is not finite")
+        op.close()
+    return out
+
+
 def theta_timing(steps=5, cfl_mult=10.0):
     """Theta-method steps (Crank-Nicolson and backward Euler) of the 512 x 64
     shock, k=2, l_max=3, at 10 times the explicit time step: restarted GMRES
@@ -435,6 +507,8 @@ def main():
         out["other_configs"] = other_configs()
     if not args.no_theta:
         out["theta"] = theta_timing()
+    if not args.no_other:
+        out["extensions"] = extension_timing()
     if args.batch_full:
         out["batch_full"] = batch_timing(full=True)
     if not args.no_cpu:

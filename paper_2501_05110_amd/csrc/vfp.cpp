@@ -1703,7 +1703,7 @@ int vfp_reconstruct(const vfp_ctx* c, const double* zeta, const double* Y, int64
   int64_t N = 0;
   vfp_ndofs(c, &N);
   const int64_t rows = N / n;
-  if ((ndir + 31) / 32 > 65535) return fail(VFP_EINVAL, "ndir too large");
+  if ((ndir + 63) / 64 > 65535) return fail(VFP_EINVAL, "ndir too large");
   if (overlaps(zeta, N, out, rows * ndir)) return fail(VFP_EINVAL, "out overlaps zeta");
   launch_reconstruct(zeta, rows, n, Y, ndir, out, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
