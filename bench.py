@@ -329,6 +329,7 @@ def theta_timing(steps=5, cfl_mult=10.0):
     import torch
     from paper_2501_05110_amd import vfp, workloads as W
 
+    import math
     wl = W.config5(steps=steps)
     op = vfp.Operator(wl)
     N = op.ndofs
@@ -351,8 +352,40 @@ def theta_timing(steps=5, cfl_mult=10.0):
             raise RuntimeError(f"Theta-method {name} did not converge: {st}")
         res[name] = {"s_per_step": t / steps, "iterations_per_step": st["iterations"] / steps,
                      "residual": st["residual"]}
-    u = u0.clone()
+    # strong scattering (nu0 = 300): explicit steps are limited by the
+    # reaction stiffness as well; the collision-diagonal preconditioner
+    # inverts the stiff part exactly
+    wl_s = W.shock_workload("shock_512x64_nu300", 512, 64, 2, 3, nu0=300.0, init=False)
+    op_s = vfp.Operator(wl_s)
+    nu_max = float(np.max(wl_s.nu))
+    dt_cfl = op_s.cfl_dt(wl_s.courant)
+    dt_rk = min(dt_cfl, 0.9 * 2.785 / (nu_max * wl_s.lmax * (wl_s.lmax + 1) / 2))
+    stiff = {"nu_max": nu_max, "dt_cfl": dt_cfl, "dt_explicit_stable": dt_rk, "dt_implicit": cfl_mult * dt_cfl}
+    us0 = torch.from_numpy(W.random_state(wl_s, 9, 1e-3).ravel()).to(dev)
+    for name, pc in (("crank_nicolson", None), ("crank_nicolson_precond", "collision")):
+        u = us0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = op_s.theta_advance(u, cfl_mult * dt_cfl, 2, theta=0.5, tol=1e-10, restart=30, work=work,
+                                precond=pc)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / 2
+        if not st["converged"]:
+            raise RuntimeError(f"stiff Theta-method {name} did not converge: {st}")
+        stiff[name] = {"s_per_step": t, "iterations_per_step": st["iterations"] / 2,
+                       "s_per_unit_time": t / (cfl_mult * dt_cfl)}
+    u = us0.clone()
     w2 = torch.empty(2 * N, dtype=torch.float64, device=dev)
+    nrk = int(math.ceil(cfl_mult * dt_cfl / dt_rk)) * 2
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op_s.advance(u, dt_rk, nrk, w2)
+    torch.cuda.synchronize()
+    stiff["explicit_rk4_s_per_unit_time"] = (time.perf_counter() - t0) / (nrk * dt_rk)
+    res["stiff_scattering"] = stiff
+    op_s.close()
+
+    u = u0.clone()
     op.advance(u, dt_exp, 5, w2)
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -316,11 +316,17 @@ int vfp_reconstruct(const vfp_ctx* ctx, const double* zeta, const double* Y, int
  * the true residual norm is at most tol times the right-hand side's
  * (Euclidean norms).
  */
+#define VFP_PRECOND_NONE      0
+#define VFP_PRECOND_COLLISION 1   /* right preconditioner 1 / (1 + dt Theta nu_c l(l+1)/2) per
+                                     DoF: the exact inverse of the scattering part of the
+                                     system (the inverse mass reduces it to that factor) */
+
 typedef struct vfp_theta_opts {
   double theta;       /* in [0, 1]                                            */
   double tol;         /* relative residual, > 0                               */
   int restart;        /* Krylov vectors per cycle, 1 .. 64                    */
   int max_iters;      /* Krylov iterations per step, >= 1                     */
+  int precond;        /* VFP_PRECOND_*                                        */
 } vfp_theta_opts;
 
 typedef struct vfp_theta_stats {
@@ -330,7 +336,7 @@ typedef struct vfp_theta_stats {
 } vfp_theta_stats;
 
 /* Doubles of device work space for vfp_theta_advance with `restart` vectors:
- * (restart + 4) ndofs plus a fixed reduction area. */
+ * (restart + 5) ndofs plus a fixed reduction area. */
 int vfp_theta_work_size(const vfp_ctx* ctx, int restart, int64_t* n);
 
 /* Advance u (device, ndofs doubles, in place) by nsteps Theta-method steps.

@@ -94,6 +94,22 @@ __global__ __launch_bounds__(kKryThreads) void lincomb_kernel(double* out, doubl
     out[i] = (b == 0.0) ? a * x[i] : fma(a, x[i], b * y[i]);
 }
 
+// out = in / (1 + s nu_c c_lms): the scattering part of I - dt Theta L0,
+// which the inverse mass reduces to the exact per-DoF factor nu_c l(l+1)/2
+// (in may alias out).  nu: per cell or null (nu0).
+__global__ __launch_bounds__(kKryThreads) void coll_precond_kernel(double* out, const double* in,
+                                                                    const double* __restrict__ nu, double nu0,
+                                                                    const double* __restrict__ cval, double s,
+                                                                    int64_t per_cell, int n, int64_t total) {
+  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; i < total; i += stride) {
+    const int64_t cell = i / per_cell;
+    const int r = (int)(i % n);
+    const double nc = nu ? nu[cell] : nu0;
+    out[i] = in[i] / fma(s * nc, cval[r], 1.0);
+  }
+}
+
 int grid_for(int64_t n) {
   const int64_t g = (n + kKryThreads - 1) / kKryThreads;
   return (int)(g < 1 ? 1 : (g > kKryBlocks ? kKryBlocks : g));
@@ -113,6 +129,13 @@ void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coe
                hipStream_t s) {
   if (k <= 0) return;
   hipLaunchKernelGGL(maxpy_kernel, dim3(grid_for(n)), dim3(kKryThreads), 0, s, w, V, ldv, k, coef, sign, n);
+}
+
+void kry_coll_precond(double* out, const double* in, const double* nu, double nu0, const double* cval, double s,
+                      int64_t ncells, int nb, int n, hipStream_t st) {
+  const int64_t per_cell = (int64_t)nb * n, total = ncells * per_cell;
+  hipLaunchKernelGGL(coll_precond_kernel, dim3(grid_for(total)), dim3(kKryThreads), 0, st, out, in, nu, nu0, cval, s,
+                     per_cell, n, total);
 }
 
 void kry_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t s) {

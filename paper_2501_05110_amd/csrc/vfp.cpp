@@ -1534,14 +1534,14 @@ int vfp_adjoint_checkpointed(vfp_ctx* c, const double* ckpt, double dt, int64_t 
 namespace {
 
 // Work layout (doubles): V [(m+1) N] Krylov basis, w [N], b [N] right-hand
-// side, s [N] = M^{-1} h, partial [kKryMaxVectors kKryBlocks], dots
-// [3 kKryMaxVectors].
+// side, s [N] = M^{-1} h, z [N] preconditioned vector, partial
+// [kKryMaxVectors kKryBlocks], dots [3 kKryMaxVectors].
 struct ThetaWork {
-  double *V, *w, *b, *s, *partial, *d1, *d2, *d3;
+  double *V, *w, *b, *s, *z, *partial, *d1, *d2, *d3;
 };
 
 int64_t theta_work_len(int64_t N, int m) {
-  return (int64_t)(m + 4) * N + (int64_t)kKryMaxVectors * kKryBlocks + 3 * kKryMaxVectors;
+  return (int64_t)(m + 5) * N + (int64_t)kKryMaxVectors * kKryBlocks + 3 * kKryMaxVectors;
 }
 
 ThetaWork theta_split(double* work, int64_t N, int m) {
@@ -1550,7 +1550,8 @@ ThetaWork theta_split(double* work, int64_t N, int m) {
   t.w = t.V + (int64_t)(m + 1) * N;
   t.b = t.w + N;
   t.s = t.b + N;
-  t.partial = t.s + N;
+  t.z = t.s + N;
+  t.partial = t.z + N;
   t.d1 = t.partial + (int64_t)kKryMaxVectors * kKryBlocks;
   t.d2 = t.d1 + kKryMaxVectors;
   t.d3 = t.d2 + kKryMaxVectors;
@@ -1576,6 +1577,11 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
   hipStream_t st = (hipStream_t)stream;
   const int m = o.restart;
   const double th = o.theta;
+  const bool pre = o.precond == VFP_PRECOND_COLLISION;
+  const double sp = dt * th * ((c->terms & VFP_TERM_COLLISION) ? 1.0 : 0.0);
+  auto precond = [&](double* out, const double* in) {
+    kry_coll_precond(out, in, c->fld.nu_cell, c->fld.nu0, c->tab.c_val, sp, c->ncells, c->nb, c->n, st);
+  };
   // right-hand side b = u + dt (1 - Theta) L(u) + dt Theta M^{-1} h
   if (th < 1.0) {
     if (int e = launch(c, u, u, t.b, 1.0, dt * (1.0 - th), 1, stream)) return e;
@@ -1626,10 +1632,16 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
     g[0] = beta;
     int j = 0;
     while (j < m && used < o.max_iters) {
-      // w = A V_j, orthogonalised against V_0..V_j by classical Gram-Schmidt;
-      // a second pass only where the first removed most of w (the criterion
-      // of Daniel, Gragg, Kaufman and Stewart: |w_new| < |w_old| / sqrt 2)
-      if (int e = theta_op(c, t.V + (int64_t)j * N, t.w, dt, th, stream)) return e;
+      // w = A P^{-1} V_j, orthogonalised against V_0..V_j by classical
+      // Gram-Schmidt; a second pass only where the first removed most of w
+      // (the criterion of Daniel, Gragg, Kaufman and Stewart:
+      // |w_new| < |w_old| / sqrt 2)
+      const double* vin = t.V + (int64_t)j * N;
+      if (pre) {
+        precond(t.z, vin);
+        vin = t.z;
+      }
+      if (int e = theta_op(c, vin, t.w, dt, th, stream)) return e;
       kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d1, st);
       kry_mdot(t.w, N, 1, t.w, N, t.partial, t.d3, st);
       kry_maxpy(t.w, t.V, N, j + 1, t.d1, -1.0, N, st);
@@ -1674,7 +1686,15 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
       y[i] = d != 0.0 ? acc / d : 0.0;
     }
     HIP_TRY(hipMemcpyAsync(t.d1, y.data(), j * sizeof(double), hipMemcpyHostToDevice, st));
-    kry_maxpy(u, t.V, N, j, t.d1, 1.0, N, st);
+    if (pre) {
+      // u += P^{-1} V y
+      kry_lincomb(t.z, 0.0, t.z, 0.0, nullptr, N, st);
+      kry_maxpy(t.z, t.V, N, j, t.d1, 1.0, N, st);
+      precond(t.z, t.z);
+      kry_lincomb(u, 1.0, u, 1.0, t.z, N, st);
+    } else {
+      kry_maxpy(u, t.V, N, j, t.d1, 1.0, N, st);
+    }
     HIP_TRY(hipGetLastError());
   }
   it += used;
@@ -1727,6 +1747,8 @@ int vfp_theta_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, const vf
   if (!(o->tol > 0.0)) return fail(VFP_EINVAL, "tol must be positive");
   if (o->restart < 1 || o->restart > 64) return fail(VFP_EINVAL, "restart must be in 1..64");
   if (o->max_iters < 1) return fail(VFP_EINVAL, "max_iters must be >= 1");
+  if (o->precond != VFP_PRECOND_NONE && o->precond != VFP_PRECOND_COLLISION)
+    return fail(VFP_EINVAL, "precond %d unknown", o->precond);
   if (nsteps < 0 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps");
   int64_t N = 0;
   vfp_ndofs(c, &N);

@@ -30,7 +30,8 @@ class VFPError(RuntimeError):
 
 class ThetaOpts(C.Structure):
     """vfp_theta_opts"""
-    _fields_ = [("theta", C.c_double), ("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int)]
+    _fields_ = [("theta", C.c_double), ("tol", C.c_double), ("restart", C.c_int), ("max_iters", C.c_int),
+                ("precond", C.c_int)]
 
 
 class ThetaStats(C.Structure):
@@ -342,15 +343,17 @@ class Operator:
         return n.value
 
     def theta_advance(self, u, dt, nsteps, theta=0.5, tol=1e-12, restart=30, max_iters=1000, work=None,
-                      stream=None):
+                      precond=None, stream=None):
         """nsteps Theta-method steps in place on u (vfp_theta_advance);
         returns {"iterations", "residual", "converged"}.  work: device
-        tensor of >= theta_work_size(restart) doubles (allocated if None)."""
+        tensor of >= theta_work_size(restart) doubles (allocated if None);
+        precond: None or "collision" (VFP_PRECOND_COLLISION)."""
         import torch
         need = self.theta_work_size(restart)
         if work is None:
             work = torch.empty(need, dtype=torch.float64, device=u.device)
-        opts = ThetaOpts(float(theta), float(tol), int(restart), int(max_iters))
+        pc = {None: 0, "none": 0, "collision": 1}.get(precond, precond)
+        opts = ThetaOpts(float(theta), float(tol), int(restart), int(max_iters), int(pc))
         st = ThetaStats()
         _check(_lib.vfp_theta_advance(self._ctx, self._t(u, "u"), float(dt), int(nsteps), C.byref(opts),
                                       self._t(work, "work", need), int(work.numel()), C.byref(st),
