@@ -1725,6 +1725,7 @@ int vfp_reconstruct(const vfp_ctx* c, const double* zeta, const double* Y, int64
   const int64_t rows = N / n;
   if ((ndir + 63) / 64 > 65535) return fail(VFP_EINVAL, "ndir too large");
   if (overlaps(zeta, N, out, rows * ndir)) return fail(VFP_EINVAL, "out overlaps zeta");
+  if (overlaps(Y, ndir * n, out, rows * ndir)) return fail(VFP_EINVAL, "out overlaps Y");
   launch_reconstruct(zeta, rows, n, Y, ndir, out, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return VFP_OK;

@@ -332,6 +332,8 @@ class Operator:
     def reconstruct(self, zeta, Y, out, stream=None):
         """out[row, d] = sum_lms zeta[row, lms] Y[d, lms] at every basis node
         (vfp_reconstruct); Y: device table (ndir, n), e.g. from sh_eval."""
+        if Y.numel() == 0 or Y.numel() % self.wl.n_lms:
+            raise VFPError(f"Y must hold ndir x {self.wl.n_lms} values")
         ndir = Y.numel() // self.wl.n_lms
         rows = self.ndofs // self.wl.n_lms
         _check(_lib.vfp_reconstruct(self._ctx, self._t(zeta, "zeta"), self._t(Y, "Y", ndir * self.wl.n_lms),
