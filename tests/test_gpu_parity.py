@@ -236,3 +236,38 @@ def test_p_axis_parity(lib, cuda, name):
         assert err <= APPLY_TOL, (name, err)
         with pytest.raises(VFPError):
             op.field_grad_size()
+
+
+def test_time_order_on_gpu(lib, cuda):
+    """Fig. 3 left on the library: the Sec. 4.1 setup at k = 5 on 64 cells
+    (spatial error far below the time error), advanced to t = 10/omega in
+    128, 256 and 512 steps: the error of f000 falls as dt^4 (ERK4)."""
+    import math
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    from test_oracle_dg import _convergence_exact
+    L, gam = 20.0, 2.0
+    p = math.sqrt(gam * gam - 1)
+    w = 2 * math.pi / gam
+    exact = _convergence_exact(L, p / gam, w, 2.0, 1.0)
+    tF = 10.0 / w
+    wl = W.Workload(name="conv_t", lmax=1, k=5, axes=("x",), nodes=(W.uniform_nodes(0.0, L, 64),),
+                    bc=((W.PERIODIC, W.PERIODIC),), terms=frozenset({W.ADVECTION, W.ROTATION}), p_fixed=p,
+                    magnetic=W.uniform_field((0, 0, 2 * math.pi)))
+    op = Operator(wl)
+    z0 = dg.project(wl, exact(0.0)).ravel()
+    only000 = lambda X, p_, f=exact(tF): f(X, p_) * np.array([1, 0, 0, 0])[:, None]
+    errs, dts = [], []
+    for nsteps in (128, 256, 512):
+        dt = tF / nsteps
+        u = torch.from_numpy(z0.copy()).cuda()
+        work = torch.empty(2 * wl.ndofs, dtype=torch.float64, device="cuda")
+        op.advance(u, dt, nsteps, work)
+        torch.cuda.synchronize()
+        z = u.cpu().numpy().reshape(wl.shape)
+        z[:, :, 1:] = 0
+        errs.append(dg.l2_error(wl, z, only000))
+        dts.append(dt)
+    order = np.polyfit(np.log2(dts), np.log2(errs), 1)[0]
+    _say(f"[time order] dt={['%.3f' % d for d in dts]} errors={['%.3e' % e for e in errs]} order={order:.2f}")
+    assert order > 3.8, (errs, order)
