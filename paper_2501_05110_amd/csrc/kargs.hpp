@@ -95,6 +95,7 @@ struct FieldArgs {
   //           t_mom / V at the lo / hi face [2], 2/h_p
   const double* xrec;
   const double* prec;
+  const double* prec2;    // linear p axis: [ip][8] gamma m (3), p (3) at the Gauss points, p at the faces (2)
   // magnetic field
   double B[3];            // uniform B
   const double* B_pts;    // [cell][q][3] or null

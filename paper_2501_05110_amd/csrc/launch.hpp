@@ -21,8 +21,9 @@ MassLauncher find_mass_launcher(int D, int k);
 
 // Specialised kernel for two axes (x, ln p) with a planar x flow and a
 // uniform B; nrot = padded non-zeros per row of B.Omega (1 or 5).
-StageLauncher find_shock_launcher(int k, int lmax, int nrot);
-StageLauncher find_shock_adjoint_launcher(int k, int lmax, int nrot);
+// linp: the momentum axis is p itself instead of ln p.
+StageLauncher find_shock_launcher(int k, int lmax, int nrot, bool linp = false);
+StageLauncher find_shock_adjoint_launcher(int k, int lmax, int nrot, bool linp = false);
 
 // Batched (x, ln p) forward stage over many runs of one (k, l_max, nrot)
 // class: one workgroup per tile.

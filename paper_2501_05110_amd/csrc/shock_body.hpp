@@ -70,8 +70,14 @@ enum : int {
   P_S2H = 30,    // 2/h_p
   C_CODE = 32,   // p-face upwind codes [side][x point]                 [2*K1]
   C_NU = 38,     // t_col nu
-  S_STRIDE = 40
+  S_STRIDE = 40,
+  // linear p axis only: coefficients of dU/dt and U' in beta^p
+  P2_CA = 40,    // gamma m at the p Gauss points                      [3]
+  P2_CU = 43,    // p at the p Gauss points                            [3]
+  P2_CUF = 46,   // p at the lo / hi p face                            [2]
+  S_STRIDE_LINP = 48
 };
+constexpr int kRec2 = 8;         // doubles per extra p record (linear p axis)
 static_assert(kRec == 16, "record layout");
 
 template <int N>
@@ -97,7 +103,11 @@ __device__ __forceinline__ void cell_sync() {
 
 // One tile (kCells cells) of one run: the whole operator / stage for those
 // cells.  blk is the tile index within the run.
-template <int K, int LMAX, int NROT, bool ADJ>
+// LINP: the momentum axis is p itself (beta^p = -(dU/dt gamma m A^x
+// + U' p (A^x A^x)_t), -div beta = dU/dt V A^x + U' (A^x A^x)_t - div U);
+// the p record then carries V, 1/V, -V (in the m/(gamma p) slot), q/(gamma m),
+// t_mom gamma m at the faces, and the extra record gamma m, p, p at the faces.
+template <int K, int LMAX, int NROT, bool ADJ, bool LINP = false>
 __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
@@ -108,7 +118,8 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   static_assert(K1 <= 3, "basis tables");
   constexpr int XS = XR * N;           // per-cell exchange area
   __shared__ double shx[CPB * XS];
-  __shared__ double shs[CPB * S_STRIDE];
+  constexpr int SST = LINP ? S_STRIDE_LINP : S_STRIDE;
+  __shared__ double shs[CPB * SST];
 
   const int tid = threadIdx.x;
   const int cl = tid / N;
@@ -124,7 +135,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   const int ix = cell % nx, ip = cell / nx;
   const int clc = in_grp ? cl : 0;
   double* X = shx + clc * XS;
-  double* sc = shs + clc * S_STRIDE;
+  double* sc = shs + clc * SST;
 
   // ---- issue every global load, in order of first use ------------------------
   constexpr int NREC = (kRec + N - 1) / N;
@@ -143,6 +154,15 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
                                        : 0.0;
   }
   if (in_grp && r == 0) rnu = F.t_col * (gp(F.nu_cell) ? gp(F.nu_cell)[cell] : F.nu0);
+  constexpr int NREC2 = LINP ? (kRec2 + N - 1) / N : 1;
+  double rp2[NREC2];
+  if constexpr (LINP) {
+#pragma unroll
+    for (int it = 0; it < NREC2; ++it) {
+      const int e = r + it * N;
+      rp2[it] = (in_grp && e < kRec2) ? gp(F.prec2)[(size_t)ip * kRec2 + e] : 0.0;
+    }
+  }
 
   const size_t cbase = (size_t)cell * NB * N + r;
   const auto win = gp(A.st.w_in) + cbase;
@@ -199,6 +219,13 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
       if (e < 2 * K1) sc[C_CODE + e] = rcode[it];
     }
     if (r == 0) sc[C_NU] = rnu;
+    if constexpr (LINP) {
+#pragma unroll
+      for (int it = 0; it < NREC2; ++it) {
+        const int e = r + it * N;
+        if (e < kRec2) sc[P2_CA + e] = rp2[it];
+      }
+    }
   }
 
   double res[NB];
@@ -288,7 +315,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   // by all lanes alike.
   bool grad = false;
 #pragma unroll
-  for (int c2 = 0; c2 < CPB; ++c2) grad |= shs[c2 * S_STRIDE + X_GRAD] != 0.0;
+  for (int c2 = 0; c2 < CPB; ++c2) grad |= shs[c2 * SST + X_GRAD] != 0.0;
 
   // ---- ln p faces: beta^{ln p} = a1 A^x + a2 (A^x A^x)_t per point ---------
   const int axc0 = gp(T.ax_col)[r], axc1 = gp(T.ax_col)[N + r];
@@ -333,7 +360,8 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
     for (int q = 0; q < K1; ++q) {
       const double a1 = -sc[X_A + q] * iVf;
-      const double a2 = -F.t_mom * sc[X_DU + q];
+      double a2 = -F.t_mom * sc[X_DU + q];
+      if constexpr (LINP) a2 *= sc[P2_CUF + side];
       const int code = (int)sc[C_CODE + side * K1 + q];
       const double* P1 = X + q * N;
       const double* P2 = X + (K1 + q) * N;
@@ -451,9 +479,14 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
             const double A2f = fma(axxv0, fpp, fma(axxv1, f, axxv2 * fmm));
             const double G2f = fma(g2v0, fpp, fma(g2v1, f, g2v2 * fmm));
             const double aiV = a * piV;
-            Pp = mom_s2hp * fma(aiV, Axf, dU * A2f);
+            if constexpr (LINP) {
+              Pp = mom_s2hp * fma(a * sc[P2_CA + q1], Axf, dU * sc[P2_CU + q1] * A2f);
+            } else {
+              Pp = mom_s2hp * fma(aiV, Axf, dU * A2f);
+            }
             G = fma(aiV, G1f, dU * fma(t_mom, G2f, -t_adv * f));
             G = fma(-a * pid, Axf, G);
+            if constexpr (LINP) G = fma(t_mom * dU, A2f, G);
           }
           G = fma(-pig, Rf, G);
           G = fma(nuc, f, G);
@@ -563,7 +596,13 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
             G = fma(-a * pid, Axf, G);
             const double Axp = fma(axv0, Qp[axc0], axv1 * Qp[axc1]);
             const double A2p = fma(axxv0, Qp[axxc0], fma(axxv1, Qp[r], axxv2 * Qp[axxc1]));
-            Pa = mom_s2hp * fma(aiV, Axp, dU * A2p);
+            if constexpr (LINP) {
+              // (A^x A^x)_t is symmetric: the divergence term is its own transpose
+              G = fma(t_mom * dU, fma(axxv0, fpp, fma(axxv1, f, axxv2 * fmm)), G);
+              Pa = mom_s2hp * fma(a * sc[P2_CA + q1], Axp, dU * sc[P2_CU + q1] * A2p);
+            } else {
+              Pa = mom_s2hp * fma(aiV, Axp, dU * A2p);
+            }
           }
           G = fma(pig, Rf, G);                // (B.Omega)^T = -B.Omega
           G = fma(nuc, f, G);

@@ -248,7 +248,7 @@ struct vfp_ctx {
   DevBuf d_s2h[3], d_u_vol, d_du_vol, d_a_vol, d_u_face;
   DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face, d_ca_vol, d_cu_vol, d_cu_face;
   DevBuf d_pf_code, d_pf_coded, d_pf_tab, d_pf_dtab, d_Bpts, d_nu, d_src;
-  DevBuf d_itab, d_dtab, d_xrec, d_prec;
+  DevBuf d_itab, d_dtab, d_xrec, d_prec, d_prec2;
   RowTables tab{};
   FieldArgs fld{};
   MeshArgs meshargs{};
@@ -771,9 +771,9 @@ int ensure_device(vfp_ctx* c) {
 
 // Packed per-x-cell and per-p-cell scalar records (see FieldArgs::xrec).
 int build_records(vfp_ctx* c) {
-  // the records hold three Gauss points per axis; the (x, ln p) kernels
-  // that read them exist for k <= 2
-  if (!c->mom || !c->mesh_set || c->k > 2 || c->linp) return VFP_OK;
+  // the records hold three Gauss points per axis; the (x, ln p) and (x, p)
+  // kernels that read them exist for k <= 2
+  if (!c->mom || !c->mesh_set || c->k > 2) return VFP_OK;
   const int K1 = c->K1, nxc = c->ncell[0], pa = c->naxes - 1, npc = c->ncell[pa];
   const double ta = (c->terms & VFP_TERM_ADVECTION) ? 1.0 : 0.0;
   const double tm = (c->terms & VFP_TERM_MOMENTUM) ? 1.0 : 0.0;
@@ -798,25 +798,37 @@ int build_records(vfp_ctx* c) {
   }
   const std::vector<double>& nd = c->nodes[pa];
   std::vector<double> g = gauss_points(c->k);
+  // on a p axis: the m/(gamma p) slot holds -V (-div beta = dU/dt V A^x + ...),
+  // the face slots t_mom gamma m, and the extra record gamma m, p (Gauss
+  // points) and p (faces)
+  std::vector<double> pr2(c->linp ? (size_t)npc * 8 : 0, 0.0);
   for (int j = 0; j < npc; ++j) {
     double* p = &pr[(size_t)j * kRec];
     for (int q = 0; q < K1; ++q) {
-      const double pp = std::exp(nd[j] + (1.0 + g[q]) * 0.5 * (nd[j + 1] - nd[j]));
+      const double xi = nd[j] + (1.0 + g[q]) * 0.5 * (nd[j + 1] - nd[j]);
+      const double pp = c->linp ? xi : std::exp(xi);
       const double gam = std::sqrt(1.0 + (pp / c->mass) * (pp / c->mass));
       p[0 + q] = pp / (gam * c->mass);
       p[3 + q] = gam * c->mass / pp;
-      p[6 + q] = c->mass / (gam * pp);
+      p[6 + q] = c->linp ? -pp / (gam * c->mass) : c->mass / (gam * pp);
       p[9 + q] = tr * c->charge / (gam * c->mass);
+      if (c->linp) {
+        pr2[(size_t)j * 8 + q] = gam * c->mass;
+        pr2[(size_t)j * 8 + 3 + q] = pp;
+      }
     }
     for (int s = 0; s < 2; ++s) {
-      const double pp = std::exp(nd[j + s]);
+      const double pp = c->linp ? nd[j + s] : std::exp(nd[j + s]);
       const double gam = std::sqrt(1.0 + (pp / c->mass) * (pp / c->mass));
-      p[12 + s] = tm * gam * c->mass / pp;
+      p[12 + s] = tm * gam * c->mass / (c->linp ? 1.0 : pp);
+      if (c->linp) pr2[(size_t)j * 8 + 6 + s] = pp;
     }
     p[14] = 2.0 / (nd[j + 1] - nd[j]);
   }
   if (int e = upload_vec(c->d_xrec, xr)) return e;
   if (int e = upload_vec(c->d_prec, pr)) return e;
+  if (c->linp)
+    if (int e = upload_vec(c->d_prec2, pr2)) return e;
   return VFP_OK;
 }
 
@@ -862,6 +874,7 @@ int refresh(vfp_ctx* c, unsigned what) {
   F.pf_coded = c->d_pf_coded.as<double>();
   F.xrec = c->d_xrec.as<double>();
   F.prec = c->d_prec.as<double>();
+  F.prec2 = c->linp ? c->d_prec2.as<double>() : nullptr;
   F.pf_tab = c->d_pf_tab.as<double>();
   F.pf_dtab = c->d_pf_dtab.as<double>();
   for (int i = 0; i < 3; ++i) F.B[i] = c->B[i];
@@ -880,15 +893,14 @@ int refresh(vfp_ctx* c, unsigned what) {
   }
   c->launcher = nullptr;
   c->shock = false;
-  // the (x, ln p) specialisation is built for a ln p axis
-  const bool shock_ok = c->naxes == 2 && c->mom && !c->linp && c->planar && !c->have_Bpts && !c->force_general;
+  const bool shock_ok = c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general;
   if (shock_ok) {
-    c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot);
+    c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot, c->linp);
     c->shock = c->launcher != nullptr;
   }
   if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
   c->adj_launcher = nullptr;
-  if (shock_ok) c->adj_launcher = find_shock_adjoint_launcher(c->k, c->lmax, c->tab.nrot);
+  if (shock_ok) c->adj_launcher = find_shock_adjoint_launcher(c->k, c->lmax, c->tab.nrot, c->linp);
   if (!c->adj_launcher) c->adj_launcher = find_adjoint_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
   c->mass_launcher = find_mass_launcher(c->naxes, c->k);
   return VFP_OK;
@@ -1942,7 +1954,7 @@ int vfp_batch_create(vfp_batch** out, vfp_ctx* const* runs, int nruns, unsigned 
   for (int i = 0; i < nruns; ++i) {
     vfp_ctx* c = runs[i];
     const int nrot = c->tab.nrot;
-    const bool batched = c->shock;
+    const bool batched = c->shock && !c->linp;   // the batched kernel is built for ln p
     vfp_batch::Class* cl = nullptr;
     for (auto& x : b->classes)
       if (x.batched == batched && x.k == c->k && x.lmax == c->lmax && x.nrot == nrot) cl = &x;

@@ -16,7 +16,7 @@ import pytest
 from oracle import dg
 from paper_2501_05110_amd import workloads as W
 
-from gpu_cases import APPLY_TOL, CASES, _say, rel_inf, shock
+from gpu_cases import APPLY_TOL, CASES, P_AXIS_CASES, _say, rel_inf, shock
 
 pytestmark = pytest.mark.gpu
 GRAD_TOL = 1e-10
@@ -225,14 +225,14 @@ def test_full_size_transpose_identity(lib, cuda, name):
     assert abs(lhs - rhs) <= APPLY_TOL * scale
 
 
-@pytest.mark.parametrize("name", ["shock_k2_l3", "shock_k1_l5", "shock_k2_l7"])
+@pytest.mark.parametrize("name", ["shock_k2_l3", "shock_k1_l5", "shock_k2_l7", "shock_p_k2_l3", "shock_p_k1_l5"])
 def test_specialised_matches_general(lib, cuda, name, monkeypatch):
     """The (x, ln p) kernels against the general kernel family on the same
     inputs (forward apply, adjoint apply, one adjoint stage with d/dnu): the
     two differ only in summation order."""
     import torch
     from paper_2501_05110_amd.vfp import Operator
-    wl = CASES[name]()
+    wl = (CASES.get(name) or P_AXIS_CASES[name])()
     g = np.random.default_rng(31)
     z, mu, fwd = (g.standard_normal(wl.ndofs) for _ in range(3))
     outs = {}
