@@ -165,15 +165,15 @@ int vfp_ndofs(const vfp_ctx* ctx, int64_t* n);
 int vfp_cfl_dt(const vfp_ctx* ctx, double courant, double* dt);
 
 /* out = M^{-1}( h [with_source] - D in ).  in, out: device, ndofs doubles,
- * must not alias. */
+ * must not overlap (VFP_EINVAL). */
 int vfp_apply(vfp_ctx* ctx, const double* in, double* out, int with_source,
               void* stream);
 
 /* One fused Runge-Kutta stage: w_out = u + cdt * L(w_in) (with the source).
  * All three are device arrays of ndofs doubles.  w_in may equal u.  w_out may
  * equal u (each lane reads its own u before writing w_out), but w_out must
- * not equal w_in, because neighbouring cells still read w_in: that case is
- * rejected with VFP_EINVAL. */
+ * not overlap w_in, because neighbouring cells still read w_in, and must
+ * otherwise be disjoint from u: those cases are rejected with VFP_EINVAL. */
 int vfp_stage(vfp_ctx* ctx, const double* w_in, const double* u, double* w_out,
               double cdt, void* stream);
 
@@ -204,11 +204,13 @@ int vfp_advance(vfp_ctx* ctx, double* u, double dt, int64_t nsteps,
  */
 
 /* out = M in (inverse = 0) or M^{-1} in (inverse != 0), cell by cell, with M
- * the DG mass matrix of eq. definition-mass-and-dg-matrix.  in may equal out. */
+ * the DG mass matrix of eq. definition-mass-and-dg-matrix.  in may equal out;
+ * a partial overlap is rejected with VFP_EINVAL. */
 int vfp_mass(vfp_ctx* ctx, const double* in, double* out, int inverse, void* stream);
 
 /* out = -D^T M^{-1} in  (the transpose of the linear part of vfp_apply; the
- * source does not enter).  in, out: device, ndofs doubles, must not alias.
+ * source does not enter).  in, out: device, ndofs doubles, must not overlap
+ * (VFP_EINVAL).
  * Uses a library-owned scratch vector of ndofs doubles, allocated on the first
  * call (VFP_ENOMEM if that fails); calls on one context that overlap in time
  * race on it. */

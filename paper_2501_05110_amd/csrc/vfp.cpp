@@ -1247,6 +1247,11 @@ static double stage_cdt(int s, double dt) {
   }
 }
 
+static bool overlaps(const double* a, int64_t na, const double* b, int64_t nb) {
+  if (!a || !b) return false;
+  return a < b + nb && b < a + na;
+}
+
 static int launch(vfp_ctx* c, const double* w_in, const double* u, double* w_out, double alpha, double beta,
                   int with_source, void* stream) {
   KernelArgs a{};
@@ -1268,14 +1273,19 @@ static int launch(vfp_ctx* c, const double* w_in, const double* u, double* w_out
 int vfp_apply(vfp_ctx* c, const double* in, double* out, int with_source, void* stream) {
   if (int e = check_ready(c)) return e;
   if (!in || !out) return fail(VFP_EINVAL, "null state pointer");
-  if (in == out) return fail(VFP_EINVAL, "in and out must not alias");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  if (overlaps(in, N, out, N)) return fail(VFP_EINVAL, "in and out must not overlap");
   return launch(c, in, nullptr, out, 0.0, 1.0, with_source, stream);
 }
 
 int vfp_stage(vfp_ctx* c, const double* w_in, const double* u, double* w_out, double cdt, void* stream) {
   if (int e = check_ready(c)) return e;
   if (!w_in || !u || !w_out) return fail(VFP_EINVAL, "null state pointer");
-  if (w_out == w_in) return fail(VFP_EINVAL, "w_out must differ from w_in");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  if (overlaps(w_out, N, w_in, N)) return fail(VFP_EINVAL, "w_out must not overlap w_in");
+  if (overlaps(w_out, N, u, N) && w_out != u) return fail(VFP_EINVAL, "w_out partially overlaps u");
   if (!std::isfinite(cdt)) return fail(VFP_EINVAL, "cdt not finite");
   return launch(c, w_in, u, w_out, 1.0, cdt, 1, stream);
 }
@@ -1297,11 +1307,6 @@ int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, 
     if (int e = launch(c, wa, u, u, 1.0, stage_cdt(3, dt), 1, stream)) return e;
   }
   return VFP_OK;
-}
-
-static bool overlaps(const double* a, int64_t na, const double* b, int64_t nb) {
-  if (!a || !b) return false;
-  return a < b + nb && b < a + na;
 }
 
 static int launch_adj(vfp_ctx* c, const double* mu_in, const double* acc_in, double* acc_out, double alpha,
@@ -1338,15 +1343,18 @@ static int launch_mass(vfp_ctx* c, const double* in, double* out, bool inv, void
 int vfp_mass(vfp_ctx* c, const double* in, double* out, int inverse, void* stream) {
   if (int e = check_ready(c)) return e;
   if (!in || !out) return fail(VFP_EINVAL, "null state pointer");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  if (overlaps(in, N, out, N) && in != out) return fail(VFP_EINVAL, "out partially overlaps in");
   return launch_mass(c, in, out, inverse != 0, stream);
 }
 
 int vfp_apply_adjoint(vfp_ctx* c, const double* in, double* out, void* stream) {
   if (int e = check_ready(c)) return e;
   if (!in || !out) return fail(VFP_EINVAL, "null state pointer");
-  if (in == out) return fail(VFP_EINVAL, "in and out must not alias");
   int64_t N = 0;
   vfp_ndofs(c, &N);
+  if (overlaps(in, N, out, N)) return fail(VFP_EINVAL, "in and out must not overlap");
   if (c->d_scratch.bytes < (size_t)N * sizeof(double)) {
     c->d_scratch.release();
     if (std::getenv("VFP_FAIL_ALLOC")) return fail(VFP_ENOMEM, "allocation refused (VFP_FAIL_ALLOC)");

@@ -271,3 +271,29 @@ def test_time_order_on_gpu(lib, cuda):
     order = np.polyfit(np.log2(dts), np.log2(errs), 1)[0]
     _say(f"[time order] dt={['%.3f' % d for d in dts]} errors={['%.3e' % e for e in errs]} order={order:.2f}")
     assert order > 3.8, (errs, order)
+
+
+def test_overlapping_buffers_rejected(lib, cuda):
+    """Output buffers that partly overlap an input that neighbouring cells
+    still read are rejected before any launch; the allowed in-place forms
+    (stage with w_out == u, mass with out == in) still run."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator, VFPError
+    op = Operator(shock(6, 4, 2, 3))
+    n = op.ndofs
+    buf = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    a, b = buf[:n], buf[16:16 + n]          # b starts inside a
+    other = torch.zeros(n, dtype=torch.float64, device="cuda")
+    with pytest.raises(VFPError):
+        op.apply(a, b)
+    with pytest.raises(VFPError):
+        op.apply_adjoint(a, b)
+    with pytest.raises(VFPError):
+        op.stage(a, other, b, 0.1)           # w_out overlaps w_in
+    with pytest.raises(VFPError):
+        op.stage(other, a, b, 0.1)           # w_out partly overlaps u
+    with pytest.raises(VFPError):
+        op.mass(a, b)
+    op.stage(other, a, a, 0.1)
+    op.mass(a, a, inverse=True)
+    torch.cuda.synchronize()
