@@ -529,7 +529,7 @@ def main():
                    "stage_launches": launches, "wall_s": wall},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "shock_kernel<2,3,1>",
+                     "kernel": "shock_kernel<2,3,1,false,false>",
                      "bytes_per_launch": bytes_per_launch, "us_per_launch": per_launch_s * 1e6},
     }
     if not args.no_adjoint:
