@@ -98,6 +98,7 @@ P_AXIS_CASES = {
     "shock_p_k2_l3": lambda: shock(13, 7, 2, 3, paxis="p", lnp=(-1.0, 2.5)),
     "shock_p_k1_l5": lambda: shock(10, 6, 1, 5, paxis="p", lnp=(-1.0, 2.5)),
     "shock_p_k3_l1": lambda: shock(9, 5, 3, 1, paxis="p", lnp=(-1.0, 2.5)),
+    "shock_p_k2_l3_tiles": lambda: shock(16, 7, 2, 3, paxis="p", lnp=(-1.0, 2.5)),
 }
 
 CASES = {
@@ -107,6 +108,11 @@ CASES = {
     "shock_k2_l1": lambda: shock(13, 9, 2, 1),
     "shock_k1_l5": lambda: shock(11, 6, 1, 5),
     "shock_k2_l7": lambda: shock(9, 5, 2, 7),
+    # x rows of whole workgroup tiles (4 cells at l_max = 3, 16 at l_max = 1),
+    # and one tile per row
+    "shock_k2_l3_tiles": lambda: shock(32, 6, 2, 3),
+    "shock_k1_l1_tiles": lambda: shock(32, 5, 1, 1),
+    "shock_k2_l3_row": lambda: shock(4, 3, 2, 3),
     "uniform2d": lambda: uniform2d(),
     "uniform2d_k2_l2": lambda: uniform2d(2, 2),
     "planar1d": lambda: planar1d(),

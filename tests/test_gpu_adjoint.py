@@ -225,7 +225,8 @@ def test_full_size_transpose_identity(lib, cuda, name):
     assert abs(lhs - rhs) <= APPLY_TOL * scale
 
 
-@pytest.mark.parametrize("name", ["shock_k2_l3", "shock_k1_l5", "shock_k2_l7", "shock_p_k2_l3", "shock_p_k1_l5"])
+@pytest.mark.parametrize("name", ["shock_k2_l3", "shock_k1_l5", "shock_k2_l7", "shock_p_k2_l3", "shock_p_k1_l5",
+                                  "shock_k2_l3_tiles", "shock_p_k2_l3_tiles"])
 def test_specialised_matches_general(lib, cuda, name, monkeypatch):
     """The (x, ln p) kernels against the general kernel family on the same
     inputs (forward apply, adjoint apply, one adjoint stage with d/dnu): the

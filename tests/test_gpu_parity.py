@@ -297,3 +297,39 @@ def test_overlapping_buffers_rejected(lib, cuda):
     op.stage(other, a, a, 0.1)
     op.mass(a, a, inverse=True)
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("paxis", ["lnp", "p"])
+def test_shock_kernel_matches_general_at_scale(lib, cuda, paxis, monkeypatch):
+    """The (x, ln p) / (x, p) shock kernel at 512 x 64 cells (8192
+    workgroups, several per compute unit): apply, one stage with w_out = u
+    (in place) and 20 steps against the general kernel family on the same
+    inputs (they differ only in summation order)."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = shock(512, 64, 2, 3, paxis=paxis, **({"lnp": (-1.0, 2.5)} if paxis == "p" else {}))
+    g = np.random.default_rng(47)
+    z, w = g.standard_normal(wl.ndofs), g.standard_normal(wl.ndofs)
+    _say(f"[shock-vs-general] {paxis}: ndofs={wl.ndofs}")
+    outs = {}
+    for kind in ("shock", "general"):
+        if kind == "general":
+            monkeypatch.setenv("VFP_KERNEL", "general")
+        else:
+            monkeypatch.delenv("VFP_KERNEL", raising=False)
+        op = Operator(wl)
+        dev = lambda x: torch.from_numpy(np.ascontiguousarray(x)).cuda()
+        a = torch.empty(wl.ndofs, dtype=torch.float64, device="cuda")
+        op.apply(dev(z), a)
+        u = dev(z)
+        op.stage(dev(w), u, u, 0.37 * op.cfl_dt(0.2))
+        s = dev(z)
+        work = torch.empty(2 * wl.ndofs, dtype=torch.float64, device="cuda")
+        op.advance(s, op.cfl_dt(0.2), 20, work)
+        torch.cuda.synchronize()
+        outs[kind] = [x.cpu().numpy() for x in (a, u, s)]
+        op.close()
+    for i, label in enumerate(("apply", "stage in place", "20 steps")):
+        err = rel_inf(outs["shock"][i], outs["general"][i])
+        _say(f"   {label}: {err:.3e}")
+        assert err <= 1e-13, (paxis, label, err)
