@@ -21,13 +21,30 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// sum of v over the workgroup (every thread gets it)
+__device__ __forceinline__ double block_sum(double v) {
+  __shared__ double red[kKryThreads / 64];
+  __syncthreads();   // red is free again
+  v = wave_sum(v);
+  if (threadIdx.x % 64 == 0) red[threadIdx.x / 64] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < kKryThreads / 64; ++q) s += red[q];
+  return s;
+}
+
 // partial[j][blockIdx.x] = sum over this block's elements of V_j . w, for the
-// kDotChunk vectors j = blockIdx.y kDotChunk + c < k
+// kDotChunk vectors j = blockIdx.y kDotChunk + c < k; with self != 0 the
+// first block row also writes w . w as row k (the norm that the Gram-Schmidt
+// step needs, from the same pass over w)
 __global__ __launch_bounds__(kKryThreads) void mdot_partial_kernel(const double* __restrict__ V, int64_t ldv,
                                                                     int k, const double* __restrict__ w,
-                                                                    int64_t n, double* __restrict__ partial) {
+                                                                    int64_t n, double* __restrict__ partial,
+                                                                    int self) {
   const int j0 = blockIdx.y * kDotChunk;
-  double acc[kDotChunk];
+  const bool do_self = self && blockIdx.y == 0;
+  double acc[kDotChunk], ws = 0.0;
 #pragma unroll
   for (int c = 0; c < kDotChunk; ++c) acc[c] = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kKryThreads;
@@ -36,13 +53,18 @@ __global__ __launch_bounds__(kKryThreads) void mdot_partial_kernel(const double*
 #pragma unroll
     for (int c = 0; c < kDotChunk; ++c)
       if (j0 + c < k) acc[c] = fma(V[(int64_t)(j0 + c) * ldv + i], wi, acc[c]);
+    if (do_self) ws = fma(wi, wi, ws);
   }
-  __shared__ double red[kDotChunk][kKryThreads / 64];
+  __shared__ double red[kDotChunk + 1][kKryThreads / 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
 #pragma unroll
   for (int c = 0; c < kDotChunk; ++c) {
     const double s = wave_sum(acc[c]);
     if (lane == 0) red[c][wave] = s;
+  }
+  if (do_self) {
+    const double s = wave_sum(ws);
+    if (lane == 0) red[kDotChunk][wave] = s;
   }
   __syncthreads();
   if (threadIdx.x < kDotChunk && j0 + (int)threadIdx.x < k) {
@@ -50,6 +72,12 @@ __global__ __launch_bounds__(kKryThreads) void mdot_partial_kernel(const double*
 #pragma unroll
     for (int q = 0; q < kKryThreads / 64; ++q) s += red[threadIdx.x][q];
     partial[(int64_t)(j0 + threadIdx.x) * gridDim.x + blockIdx.x] = s;
+  }
+  if (do_self && threadIdx.x == kDotChunk) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < kKryThreads / 64; ++q) s += red[kDotChunk][q];
+    partial[(int64_t)k * gridDim.x + blockIdx.x] = s;
   }
 }
 
@@ -71,18 +99,25 @@ __global__ __launch_bounds__(kKryThreads) void mdot_final_kernel(const double* _
   }
 }
 
-// w += sign * sum_{j<k} coef[j] V_j
+// w += sign * sum_{j<k} coef[j] V_j; with partial != null also
+// partial[blockIdx.x] = sum over this block's elements of the new w . w
 __global__ __launch_bounds__(kKryThreads) void maxpy_kernel(double* __restrict__ w, const double* __restrict__ V,
                                                              int64_t ldv, int k, const double* __restrict__ coef,
-                                                             double sign, int64_t n) {
+                                                             double sign, int64_t n, double* __restrict__ partial) {
   __shared__ double cs[kKryMaxVectors];
   for (int j = threadIdx.x; j < k; j += kKryThreads) cs[j] = sign * coef[j];
   __syncthreads();
+  double ws = 0.0;
   const int64_t stride = (int64_t)gridDim.x * kKryThreads;
   for (int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; i < n; i += stride) {
     double acc = w[i];
     for (int j = 0; j < k; ++j) acc = fma(cs[j], V[(int64_t)j * ldv + i], acc);
     w[i] = acc;
+    ws = fma(acc, acc, ws);
+  }
+  if (partial) {
+    const double s = block_sum(ws);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
   }
 }
 
@@ -118,17 +153,21 @@ int grid_for(int64_t n) {
 }  // namespace
 
 void kry_mdot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial, double* out,
-              hipStream_t s) {
+              hipStream_t s, bool self) {
   if (k <= 0) return;
   const dim3 grid(kKryBlocks, (k + kDotChunk - 1) / kDotChunk);
-  hipLaunchKernelGGL(mdot_partial_kernel, grid, dim3(kKryThreads), 0, s, V, ldv, k, w, n, partial);
-  hipLaunchKernelGGL(mdot_final_kernel, dim3(k), dim3(kKryThreads), 0, s, partial, kKryBlocks, out);
+  hipLaunchKernelGGL(mdot_partial_kernel, grid, dim3(kKryThreads), 0, s, V, ldv, k, w, n, partial, self ? 1 : 0);
+  hipLaunchKernelGGL(mdot_final_kernel, dim3(k + (self ? 1 : 0)), dim3(kKryThreads), 0, s, partial, kKryBlocks,
+                     out);
 }
 
 void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coef, double sign, int64_t n,
-               hipStream_t s) {
+               hipStream_t s, double* partial, double* norm2) {
   if (k <= 0) return;
-  hipLaunchKernelGGL(maxpy_kernel, dim3(grid_for(n)), dim3(kKryThreads), 0, s, w, V, ldv, k, coef, sign, n);
+  const int g = grid_for(n);
+  hipLaunchKernelGGL(maxpy_kernel, dim3(g), dim3(kKryThreads), 0, s, w, V, ldv, k, coef, sign, n,
+                     norm2 ? partial : nullptr);
+  if (norm2) hipLaunchKernelGGL(mdot_final_kernel, dim3(1), dim3(kKryThreads), 0, s, partial, g, norm2);
 }
 
 void kry_coll_precond(double* out, const double* in, const double* nu, double nu0, const double* cval, double s,

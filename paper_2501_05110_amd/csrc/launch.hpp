@@ -47,15 +47,18 @@ FieldGradReduce find_field_grad_reduce(int k);
 int field_grad_slots_per_cell(int k);
 
 // Krylov-basis vector arithmetic (restarted GMRES of the Theta-method).
-// Vectors j of a basis are V + j ldv.  kry_mdot: out[j] = V_j . w for j < k
-// (partial: kKryMaxVectors * kKryBlocks doubles of scratch); kry_maxpy:
-// w += sign sum_j coef[j] V_j (coef on the device); kry_lincomb: out = a x + b y.
+// Vectors j of a basis are V + j ldv.  kry_mdot: out[j] = V_j . w for j < k,
+// and with self also out[k] = w . w from the same pass (partial:
+// kKryMaxVectors * kKryBlocks doubles of scratch, k + self <= kKryMaxVectors);
+// kry_maxpy: w += sign sum_j coef[j] V_j (coef on the device), and with norm2
+// also *norm2 = |w|^2 of the result (partial: kKryBlocks doubles);
+// kry_lincomb: out = a x + b y.
 constexpr int kKryMaxVectors = 72;
 constexpr int kKryBlocks = 1024;
 void kry_mdot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial, double* out,
-              hipStream_t s);
+              hipStream_t s, bool self = false);
 void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coef, double sign, int64_t n,
-               hipStream_t s);
+               hipStream_t s, double* partial = nullptr, double* norm2 = nullptr);
 void kry_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t s);
 // out = in / (1 + s nu_c c_lms) on a [cell][nb][n] vector (nu per cell, or nu0 if null)
 void kry_coll_precond(double* out, const double* in, const double* nu, double nu0, const double* cval, double s,

@@ -1662,17 +1662,16 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
         vin = t.z;
       }
       if (int e = theta_op(c, vin, t.w, dt, th, stream)) return e;
-      kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d1, st);
-      kry_mdot(t.w, N, 1, t.w, N, t.partial, t.d3, st);
-      kry_maxpy(t.w, t.V, N, j + 1, t.d1, -1.0, N, st);
-      kry_mdot(t.w, N, 1, t.w, N, t.partial, t.d3 + 1, st);
+      // d1[0..j] = V^T w and d1[j+1] = |w|^2 in one pass over w; the update
+      // leaves |w_new|^2 in d3[1]
+      kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d1, st, true);
+      kry_maxpy(t.w, t.V, N, j + 1, t.d1, -1.0, N, st, t.partial, t.d3 + 1);
       if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st)) return e;
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i];
       double hn2 = hb[2 * kKryMaxVectors + 1];
-      if (hn2 < 0.5 * hb[2 * kKryMaxVectors]) {
+      if (hn2 < 0.5 * hb[j + 1]) {
         kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d2, st);
-        kry_maxpy(t.w, t.V, N, j + 1, t.d2, -1.0, N, st);
-        kry_mdot(t.w, N, 1, t.w, N, t.partial, t.d3 + 2, st);
+        kry_maxpy(t.w, t.V, N, j + 1, t.d2, -1.0, N, st, t.partial, t.d3 + 2);
         if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st)) return e;
         for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hb[kKryMaxVectors + i];
         hn2 = hb[2 * kKryMaxVectors + 2];
