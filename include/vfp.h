@@ -345,9 +345,12 @@ int vfp_theta_work_size(const vfp_ctx* ctx, int restart, int64_t* n);
  * work: device, at least vfp_theta_work_size doubles (work_len), disjoint
  * from u.  Unlike the other compute calls this one synchronises `stream`
  * once per Krylov iteration (the Hessenberg least-squares problem is solved
- * on the host).  stats (host, may be NULL) reports the iterations and
- * residuals; a step that does not reach tol within max_iters keeps its last
- * iterate, the run continues, and stats->converged is 0. */
+ * on the host; the first call on a context also allocates a 1.7 KB pinned
+ * host buffer for those read-backs, kept until vfp_destroy).  stats (host,
+ * may be NULL) reports the iterations and residuals; a step that does not
+ * reach tol within max_iters keeps its last iterate, the run continues, and
+ * stats->converged is 0.  Calls on one context that overlap in time race on
+ * that buffer. */
 int vfp_theta_advance(vfp_ctx* ctx, double* u, double dt, int64_t nsteps, const vfp_theta_opts* opts,
                       double* work, int64_t work_len, vfp_theta_stats* stats, void* stream);
 

@@ -56,6 +56,15 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
+// Pinned host memory (page-locked, so device-to-host copies into it go
+// straight over the bus instead of through a staging buffer)
+struct HostPin {
+  double* p = nullptr;
+  ~HostPin() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 int upload(DevBuf& b, const void* host, size_t bytes) {
   b.release();
   if (bytes == 0) return VFP_OK;
@@ -256,6 +265,7 @@ struct vfp_ctx {
   StageLauncher adj_launcher = nullptr;
   MassLauncher mass_launcher = nullptr;
   DevBuf d_scratch;         // ndofs doubles, used by vfp_apply_adjoint
+  HostPin h_kry;            // 3 kKryMaxVectors doubles: the Theta-method's per-iteration read-backs
   double beta_pmax = 0.0;   // spectral-radius bound of beta^{ln p} over p faces
   double vmax = 0.0;
   double lam_max = 0.0;     // largest eigenvalue of A^x
@@ -1578,10 +1588,13 @@ ThetaWork theta_split(double* work, int64_t N, int m) {
   return t;
 }
 
-// device -> host copy of n doubles, then wait for the stream
-int fetch(double* host, const double* dev, int n, hipStream_t st) {
-  HIP_TRY(hipMemcpyAsync(host, dev, n * sizeof(double), hipMemcpyDeviceToHost, st));
+// device -> host copy of n doubles (through the pinned buffer pin when
+// there is one), then wait for the stream
+int fetch(double* host, const double* dev, int n, hipStream_t st, double* pin = nullptr) {
+  double* dst = pin ? pin : host;
+  HIP_TRY(hipMemcpyAsync(dst, dev, n * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
+  if (pin) std::memcpy(host, pin, n * sizeof(double));
   return VFP_OK;
 }
 
@@ -1621,7 +1634,7 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
   }
   double bn2 = 0.0;
   kry_mdot(t.b, N, 1, t.b, N, t.partial, t.d3, st);
-  if (int e = fetch(&bn2, t.d3, 1, st)) return e;
+  if (int e = fetch(&bn2, t.d3, 1, st, c->h_kry.p)) return e;
   const double bn = std::sqrt(bn2);
   if (bn == 0.0) {
     kry_lincomb(u, 0.0, u, 0.0, nullptr, N, st);
@@ -1638,7 +1651,7 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
     kry_lincomb(t.V, 1.0, t.b, -1.0, t.w, N, st);
     kry_mdot(t.V, N, 1, t.V, N, t.partial, t.d3, st);
     double rn2 = 0.0;
-    if (int e = fetch(&rn2, t.d3, 1, st)) return e;
+    if (int e = fetch(&rn2, t.d3, 1, st, c->h_kry.p)) return e;
     const double beta = std::sqrt(rn2);
     res = beta / bn;
     if (!std::isfinite(res)) return fail(VFP_EDEVICE, "non-finite residual in the Theta step");
@@ -1666,13 +1679,13 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
       // leaves |w_new|^2 in d3[1]
       kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d1, st, true);
       kry_maxpy(t.w, t.V, N, j + 1, t.d1, -1.0, N, st, t.partial, t.d3 + 1);
-      if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st)) return e;
+      if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st, c->h_kry.p)) return e;
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i];
       double hn2 = hb[2 * kKryMaxVectors + 1];
       if (hn2 < 0.5 * hb[j + 1]) {
         kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d2, st);
         kry_maxpy(t.w, t.V, N, j + 1, t.d2, -1.0, N, st, t.partial, t.d3 + 2);
-        if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st)) return e;
+        if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st, c->h_kry.p)) return e;
         for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hb[kKryMaxVectors + i];
         hn2 = hb[2 * kKryMaxVectors + 2];
       }
@@ -1778,6 +1791,11 @@ int vfp_theta_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, const vf
   if (overlaps(u, N, work, need)) return fail(VFP_EINVAL, "work overlaps u");
   const ThetaWork t = theta_split(work, N, o->restart);
   hipStream_t st = (hipStream_t)stream;
+  if (!c->h_kry.p && hipHostMalloc((void**)&c->h_kry.p, 3 * kKryMaxVectors * sizeof(double), hipHostMallocDefault) !=
+                         hipSuccess) {
+    c->h_kry.p = nullptr;      // read-backs go to pageable memory instead
+    (void)hipGetLastError();
+  }
   const bool have_s = (c->terms & VFP_TERM_SOURCE) && c->have_src && o->theta > 0.0;
   if (have_s) {
     // s = M^{-1} h = L(0)
