@@ -5,8 +5,11 @@
 // A (rows x n) by (n x ndir) product with n <= 64: each workgroup keeps 64
 // directions of the Y table in LDS, stages tiles of 32 node rows and writes
 // 32 x 64 outputs per tile, direction index fastest (row-major
-// [row][direction], so a wavefront stores a whole 64-direction row); it walks
-// a strided set of row tiles.
+// [row][direction]); it walks a strided set of row tiles.  A lane computes
+// two neighbouring directions of four rows and writes each pair with one
+// 16-byte streaming store, so a wavefront stores two whole 64-direction rows
+// per instruction (an odd ndir, or an output not 16-byte aligned, falls back
+// to 8-byte stores).
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -17,7 +20,8 @@ namespace {
 constexpr int kRecTile = 32;        // node rows per tile
 constexpr int kRecDirs = 64;        // directions per workgroup
 constexpr int kRecThreads = 256;
-constexpr int kRecRowStep = kRecThreads / kRecDirs;
+constexpr int kRecPairs = kRecDirs / 2;                 // direction pairs per workgroup
+constexpr int kRecRowStep = kRecThreads / kRecPairs;    // rows between a lane's rows
 constexpr int kRecMaxN = 64;
 
 __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(const double* __restrict__ zeta, int64_t rows,
@@ -31,8 +35,9 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(const double* 
     const int i = e / n, j = e - (e / n) * n;
     ys[i][j] = (d0 + i < ndir) ? Y[(d0 + i) * n + j] : 0.0;
   }
-  // thread -> (direction column dc, rows rr + kRecRowStep q)
-  const int dc = threadIdx.x % kRecDirs, rr = threadIdx.x / kRecDirs;
+  // thread -> (directions 2 dp and 2 dp + 1, rows rr + kRecRowStep q)
+  const int dp = threadIdx.x % kRecPairs, rr = threadIdx.x / kRecPairs;
+  const bool pairs = (ndir % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 16) == 0;   // 16-byte aligned pairs
   for (int64_t r0 = (int64_t)blockIdx.x * kRecTile; r0 < rows; r0 += (int64_t)gridDim.x * kRecTile) {
     __syncthreads();   // the previous tile's reads of zs are done
     for (int e = threadIdx.x; e < kRecTile * n; e += kRecThreads) {
@@ -41,20 +46,38 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(const double* 
     }
     __syncthreads();
     constexpr int NQ = kRecTile / kRecRowStep;
-    double acc[NQ];
+    double a0[NQ], a1[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+    for (int q = 0; q < NQ; ++q) a0[q] = a1[q] = 0.0;
     for (int j = 0; j < n; ++j) {
-      const double y = ys[dc][j];
+      const double y0 = ys[2 * dp][j], y1 = ys[2 * dp + 1][j];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) acc[q] = fma(zs[rr + kRecRowStep * q][j], y, acc[q]);
+      for (int q = 0; q < NQ; ++q) {
+        const double zv = zs[rr + kRecRowStep * q][j];
+        a0[q] = fma(zv, y0, a0[q]);
+        a1[q] = fma(zv, y1, a1[q]);
+      }
     }
-    if (d0 + dc < ndir) {
+    // written once and not read again here: streaming stores
+    const int64_t d = d0 + 2 * dp;
+    if (pairs && d + 1 < ndir) {
+      typedef double d2v __attribute__((ext_vector_type(2)));
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int64_t r = r0 + rr + kRecRowStep * q;
-        // written once and not read again here: streaming stores
-        if (r < rows) __builtin_nontemporal_store(acc[q], &out[r * ndir + d0 + dc]);
+        if (r < rows) {
+          d2v v;
+          v.x = a0[q];
+          v.y = a1[q];
+          __builtin_nontemporal_store(v, reinterpret_cast<d2v*>(&out[r * ndir + d]));
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int64_t r = r0 + rr + kRecRowStep * q;
+        if (r < rows && d < ndir) __builtin_nontemporal_store(a0[q], &out[r * ndir + d]);
+        if (r < rows && d + 1 < ndir) __builtin_nontemporal_store(a1[q], &out[r * ndir + d + 1]);
       }
     }
   }

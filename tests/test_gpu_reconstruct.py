@@ -14,8 +14,13 @@ from gpu_cases import _say, rel_inf, shock
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("wl_args,ndir", [((13, 9, 2, 1), 50), ((9, 5, 2, 7), 33), ((11, 6, 1, 5), 1)])
-def test_reconstruct_parity(lib, cuda, wl_args, ndir):
+@pytest.mark.parametrize("wl_args,ndir,offset", [((13, 9, 2, 1), 50, 0), ((9, 5, 2, 7), 33, 0),
+                                                 ((11, 6, 1, 5), 1, 0), ((14, 7, 2, 3), 64, 0),
+                                                 ((14, 7, 2, 3), 64, 1), ((10, 3, 1, 3), 130, 0)])
+def test_reconstruct_parity(lib, cuda, wl_args, ndir, offset):
+    """Even ndir writes direction pairs with 16-byte stores; odd ndir, or an
+    output that starts 8 bytes past a 16-byte boundary (offset 1), takes the
+    8-byte stores; 130 directions span three direction tiles."""
     import torch
     from paper_2501_05110_amd import vfp
     wl = shock(*wl_args)
@@ -25,11 +30,14 @@ def test_reconstruct_parity(lib, cuda, wl_args, ndir):
     z = W.random_state(wl, 3)
     Y = torch.from_numpy(vfp.sh_eval(wl.lmax, th, ph)).cuda()
     rows = wl.ndofs // wl.n_lms
-    out = torch.empty(rows * ndir, dtype=torch.float64, device="cuda")
+    buf = torch.full((rows * ndir + 2,), 7.0, dtype=torch.float64, device="cuda")
+    out = buf[offset:offset + rows * ndir]
     op.reconstruct(torch.from_numpy(z.ravel()).cuda(), Y, out)
     torch.cuda.synchronize()
     got = out.cpu().numpy().reshape(rows, ndir)
+    rest = np.delete(buf.cpu().numpy(), np.arange(offset, offset + rows * ndir))
+    assert np.all(rest == 7.0)          # nothing written outside out
     want = sh.reconstruct(z, wl.lmax, th, ph)
     err = rel_inf(got, want)
-    _say(f"[reconstruct] {wl.name} rows={rows} ndir={ndir} rel_inf={err:.2e}")
+    _say(f"[reconstruct] {wl.name} rows={rows} ndir={ndir} offset={offset} rel_inf={err:.2e}")
     assert err <= 1e-13
