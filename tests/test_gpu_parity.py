@@ -333,3 +333,39 @@ def test_shock_kernel_matches_general_at_scale(lib, cuda, paxis, monkeypatch):
         err = rel_inf(outs["shock"][i], outs["general"][i])
         _say(f"   {label}: {err:.3e}")
         assert err <= 1e-13, (paxis, label, err)
+
+
+def test_advance_under_caller_graph_capture(lib, cuda):
+    """vfp_advance only enqueues kernel launches on the caller's stream, so a
+    caller can capture it into a graph (here a torch CUDA graph of 6 steps,
+    24 stage launches): each of several replays (with eager work and
+    synchronisations between them) matches the eager run from the same
+    start bit for bit."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = CASES["shock_k2_l3"]()
+    op = Operator(wl)
+    z = torch.from_numpy(np.ascontiguousarray(W.random_state(wl, 23)).ravel()).cuda()
+    dt = op.cfl_dt(0.2)
+    u = z.clone()
+    work = torch.empty(2 * wl.ndofs, dtype=torch.float64, device="cuda")
+    eager = z.clone()
+    op.advance(eager, dt, 6, torch.empty_like(work))
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        op.advance(u, dt, 6, work)          # warm-up on the side stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        op.advance(u, dt, 6, work)
+    for rep in range(3):
+        u.copy_(z)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(u, eager), (rep, float((u - eager).abs().max()))
+        _ = (u * 2.0).sum().item()          # eager work between replays
+    op.close()
