@@ -16,11 +16,15 @@ pytestmark = pytest.mark.gpu
 
 @pytest.mark.parametrize("wl_args,ndir,offset", [((13, 9, 2, 1), 50, 0), ((9, 5, 2, 7), 33, 0),
                                                  ((11, 6, 1, 5), 1, 0), ((14, 7, 2, 3), 64, 0),
-                                                 ((14, 7, 2, 3), 64, 1), ((10, 3, 1, 3), 130, 0)])
+                                                 ((14, 7, 2, 3), 64, 1), ((10, 3, 1, 3), 130, 0),
+                                                 ((14, 7, 2, 3), 16, 0), ((13, 9, 2, 1), 7, 1),
+                                                 ((11, 6, 1, 5), 16, 1), ((9, 5, 2, 7), 12, 0)])
 def test_reconstruct_parity(lib, cuda, wl_args, ndir, offset):
     """Even ndir writes direction pairs with 16-byte stores; odd ndir, or an
     output that starts 8 bytes past a 16-byte boundary (offset 1), takes the
-    8-byte stores; 130 directions span three direction tiles."""
+    8-byte stores; 130 directions span three direction tiles; up to 16
+    directions (n <= 49) take the 16-direction workgroups with 128-row
+    tiles, and l_max = 7 with 12 directions the 64-direction ones."""
     import torch
     from paper_2501_05110_amd import vfp
     wl = shock(*wl_args)
