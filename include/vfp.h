@@ -209,12 +209,11 @@ int vfp_advance(vfp_ctx* ctx, double* u, double dt, int64_t nsteps,
 int vfp_mass(vfp_ctx* ctx, const double* in, double* out, int inverse, void* stream);
 
 /* out = -D^T M^{-1} in  (the transpose of the linear part of vfp_apply; the
- * source does not enter).  in, out: device, ndofs doubles, must not overlap
- * (VFP_EINVAL).
- * Uses a library-owned scratch vector of ndofs doubles, allocated on the first
- * call (VFP_ENOMEM if that fails); calls on one context that overlap in time
- * race on it. */
-int vfp_apply_adjoint(vfp_ctx* ctx, const double* in, double* out, void* stream);
+ * source does not enter).  in, out: device, ndofs doubles, must not overlap.
+ * work: caller-owned device scratch of ndofs doubles, disjoint from both; it
+ * receives M^{-1} in.  VFP_EINVAL for a NULL pointer or an overlap.  Nothing
+ * is allocated. */
+int vfp_apply_adjoint(vfp_ctx* ctx, const double* in, double* out, double* work, void* stream);
 
 /* One adjoint Runge-Kutta stage in mu variables:
  *     t = cdt K(mu_in);   t_out = t (if t_out != NULL);   acc_out = acc_in + t.

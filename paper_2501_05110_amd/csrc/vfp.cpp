@@ -16,6 +16,7 @@
 #include <thread>
 #include <vector>
 
+#include "internal.hpp"
 #include "kargs.hpp"
 #include "launch.hpp"
 #include "shtab.hpp"
@@ -264,7 +265,6 @@ struct vfp_ctx {
   StageLauncher launcher = nullptr;
   StageLauncher adj_launcher = nullptr;
   MassLauncher mass_launcher = nullptr;
-  DevBuf d_scratch;         // ndofs doubles, used by vfp_apply_adjoint
   HostPin h_kry;            // 3 kKryMaxVectors doubles: the Theta-method's per-iteration read-backs
   double beta_pmax = 0.0;   // spectral-radius bound of beta^{ln p} over p faces
   double vmax = 0.0;
@@ -1359,25 +1359,18 @@ int vfp_mass(vfp_ctx* c, const double* in, double* out, int inverse, void* strea
   return launch_mass(c, in, out, inverse != 0, stream);
 }
 
-int vfp_apply_adjoint(vfp_ctx* c, const double* in, double* out, void* stream) {
+int vfp_apply_adjoint(vfp_ctx* c, const double* in, double* out, double* work, void* stream) {
   if (int e = check_ready(c)) return e;
-  if (!in || !out) return fail(VFP_EINVAL, "null state pointer");
+  if (!in || !out || !work) return fail(VFP_EINVAL, "null pointer (in, out and work are required)");
   int64_t N = 0;
   vfp_ndofs(c, &N);
   if (overlaps(in, N, out, N)) return fail(VFP_EINVAL, "in and out must not overlap");
-  if (c->d_scratch.bytes < (size_t)N * sizeof(double)) {
-    c->d_scratch.release();
-    if (std::getenv("VFP_FAIL_ALLOC")) return fail(VFP_ENOMEM, "allocation refused (VFP_FAIL_ALLOC)");
-    hipError_t e = hipMalloc(&c->d_scratch.p, (size_t)N * sizeof(double));
-    if (e != hipSuccess) {
-      c->d_scratch.p = nullptr;
-      return fail(VFP_ENOMEM, "hipMalloc(%lld doubles): %s", (long long)N, hipGetErrorString(e));
-    }
-    c->d_scratch.bytes = (size_t)N * sizeof(double);
-  }
-  double* mu = c->d_scratch.as<double>();
-  if (int e = launch_mass(c, in, mu, true, stream)) return e;
-  return launch_adj(c, mu, nullptr, out, 0.0, 1.0, nullptr, nullptr, nullptr, 1, stream);
+  if (overlaps(work, N, in, N) || overlaps(work, N, out, N))
+    return fail(VFP_EINVAL, "work must be disjoint from in and out");
+  // work receives mu = M^{-1} in; the adjoint kernel then forms -D^T mu with
+  // the mass multiply fused (M K M^{-1} = -D^T M^{-1})
+  if (int e = launch_mass(c, in, work, true, stream)) return e;
+  return launch_adj(c, work, nullptr, out, 0.0, 1.0, nullptr, nullptr, nullptr, 1, stream);
 }
 
 int vfp_adjoint_stage(vfp_ctx* c, const double* mu_in, const double* acc_in, const double* fwd, double cdt,
@@ -2177,3 +2170,18 @@ int vfp_batch_class_info(const vfp_batch* b, int i, int* info) {
 }
 
 }  // extern "C"
+
+namespace vfp {
+int api_fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ctx_device(const vfp_ctx* c) { return c ? c->device : -1; }
+}  // namespace vfp
+

@@ -72,7 +72,7 @@ def load(path: str = None):
         "vfp_stage": (I, [P, P, P, P, D, P]),
         "vfp_advance": (I, [P, P, D, L, P, P]),
         "vfp_mass": (I, [P, P, P, I, P]),
-        "vfp_apply_adjoint": (I, [P, P, P, P]),
+        "vfp_apply_adjoint": (I, [P, P, P, P, P]),
         "vfp_adjoint_stage": (I, [P, P, P, P, D, P, P, P, P]),
         "vfp_advance_tape": (I, [P, P, D, L, P, P]),
         "vfp_adjoint_steps": (I, [P, P, P, D, L, P, P, P, P, P]),
@@ -271,9 +271,14 @@ class Operator:
         _check(_lib.vfp_mass(self._ctx, self._t(zin, "in"), self._t(zout, "out"), int(bool(inverse)),
                              _stream_handle(stream)))
 
-    def apply_adjoint(self, zin, zout, stream=None):
+    def apply_adjoint(self, zin, zout, work=None, stream=None):
+        """zout = -D^T M^{-1} zin; work (ndofs doubles) is the call's scratch,
+        taken from torch's allocator when not given."""
+        import torch
+        if work is None:
+            work = torch.empty(self.ndofs, dtype=torch.float64, device=zin.device)
         _check(_lib.vfp_apply_adjoint(self._ctx, self._t(zin, "in"), self._t(zout, "out"),
-                                      _stream_handle(stream)))
+                                      self._t(work, "work"), _stream_handle(stream)))
 
     def adjoint_stage(self, mu_in, acc_in, fwd, cdt, t_out, acc_out, grad_nu=None, stream=None):
         _check(_lib.vfp_adjoint_stage(

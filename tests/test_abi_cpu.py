@@ -72,7 +72,7 @@ def test_calls_out_of_order(lib):
     assert lib.vfp_ndofs(ctx, C.byref(n)) == -4
     assert lib.vfp_apply(ctx, None, None, 1, None) == -4
     # every compute call checks the state first
-    assert lib.vfp_apply_adjoint(ctx, None, None, None) == -4
+    assert lib.vfp_apply_adjoint(ctx, None, None, None, None) == -4
     assert lib.vfp_mass(ctx, None, None, 1, None) == -4
     assert lib.vfp_adjoint_stage(ctx, None, None, None, 0.1, None, None, None, None) == -4
     assert lib.vfp_advance_tape(ctx, None, 0.1, 1, None, None) == -4

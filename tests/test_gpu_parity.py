@@ -288,6 +288,11 @@ def test_overlapping_buffers_rejected(lib, cuda):
         op.apply(a, b)
     with pytest.raises(VFPError):
         op.apply_adjoint(a, b)
+    buf2 = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    with pytest.raises(VFPError):
+        op.apply_adjoint(other, buf2[:n], work=buf2[8:8 + n])   # work overlaps out
+    with pytest.raises(VFPError):
+        op.apply_adjoint(a, other, work=b)                      # work overlaps in
     with pytest.raises(VFPError):
         op.stage(a, other, b, 0.1)           # w_out overlaps w_in
     with pytest.raises(VFPError):
