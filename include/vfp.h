@@ -215,6 +215,19 @@ int vfp_mass(vfp_ctx* ctx, const double* in, double* out, int inverse, void* str
  * is allocated. */
 int vfp_apply_adjoint(vfp_ctx* ctx, const double* in, double* out, double* work, void* stream);
 
+/* vfp_apply_adjoint without a work argument, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops,
+ * harnesses that forbid hipMalloc).  The scratch vector M^{-1} in is a fixed
+ * library array of VFP_NOALLOC_MAX_NDOFS doubles (64 MiB) per device, held
+ * until the process ends; the call allocates and frees nothing.  Results
+ * equal vfp_apply_adjoint's to the bit.  VFP_EINVAL if ndofs exceeds
+ * VFP_NOALLOC_MAX_NDOFS or the context lives on another device than the
+ * current one.  Every call on one device shares that array: calls that
+ * overlap in time on a device (other streams, other threads, other
+ * contexts) race on it. */
+#define VFP_NOALLOC_MAX_NDOFS 8388608
+int vfp_apply_adjoint_noalloc(vfp_ctx* ctx, const double* in, double* out, void* stream);
+
 /* One adjoint Runge-Kutta stage in mu variables:
  *     t = cdt K(mu_in);   t_out = t (if t_out != NULL);   acc_out = acc_in + t.
  * If grad_nu != NULL (fwd must then be given), also

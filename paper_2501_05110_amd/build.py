@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-ffp-contract=fast"]
 SOURCES = ["shtab.cpp", "vfp.cpp", "stage.hip", "stage_shock.hip", "stage_batch.hip", "field_grad.hip",
-           "krylov.hip", "reconstruct.hip"]
+           "krylov.hip", "reconstruct.hip", "noalloc.hip"]
 
 
 def _hipcc():

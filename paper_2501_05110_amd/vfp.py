@@ -73,6 +73,7 @@ def load(path: str = None):
         "vfp_advance": (I, [P, P, D, L, P, P]),
         "vfp_mass": (I, [P, P, P, I, P]),
         "vfp_apply_adjoint": (I, [P, P, P, P, P]),
+        "vfp_apply_adjoint_noalloc": (I, [P, P, P, P]),
         "vfp_adjoint_stage": (I, [P, P, P, P, D, P, P, P, P]),
         "vfp_advance_tape": (I, [P, P, D, L, P, P]),
         "vfp_adjoint_steps": (I, [P, P, P, D, L, P, P, P, P, P]),
@@ -106,7 +107,7 @@ def exported_symbols():
             "vfp_query_points", "vfp_set_flow_uniform", "vfp_set_flow_planar",
             "vfp_set_magnetic_uniform", "vfp_set_magnetic_points", "vfp_set_scattering",
             "vfp_set_source_points", "vfp_ndofs", "vfp_cfl_dt", "vfp_apply", "vfp_stage",
-            "vfp_advance", "vfp_mass", "vfp_apply_adjoint", "vfp_adjoint_stage", "vfp_advance_tape",
+            "vfp_advance", "vfp_mass", "vfp_apply_adjoint", "vfp_apply_adjoint_noalloc", "vfp_adjoint_stage", "vfp_advance_tape",
             "vfp_adjoint_steps", "vfp_forward_checkpoints", "vfp_adjoint_checkpointed",
             "vfp_batch_create", "vfp_batch_destroy", "vfp_batch_bind", "vfp_batch_advance",
             "vfp_batch_autotune", "vfp_batch_nclasses", "vfp_batch_class_info",
