@@ -10,17 +10,18 @@ Prints one JSON line: DoF-updates/s over the timed steps, the stage kernel's
 HBM roofline fraction (algorithmic bytes / measured launch time, against
 8 TB/s), and the CPU oracle's rate on a bounded sample of the same workload.
 
-  python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu] [--no-adjoint] [--no-batch]
-                  [--no-other] [--no-theta] [--batch-full] [--copy-probe]
+  python bench.py [--steps K] [--warmup W] [--warmup-seconds S] [--gpus 1] [--no-cpu] [--no-adjoint]
+                  [--no-batch] [--no-other] [--no-theta] [--batch-small] [--copy-probe]
 
 It also reports the adjoint: a 1000-step forward run of the 512 x 64 shock
 and its reverse pass (gradients w.r.t. the initial state and nu per cell,
 and with the flow sensitivities for the shock profile), from sqrt(N)
 checkpoints and from the whole stage tape (151 GB here; the default where
 it fits), with the reverse / forward time ratios, and the batched path:
-512 small shock runs of mixed k and l_max advanced by one launch per stage
-and class against one run per launch sequence (--batch-full: the 256 runs
-of 128-1024 x 32-128 cells), and the stage throughput of the 3-D box
+256 shock runs of 128-1024 x 32-128 cells, mixed k and l_max, advanced by
+one launch per stage and class (workgroup shape and tile order autotuned
+per class) against one run per launch sequence on the same GPU
+(--batch-small: 512 small runs), and the stage throughput of the 3-D box
 (48^3, k=2, l_max=5) and the 1-D line (64 cells, k=1, l_max=3), and
 Theta-method steps (Crank-Nicolson, backward Euler) of the 512 x 64 shock at
 10 times the explicit time step, and (with the other configurations) the
@@ -145,7 +146,9 @@ def adjoint_timing(steps=1000):
                        generator=torch.Generator(device=dev).manual_seed(5))
     lam = lam0.clone()
     t_rev = timed(lambda: op.adjoint_checkpointed(ckpt, dt, steps, seg, tape, lam, gnu, work))
-    # the same with the flow sensitivities (for dJ/d(r, w)) and their reduction
+    # the same with the flow sensitivities (for dJ/d(r, w)) and their reduction;
+    # U' and dU/dt move with (r, w) only inside the shock (the support)
+    op.field_grad_support(vfp.planar_shock_support(op, wl.meta["w"]))
     slots = torch.zeros(op.field_grad_size(), dtype=torch.float64, device=dev)
     nq = wl.ncells_axis[0] * (wl.k + 1)
     gf = [torch.empty(nq, dtype=torch.float64, device=dev) for _ in range(3)]
@@ -197,7 +200,8 @@ def adjoint_timing(steps=1000):
 
 def batch_timing(full=False, steps=None):
     """Many independent shock runs advanced by the batched path (one launch
-    per stage and (k, l_max) class, graph replay, autotuned tile order) and,
+    per stage and (k, l_max) class, graph replay, autotuned workgroup shape and
+    tile order) and,
     on the same GPU and buffers, one run per launch sequence.  full: the 256
     runs of mixed size, k and l_max (about 2.3e9 DoF); else 512 small runs."""
     import numpy as np
@@ -235,7 +239,9 @@ def batch_timing(full=False, steps=None):
     def per_run():
         for i, op in enumerate(ops):
             op.advance(u[i], dts[i], steps, work[i])
+    # the runs advanced alone get the same tuning: each run's own launch shape
     for i, op in enumerate(ops):
+        op.autotune(u[i], work[i][:N[i]], reps=2)
         op.advance(u[i], dts[i], 2, work[i])
     t_s = timed(per_run)
     for x in u:
@@ -247,7 +253,10 @@ def batch_timing(full=False, steps=None):
     return {"workload": "batch_256_mixed" if full else "batch_512_small", "runs": len(ops), "ndofs": tot,
             "steps": steps, "batched_dofs_per_s": tot * steps / t_b, "per_run_dofs_per_s": tot * steps / t_s,
             "speedup": t_s / t_b, "setup_s": t_setup,
-            "classes": [{k: c[k] for k in ("k", "lmax", "runs", "tiles", "tile_map")} for c in cls]}
+            "classes": [{k: c[k] for k in ("k", "lmax", "runs", "tiles", "lanes", "tile_map")} for c in cls],
+            "note": "batched: one launch per stage and (k, l_max) class, graph replay, workgroup shape and tile "
+                    "order tuned per class; alone: each run's stages launched in sequence, launch shape tuned "
+                    "per run"}
 
 
 def extension_timing():
@@ -407,6 +416,7 @@ def other_configs():
     out = {}
     stream = torch.cuda.current_stream()
     for name, wl, steps in (("box3d_48_k2_lmax5", W.config3(), 20), ("line1d_64_k1_lmax3", W.config1(), 100)):
+        # (the line: 100 steps, the configuration's run length)
         op = vfp.Operator(wl)
         N = op.ndofs
         dt = op.cfl_dt(wl.courant)
@@ -415,8 +425,12 @@ def other_configs():
         else:
             u = torch.from_numpy(np.ascontiguousarray(W.nodal_state(wl, wl.meta["init_func"])).ravel()).cuda()
         work = torch.empty(2 * N, dtype=torch.float64, device="cuda")
-        op.advance(u, dt, 3, work)
-        torch.cuda.synchronize()
+        t_w = time.perf_counter()
+        while True:                      # untimed warm-up, at least 0.5 s of kernel time
+            op.advance(u, dt, 3, work)
+            torch.cuda.synchronize()
+            if time.perf_counter() - t_w > 0.5:
+                break
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
         op.advance(u, dt, steps, work)
@@ -426,6 +440,9 @@ def other_configs():
         if not torch.isfinite(u).all():
             raise RuntimeError(f"{name}: state is not finite")
         rec = {"ndofs": N, "steps": steps, "dofs_per_s": N * steps / secs, "us_per_step": secs / steps * 1e6}
+        if name.startswith("line"):
+            rec["path"] = "one launch for all steps (the state in one workgroup's LDS)"
+            rec["steps"] = steps
         if name.startswith("box"):
             per_launch = secs / (4 * steps)
             fields = 8 * wl.ncells * wl.n_basis * 3
@@ -443,13 +460,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--warmup-seconds", type=float, default=2.0,
+                    help="keep warming up (untimed) until this much time has passed")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-other", action="store_true", help="skip the 3-D box and 1-D line legs")
     ap.add_argument("--no-theta", action="store_true", help="skip the Theta-method (implicit) leg")
-    ap.add_argument("--batch-full", action="store_true",
-                    help="also time the 256 mixed runs (about 2.3e9 DoF, 52 GB; minutes of set-up)")
+    ap.add_argument("--batch-small", action="store_true",
+                    help="also time 512 small runs (16-64 x 8-16 cells), where one launch per run is launch-bound")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the stage kernel's default launch shape (no vfp_autotune)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -482,8 +503,23 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # launch shape of the stage kernel: the library times its workgroup
+    # shapes and tile orders on this state and keeps the fastest
+    tuned = op.autotune(u, work[:N], reps=10) if not args.no_autotune else None
+
+    # untimed warm-up: the requested steps, then more until the kernel has
+    # run for --warmup-seconds (the GPU's clocks ramp up over the first
+    # second of sustained work; a short warm-up leaves the timed steps on a
+    # cold clock)
+    t_w = time.perf_counter()
     op.advance(u, dt, args.warmup, work)
     torch.cuda.synchronize()
+    warm_steps = args.warmup
+    while time.perf_counter() - t_w < args.warmup_seconds:
+        op.advance(u, dt, 100, work)
+        torch.cuda.synchronize()
+        warm_steps += 100
+    warm_s = time.perf_counter() - t_w
 
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -526,7 +562,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl.name, "cells": list(wl.ncells_axis), "k": wl.k,
                    "lmax": wl.lmax, "ndofs": N, "dt": dt, "courant": wl.courant,
-                   "stage_launches": launches, "wall_s": wall},
+                   "stage_launches": launches, "wall_s": wall,
+                   "warmup_steps_run": warm_steps, "warmup_s": warm_s, "launch_shape": tuned},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "shock_kernel<2,3,1,false,false>",
@@ -535,15 +572,15 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
     if not args.no_batch:
-        out["batch"] = batch_timing(full=False)
+        out["batch"] = batch_timing(full=True)
+    if args.batch_small:
+        out["batch_small"] = batch_timing(full=False)
     if not args.no_other:
         out["other_configs"] = other_configs()
     if not args.no_theta:
         out["theta"] = theta_timing()
     if not args.no_other:
         out["extensions"] = extension_timing()
-    if args.batch_full:
-        out["batch_full"] = batch_timing(full=True)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

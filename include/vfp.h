@@ -92,7 +92,10 @@ typedef struct vfp_ctx vfp_ctx;
 const char* vfp_last_error(void);
 
 /* Create a context.
- *   lmax       expansion degree l_max, 1..7 (n = (l_max+1)^2 coefficients)
+ *   lmax       expansion degree l_max, 1..11 (n = (l_max+1)^2 coefficients);
+ *              above 7 for one spatial axis x at fixed p, k <= 2, a uniform
+ *              flow and B along x (the closure example of Sec. 4.3; forward
+ *              operator), VFP_EUNSUPPORTED otherwise
  *   k          DG degree 1..5 (Gauss-Lobatto nodes, eq. lagrange-polynomial);
  *              k <= 3 with two axes and k <= 2 with three.  The (x, ln p)
  *              kernels, the adjoint, the mass and the flow-sensitivity calls
@@ -141,16 +144,48 @@ int vfp_set_flow_uniform(vfp_ctx* ctx, const double* U);
 int vfp_set_flow_planar(vfp_ctx* ctx, const double* u, const double* dudx,
                         const double* dudt, const double* u_face);
 
+/* Flow U(x) at every point, for contexts without a momentum axis and with
+ * the momentum term off (U enters through beta^a = U^a 1 + V A^a and the
+ * divergence term (div U) 1 of eq. definitions-advection-reaction-eq; the
+ * flow-gradient terms of R and of beta^p need a momentum axis, which takes
+ * vfp_set_flow_planar).  Host arrays:
+ *   U      [cell][q][3] at the volume points (q as in vfp_query_points)
+ *   gradU  [cell][q][3][3], gradU[..][a][b] = dU_b/dx^a; only the diagonal
+ *          entries of the run's spatial axes are used (div U over those axes)
+ *   U_face naxes arrays; U_face[a] is [face][qf][3] at the Gauss points of
+ *          the faces normal to axis a: faces numbered over (N_a + 1)
+ *          positions on axis a and N_b cells on the other axes (axis 0
+ *          fastest), qf over the (k+1) Gauss points of each other axis in
+ *          increasing axis order (first fastest).  Only U^a is used.  At a
+ *          periodic axis both end positions are given and must agree (one
+ *          face; VFP_EINVAL otherwise).
+ * Upwinding uses the characteristic speeds U^a + lambda V with the constant
+ * eigenvectors of A^a (eq. definition-upwind-flux).  k <= 2.  VFP_EUNSUPPORTED
+ * with a momentum axis, the momentum term or k > 2; VFP_EINVAL for a value
+ * that is not finite. */
+int vfp_set_flow_points(vfp_ctx* ctx, const double* U, const double* gradU,
+                        const double* const* U_face);
+
 /* Uniform magnetic field B (3 components). */
 int vfp_set_magnetic_uniform(vfp_ctx* ctx, const double* B);
 
 /* Magnetic field at every volume point: host array [cell][q][3]
- * (ncells (k+1)^naxes 3 values).  Only for contexts without a ln p axis. */
+ * (ncells (k+1)^naxes 3 values; with a momentum axis the points span it
+ * too, and omega = q B / (gamma m) takes each point's p).  The (x, ln p)
+ * specialised kernels need a uniform B, so this selects the general ones. */
 int vfp_set_magnetic_points(vfp_ctx* ctx, const double* B);
 
 /* Scattering frequency nu of the collision term: nu_cell (host, one value
  * per cell) if not NULL, else the uniform value nu. */
 int vfp_set_scattering(vfp_ctx* ctx, double nu, const double* nu_cell);
+
+/* Scattering frequency at every volume point: host array [cell][q]
+ * (ncells (k+1)^naxes values), integrated by the same Gauss rule as the
+ * other variable coefficients, so nu may vary inside a cell.  Selects the
+ * general kernels.  With nu at the points the per-cell gradient dJ/dnu
+ * (grad_nu of the adjoint calls) and VFP_PRECOND_COLLISION are
+ * VFP_EUNSUPPORTED. */
+int vfp_set_scattering_points(vfp_ctx* ctx, const double* nu);
 
 /* Isotropic source s (the s of eq. monoenergetic-point-source, so that
  * s_000 = sqrt(4 pi) s) at every volume point: host array [cell][q]. */
@@ -163,6 +198,19 @@ int vfp_ndofs(const vfp_ctx* ctx, int64_t* n);
  * beta_a,max bounds the spectral radius of beta^a over the mesh (the CFL rule
  * of the convergence study, Sec. 4.1, summed over axes). */
 int vfp_cfl_dt(const vfp_ctx* ctx, double courant, double* dt);
+
+/* Choose the fastest launch shape of this context's stage kernel by timing:
+ * for the specialised (x, ln p) kernel, every built workgroup shape (lanes
+ * per workgroup, and so cells per tile) and both tile orders (launch order,
+ * or each of the 8 XCDs taking one contiguous range of tiles), reps launches
+ * each of the stage-1 form (reads u, writes work: device, ndofs doubles,
+ * disjoint from u; u is unchanged).  The choice stays with the context (a
+ * later set-up call keeps it where the kernel exists) and changes no result:
+ * every shape computes each cell with the same arithmetic.  chosen (host,
+ * 3 ints, may be NULL):
+ * shape slot, lanes per workgroup, tile order.  Other kernels have one
+ * shape: nothing is timed.  Synchronises `stream`. */
+int vfp_autotune(vfp_ctx* ctx, const double* u, double* work, int reps, int* chosen, void* stream);
 
 /* out = M^{-1}( h [with_source] - D in ).  in, out: device, ndofs doubles,
  * must not overlap (VFP_EINVAL). */
@@ -288,6 +336,15 @@ int vfp_adjoint_checkpointed(vfp_ctx* ctx, const double* ckpt, double dt, int64_
  * (N0 + 1 doubles), overwriting them.  VFP_EUNSUPPORTED for contexts without
  * an (x, ln p) planar flow. */
 int vfp_field_grad_size(const vfp_ctx* ctx, int64_t* n);
+/* Restrict the U' and dU/dt sensitivities (volume and ln p faces) to the x
+ * cells with xcells[i] != 0 (host array of N0 flags; NULL: every cell, the
+ * default); dJ/dU and dJ/dU_face are formed everywhere.  For a caller whose
+ * parameters move U' and dU/dt only on some cells (a tanh shock: its U' and
+ * every parameter derivative of U' and U U' vanish exactly where
+ * 1 - tanh^2(x/w) rounds to 0), the skipped contributions are multiplied
+ * by zero in the chain rule anyway.  Set-up call (synchronous); a new mesh
+ * drops it. */
+int vfp_field_grad_support(vfp_ctx* ctx, const unsigned char* xcells);
 int vfp_field_grad_stage(vfp_ctx* ctx, const double* mu, const double* fwd, double cdt, double* slots,
                          void* stream);
 int vfp_field_grad_reduce(vfp_ctx* ctx, const double* slots, double* g_u, double* g_dudx, double* g_dudt,
@@ -304,7 +361,7 @@ int vfp_field_grad_reduce(vfp_ctx* ctx, const double* slots, double* g_u, double
  */
 
 /* Host only: Y[d n + lms] = Y_lms(theta[d], phi[d]) for d < ndir,
- * n = (lmax+1)^2, 0 <= lmax <= 7 (host arrays). */
+ * n = (lmax+1)^2, 0 <= lmax <= 11 (host arrays). */
 int vfp_sh_eval(int lmax, int64_t ndir, const double* theta, const double* phi, double* Y);
 
 /* f at every basis node of every cell in ndir directions:
@@ -381,8 +438,9 @@ typedef struct vfp_batch vfp_batch;
 #define VFP_BATCH_GRAPH 1u   /* replay each step as a captured HIP graph */
 
 /* Group nruns ready contexts (all on one device, none repeated).  The batch
- * borrows the contexts: they must outlive it, and set-up calls on them
- * after vfp_batch_bind need a new vfp_batch_bind. */
+ * borrows the contexts: they must outlive it.  A set-up call (vfp_set_*) on
+ * a run after vfp_batch_bind makes vfp_batch_advance and vfp_batch_autotune
+ * return VFP_ESTATE, before any launch, until the batch is bound again. */
 int vfp_batch_create(vfp_batch** out, vfp_ctx* const* runs, int nruns, unsigned flags);
 
 void vfp_batch_destroy(vfp_batch* b);
@@ -401,14 +459,18 @@ int vfp_batch_advance(vfp_batch* b, int64_t nsteps, void* stream);
 
 /* Time the batched kernel of every class over the bound buffers (stage-1
  * form: reads u, writes the first work vector; u is unchanged), reps
- * launches per candidate, for each tile order -- launch order, or each of the
- * 8 XCDs taking one contiguous range of tiles -- and keep the faster.
+ * launches per candidate, for each workgroup shape (lanes per workgroup:
+ * 64 / 128 / 256 where n = (l_max+1)^2 divides 64, else 256 / 64 / 128;
+ * cells per tile follow) and each tile order -- launch order, or each of the
+ * 8 XCDs taking one contiguous range of tiles -- and keep the fastest.
+ * Results do not depend on the choice (each cell's arithmetic is the same).
  * Synchronises `stream`; drops a captured graph. */
 int vfp_batch_autotune(vfp_batch* b, int reps, void* stream);
 
 /* Number of classes, and for class i: info[0..7] = k, l_max, rows of B.Omega,
- * runs, batched (1/0), tiles, workgroups per launch (one per tile), tile order
- * (1: XCD ranges). */
+ * runs, batched (1/0), tiles (= workgroups per launch), lanes per workgroup
+ * (the tuned shape; 0 for runs launched one by one), tile order (1: XCD
+ * ranges). */
 int vfp_batch_nclasses(const vfp_batch* b);
 int vfp_batch_class_info(const vfp_batch* b, int i, int* info);
 

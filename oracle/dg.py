@@ -207,8 +207,11 @@ class Grid:
         self.Lend, _ = lagrange(self.ref_nodes, np.array([-1.0, 1.0]))  # (2, j)
         self.phys = Physics(wl.lmax, frozenset(wl.terms), wl.mass, wl.charge)
         nu = wl.nu
-        self.nu_cell = (np.full(self.ncells, float(nu)) if np.isscalar(nu)
-                        else np.asarray(nu, float))
+        # nu is a constant, one value per cell, or a function nu(X, p)
+        # sampled at the quadrature points like the other coefficients
+        self.nu_fn = nu if callable(nu) else None
+        self.nu_cell = (None if self.nu_fn else
+                        np.full(self.ncells, float(nu)) if np.isscalar(nu) else np.asarray(nu, float))
 
     def cell_multi(self, c):
         idx = []
@@ -251,7 +254,7 @@ class Grid:
                          for a in range(self.d)])
 
     def coefficients(self, c, X, p):
-        nu = np.full(X.shape[1], self.nu_cell[c])
+        nu = self.nu_fn(X, p) if self.nu_fn else np.full(X.shape[1], self.nu_cell[c])
         return point_coefficients(self.phys, self.axes, X, p, self.wl.flow,
                                   self.wl.magnetic, nu)
 

@@ -23,8 +23,9 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object
 # packed FP32 instructions stay disabled in every HIP translation unit
 DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-ffp-contract=fast"]
-SOURCES = ["shtab.cpp", "vfp.cpp", "stage.hip", "stage_shock.hip", "stage_batch.hip", "field_grad.hip",
-           "krylov.hip", "reconstruct.hip", "noalloc.hip"]
+SOURCES = ["shtab.cpp", "vfp.cpp", "stage.hip", "stage_gen_1f.hip", "stage_gen_1a.hip", "stage_gen_2f.hip",
+           "stage_gen_2a.hip", "stage_gen_3f.hip", "stage_gen_3a.hip", "stage_shock.hip", "stage_shock_shapes.hip", "stage_batch.hip", "stage_batch_shapes.hip", "field_grad.hip",
+           "krylov.hip", "reconstruct.hip", "noalloc.hip", "resident.hip"]
 
 
 def _hipcc():
@@ -49,7 +50,7 @@ def _compile(src: str, extra=()) -> str:
 def build(verbose: bool = True, out: str = LIB, extra=()) -> str:
     """Compile every source (with optional extra flags) and link `out`."""
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(int(os.environ.get("MAX_JOBS", "8")), len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, tuple(extra)), SOURCES))
     tmp = out + ".tmp"
     cmd = [_hipcc(), "-shared", f"--offload-arch={ARCH}", "-fPIC", *objs, "-o", tmp]

@@ -64,7 +64,8 @@ __device__ __forceinline__ double heav(double x) { return x > 0.0 ? 1.0 : (x < 0
 template <int K, int LMAX>
 __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const double* __restrict__ mu,
                                                            const double* __restrict__ fwd, double cdt,
-                                                           double* __restrict__ slots) {
+                                                           double* __restrict__ slots,
+                                                           const unsigned char* __restrict__ support) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
   constexpr int NB = K1 * K1;
@@ -131,6 +132,46 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
 #pragma unroll
   for (int i = 0; i < 3 * K1; ++i) part[i] = 0.0;
 
+  // The U' and dU/dt sensitivities (volume and ln p faces) are formed for
+  // the x cells the caller's support marks (all without one); the decision
+  // is uniform over the wavefront (the workgroup), whose LDS exchanges all
+  // lanes then take alike.  dJ/dU (volume and x faces) is formed everywhere.
+  bool full = support == nullptr;
+  if (!full) {
+    for (int c2 = 0; c2 < CPB; ++c2) {
+      const int cc = blockIdx.x * CPB + c2;
+      if (cc < M.ncells) full |= support[cc % nx] != 0;
+    }
+  }
+  if (!full) {
+    // dJ/dU at the x Gauss points: t_adv (2/h_x) (d_x mu) f, no exchange
+#pragma unroll
+    for (int q1 = 0; q1 < K1; ++q1) {
+      double wy[K1], my[K1];
+#pragma unroll
+      for (int j0 = 0; j0 < K1; ++j0) {
+        double a = 0.0, b = 0.0;
+#pragma unroll
+        for (int j1 = 0; j1 < K1; ++j1) {
+          a = fma(CB::phi[q1][j1], w[j0 + K1 * j1], a);
+          b = fma(CB::phi[q1][j1], m[j0 + K1 * j1], b);
+        }
+        wy[j0] = a;
+        my[j0] = b;
+      }
+#pragma unroll
+      for (int q0 = 0; q0 < K1; ++q0) {
+        double f = 0.0, mx = 0.0;
+#pragma unroll
+        for (int j0 = 0; j0 < K1; ++j0) {
+          f = fma(CB::phi[q0][j0], wy[j0], f);
+          mx = fma(CB::dphi[q0][j0], my[j0], mx);
+        }
+        const double wq = gw[q0] * gw[q1] * jac;
+        part[S::VOL + 3 * q0 + 0] += wq * (s2hx * t_adv * mx * f);
+      }
+    }
+  } else {
   // ---- volume, one row of Gauss points (fixed q1) at a time: interpolate
   // along ln p first (K1 values per row), then along x
 #pragma unroll
@@ -184,6 +225,8 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
     wave_sync();
   }
 
+  }
+
   if (in_grp)
 #pragma unroll
     for (int i = 0; i < 3 * K1; ++i) Rd[(S::VOL + i) * N + r] = part[i];
@@ -217,6 +260,13 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
   // the mesh counted as zero
 #pragma unroll
   for (int ax = 0; ax < 2; ++ax) {
+    if (ax == 1 && !full) {
+      // no U' and dU/dt sensitivities here: the ln p face slots stay zero
+      if (in_grp)
+#pragma unroll
+        for (int i = 0; i < 4 * K1; ++i) Rd[(S::PF + i) * N + r] = 0.0;
+      break;
+    }
     const int ia = ax ? ip : ix, na = ax ? np : nx;
     // f1, f2 rows of both sides: [side][f1 / f2][q] in X
 #pragma unroll
@@ -367,11 +417,12 @@ __global__ void fgrad_reduce_kernel(MeshArgs M, const double* __restrict__ slots
 
 template <int K, int LMAX>
 void launch_fg_t(const KernelArgs& a, const double* mu, const double* fwd, double cdt, double* slots,
-                 hipStream_t s) {
+                 const unsigned char* support, hipStream_t s) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int CPB = (kFgThreads / N) > 0 ? kFgThreads / N : 1;
   const int blocks = (a.mesh.ncells + CPB - 1) / CPB;
-  hipLaunchKernelGGL((fgrad_kernel<K, LMAX>), dim3(blocks), dim3(kFgThreads), 0, s, a, mu, fwd, cdt, slots);
+  hipLaunchKernelGGL((fgrad_kernel<K, LMAX>), dim3(blocks), dim3(kFgThreads), 0, s, a, mu, fwd, cdt, slots,
+                     support);
 }
 
 template <int K>

@@ -4,7 +4,7 @@
 
 namespace vfp {
 
-constexpr int kMaxLmax = 7;
+constexpr int kMaxLmax = 11;     // above 7: runs along x with B along x only (general kernels)
 constexpr int kMaxN = (kMaxLmax + 1) * (kMaxLmax + 1);
 constexpr int kMaxK = 5;           // general kernels: k <= 5 on one axis, 3 on two, 2 on three
 constexpr int kMaxK1 = kMaxK + 1;
@@ -21,6 +21,8 @@ struct Basis1D {
   double dtst[kMaxK1][kMaxK1];   // dtst[i][q] = sum_j (M1^{-1})_ij l_j'(g_q) w_q
   double lift[2][kMaxK1];        // lift[side][i] = (M1^{-1})_{i, 0 or K}
   double dphi[kMaxK1][kMaxK1];   // dphi[q][j] = l_j'(g_q)
+  double dvol[kMaxK1][kMaxK1];   // dvol[i][j] = sum_q dtst[i][q] phi[q][j]: the 1-D volume derivative
+                                 // term of a coefficient constant on the cell, in node space
   double mass[kMaxK1][kMaxK1];   // M1
   double imass[kMaxK1][kMaxK1];  // M1^{-1}
 };
@@ -51,6 +53,10 @@ struct RowTables {
   const int* rot_col;
   const double* rot_val;
   int nrot;
+  // dense eigen-decomposition of A^a per spatial axis (point flows):
+  // wd[a][j n + k] = W[j][k] (orthonormal columns), lamd[a][k] = lambda_k
+  const double* wd[3];
+  const double* lamd[3];
   // uniform-axis face matrices beta^a and |beta^a| (per spatial axis)
   const int* fb_col[3];
   const double* fb_val[3];
@@ -61,12 +67,19 @@ struct RowTables {
 };
 
 struct FieldArgs {
-  // planar flow along x (profile) -- used when the kernel is built with XPROF
+  // planar flow along x (profile) -- used by the kernels built for a planar profile
   const double* u_vol;   // [N0 (k+1)]
   const double* du_vol;
   const double* a_vol;
   const double* u_face;  // [N0 + 1]
-  double U[3];           // uniform flow components (y, z always; x if !XPROF)
+  double U[3];           // uniform flow components (y, z always; x without a profile)
+  // flow at the points (kernels built for point flows): [cell][q][4] holding
+  // U^x, U^y, U^z and div U (summed over the run's spatial axes); and per
+  // axis a the normal component U^a at the face points [face][qf], faces
+  // numbered over (N_a + 1) positions on axis a and N_b on the others (axis 0
+  // fastest), points over the other axes in increasing order (first fastest)
+  const double* u_pts;
+  const double* uf_pts[3];
   // momentum axis profiles (ln p): at volume points [Np (k+1)] and faces [Np+1]
   const double* V_vol;
   const double* iV_vol;   // 1/V
@@ -102,6 +115,7 @@ struct FieldArgs {
   // scattering and source
   double nu0;
   const double* nu_cell;  // [cell] or null
+  const double* nu_pts;   // [cell][q] at the volume points, or null (takes precedence)
   const double* src;      // [cell][nb] = M^{-1} h (000 component) or null
   // term multipliers (0 or 1)
   double t_adv, t_mom, t_rot, t_col;

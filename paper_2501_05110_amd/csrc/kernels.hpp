@@ -21,7 +21,9 @@
 
 namespace vfp {
 
-extern __constant__ Basis1D c_basis[kMaxK];
+// One copy per translation unit (no relocatable device code); the host fills
+// every copy that launches kernels reading it (upload_basis).
+static __constant__ Basis1D c_basis[kMaxK];
 
 // A generic pointer known to address global memory, retyped into the global
 // address space: loads and stores through it are global (not flat) memory
@@ -56,6 +58,28 @@ __device__ __forceinline__ void sweep(const double* in, double* out, const doubl
   }
 }
 
+// In-place form of sweep: each line of K1 values along AX is replaced by M
+// times itself (one line of temporaries instead of a second tensor).
+template <int D, int K1, int AX>
+__device__ __forceinline__ void sweep_ip(double* v, const double (&M)[kMaxK1][kMaxK1]) {
+  constexpr int NB = IPow<K1, D>::v;
+  constexpr int st = IPow<K1, AX>::v;
+#pragma unroll
+  for (int base = 0; base < NB; ++base) {
+    if ((base / st) % K1 != 0) continue;
+    double t[K1];
+#pragma unroll
+    for (int j = 0; j < K1; ++j) t[j] = v[base + j * st];
+#pragma unroll
+    for (int q = 0; q < K1; ++q) {
+      double acc = 0.0;
+#pragma unroll
+      for (int j = 0; j < K1; ++j) acc = fma(M[q][j], t[j], acc);
+      v[base + q * st] = acc;
+    }
+  }
+}
+
 // Contract a quadrature-point tensor with the test matrices: axis DER uses
 // dtst, the others tst (DER < 0: tst everywhere).  out += scale * result.
 template <int D, int K, int DER>
@@ -78,6 +102,29 @@ __device__ __forceinline__ void contract_add(const double* g, double* out, doubl
 #pragma unroll
     for (int i = 0; i < NB; ++i) out[i] = fma(scale, t0[i], out[i]);
   }
+}
+
+// contract_add with tst on every axis, in place: g is overwritten.
+template <int D, int K>
+__device__ __forceinline__ void contract_add_ip(double* g, double* out, double scale) {
+  constexpr int K1 = K + 1;
+  constexpr int NB = IPow<K1, D>::v;
+  const Basis1D& bs = c_basis[K - 1];
+  sweep_ip<D, K1, 0>(g, bs.tst);
+  if constexpr (D > 1) sweep_ip<D, K1, (D > 1 ? 1 : 0)>(g, bs.tst);
+  if constexpr (D > 2) sweep_ip<D, K1, (D > 2 ? 2 : 0)>(g, bs.tst);
+#pragma unroll
+  for (int i = 0; i < NB; ++i) out[i] = fma(scale, g[i], out[i]);
+}
+
+// Interpolate nodal values to the Gauss points in place (all axes).
+template <int D, int K>
+__device__ __forceinline__ void interp_ip(double* v) {
+  constexpr int K1 = K + 1;
+  const Basis1D& bs = c_basis[K - 1];
+  sweep_ip<D, K1, 0>(v, bs.phi);
+  if constexpr (D > 1) sweep_ip<D, K1, (D > 1 ? 1 : 0)>(v, bs.phi);
+  if constexpr (D > 2) sweep_ip<D, K1, (D > 2 ? 2 : 0)>(v, bs.phi);
 }
 
 // Interpolate nodal values to the Gauss points (all axes).

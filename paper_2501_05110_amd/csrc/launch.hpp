@@ -8,12 +8,13 @@ namespace vfp {
 
 using StageLauncher = void (*)(const KernelArgs&, hipStream_t);
 
-// Kernel for (axes D, degree k, l_max, ln-p axis present, planar-x flow
-// profile), or nullptr if that combination is not built.
-StageLauncher find_stage_launcher(int D, int k, int lmax, bool mom, bool xprof);
+// Kernel for (axes D, degree k, l_max, ln-p axis present, flow kind: 0
+// uniform, 1 planar x profile, 2 given at the points), or nullptr if that
+// combination is not built.
+StageLauncher find_stage_launcher(int D, int k, int lmax, bool mom, int flow);
 
 // Adjoint kernel (K = -M^{-1} D^T on mu = M^{-1} lambda) for the same families.
-StageLauncher find_adjoint_launcher(int D, int k, int lmax, bool mom, bool xprof);
+StageLauncher find_adjoint_launcher(int D, int k, int lmax, bool mom, int flow);
 
 // out = M in (inv = false) or M^{-1} in per cell, n coefficients per node.
 using MassLauncher = void (*)(const MeshArgs&, int n, const double* in, double* out, bool inv, hipStream_t);
@@ -24,22 +25,34 @@ MassLauncher find_mass_launcher(int D, int k);
 // linp: the momentum axis is p itself instead of ln p.
 StageLauncher find_shock_launcher(int k, int lmax, int nrot, bool linp = false);
 StageLauncher find_shock_adjoint_launcher(int k, int lmax, int nrot, bool linp = false);
+// The forward ln p kernel in workgroup shape slot 1 or 2 (slot 0 is the
+// default of find_shock_launcher): 128 / 256 lanes where n divides 64, else
+// 64 / 128 lanes; built for nrot = 1.  nullptr where not built.
+StageLauncher find_shock_launcher_shape(int k, int lmax, int nrot, int slot);
+constexpr int kShockShapes = 3;
+// Cells per workgroup (tile) and lanes of shape slot 0..2 for l_max.
+int shock_shape_cells(int lmax, int slot);
+int shock_shape_threads(int lmax, int slot);
 
 // Batched (x, ln p) forward stage over many runs of one (k, l_max, nrot)
-// class: one workgroup per tile.
+// class: one workgroup per tile, in workgroup shape slot 0..2 (as above).
 struct BatchKernel {
   void (*launch)(const BatchArgs&, hipStream_t) = nullptr;
   int cells_per_tile = 0;
+  int threads = 0;
 };
-BatchKernel find_shock_batch_kernel(int k, int lmax, int nrot);
+BatchKernel find_shock_batch_kernel(int k, int lmax, int nrot, int slot = 0);
+BatchKernel find_shock_batch_kernel_shape(int k, int lmax, int nrot, int slot);
 int shock_cells_per_tile(int lmax);
 
 // Field sensitivities of one stage (planar flow of an (x, ln p) run):
 // accumulate cdt <mu, d(h - D fwd)/dfield> into per-cell slots; reduce the
 // slots to dJ/dU, dJ/dU', dJ/d(dU/dt) at the x Gauss points and dJ/dU at the
 // x faces.
+// support: per x cell, 0 where the U' and dU/dt sensitivities are not
+// wanted (null: everywhere).
 using FieldGradLauncher = void (*)(const KernelArgs&, const double* mu, const double* fwd, double cdt,
-                                   double* slots, hipStream_t);
+                                   double* slots, const unsigned char* support, hipStream_t);
 using FieldGradReduce = void (*)(const MeshArgs&, const double* slots, double* g_u, double* g_du, double* g_a,
                                  double* g_uf, hipStream_t);
 FieldGradLauncher find_field_grad_launcher(int k, int lmax);
@@ -71,6 +84,15 @@ int reconstruct_max_lms();
 
 hipError_t upload_basis(const Basis1D* b);
 
+// A small run on one axis (uniform flow, fixed p, uniform B; 3 ndofs doubles
+// within resident_max_lds() bytes) advanced nsteps Runge-Kutta steps in one
+// launch of one workgroup holding the state in LDS; u in place.
+using ResidentLauncher = void (*)(const KernelArgs&, double dt, long long nsteps, double* u, hipStream_t);
+ResidentLauncher find_resident_launcher(int k, int lmax);
+size_t resident_max_lds();
+hipError_t upload_basis_resident(const Basis1D* b);
+
 int stage_cells_per_block(int lmax);
+int stage_threads_general();
 
 }  // namespace vfp

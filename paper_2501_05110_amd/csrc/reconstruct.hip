@@ -21,7 +21,8 @@ namespace vfp {
 namespace {
 
 constexpr int kRecThreads = 256;
-constexpr int kRecMaxN = 64;
+constexpr int kRecMaxN = 64;        // LDS-tiled kernels
+constexpr int kRecMaxWideN = 144;   // the plain kernel beyond (l_max <= 11)
 constexpr int kRecRowsPerLane = 4;
 
 template <int DIRS>
@@ -117,16 +118,37 @@ void launch_t(const double* zeta, int64_t rows, int n, const double* Y, int64_t 
   hipLaunchKernelGGL(reconstruct_kernel<DIRS>, grid, dim3(kRecThreads), lds, s, zeta, rows, n, Y, ndir, out);
 }
 
+// n > 64 (l_max 8..11): one output per lane, the row and the direction's
+// table read through the caches (the LDS tiles above are sized for n <= 64).
+__global__ __launch_bounds__(256) void reconstruct_wide_kernel(const double* __restrict__ zeta, int64_t rows, int n,
+                                                              const double* __restrict__ Y, int64_t ndir,
+                                                              double* __restrict__ out) {
+  const int64_t total = rows * ndir;
+  for (int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x; t < total; t += (int64_t)gridDim.x * 256) {
+    const int64_t r = t / ndir, d = t - r * ndir;
+    const double* z = zeta + r * n;
+    const double* y = Y + d * n;
+    double acc = 0.0;
+    for (int j = 0; j < n; ++j) acc = fma(z[j], y[j], acc);
+    out[t] = acc;
+  }
+}
+
 }  // namespace
 
-int reconstruct_max_lms() { return kRecMaxN; }
+int reconstruct_max_lms() { return kRecMaxWideN; }
 
 // LDS per workgroup stays within 64 KB: 64 directions need (32 + 64) 65
 // doubles (50 KB); 16 directions need (128 + 16)(n + 1), taken up to n = 49
 // (58 KB)
 void launch_reconstruct(const double* zeta, int64_t rows, int n, const double* Y, int64_t ndir, double* out,
                         hipStream_t s) {
-  if (ndir <= 16 && n <= 49)
+  if (n > kRecMaxN) {
+    const int64_t total = rows * ndir;
+    const int64_t blocks = (total + 255) / 256;
+    hipLaunchKernelGGL(reconstruct_wide_kernel, dim3((unsigned)(blocks < 65536 ? blocks : 65536)), dim3(256), 0, s,
+                       zeta, rows, n, Y, ndir, out);
+  } else if (ndir <= 16 && n <= 49)
     launch_t<16>(zeta, rows, n, Y, ndir, out, s);
   else
     launch_t<64>(zeta, rows, n, Y, ndir, out, s);

@@ -52,6 +52,15 @@ namespace shock {
 #ifndef VFP_NT_LOAD_U
 #define VFP_NT_LOAD_U 0
 #endif
+#ifndef VFP_LATE_U
+#define VFP_LATE_U 0
+#endif
+// ln p neighbour traces loaded after the x faces, and only for cells whose
+// x column has a flow gradient (measured faster: 96.7 against 100.8 us per
+// launch at 1024 x 128)
+#ifndef VFP_LATE_PT
+#define VFP_LATE_PT 1
+#endif
 
 // per-cell scalar record in LDS (doubles): the packed x record of the cell's
 // x column, the packed p record of its p row, the p-face codes and nu
@@ -80,19 +89,26 @@ enum : int {
 constexpr int kRec2 = 8;         // doubles per extra p record (linear p axis)
 static_assert(kRec == 16, "record layout");
 
-template <int N>
+// Workgroup shape: TPB lanes (0: the default, one wavefront where n divides
+// 64, else 256 lanes) holding floor(TPB / n) cells (at least one).  kWave:
+// the lanes of every cell lie in one wavefront, so the per-cell LDS
+// exchanges need only wavefront-level ordering.
+template <int N, int TPB = 0>
 struct Launch {
-  static constexpr bool kWave = (64 % N) == 0;
-  static constexpr int kThreads = kWave ? 64 : 256;
+  static constexpr int kThreads = TPB ? TPB : ((64 % N) == 0 ? 64 : 256);
+  static constexpr bool kWave = (64 % N) == 0 || kThreads == 64;
   static constexpr int kCells = (kThreads / N) > 0 ? kThreads / N : 1;
+  // cells whose lanes share one wavefront (the uniformity scope of a branch
+  // taken before wavefront-level ordering points)
+  static constexpr int kCellsPerWave = (64 % N) == 0 ? 64 / N : kCells;
 };
 
 // Orders the LDS exchange between the lanes of one cell.  LDS operations of
 // one wavefront complete in order, so within a wavefront a compiler-level
 // fence suffices; otherwise the workgroup synchronises.
-template <int N>
+template <int N, int TPB = 0>
 __device__ __forceinline__ void cell_sync() {
-  if constexpr (Launch<N>::kWave) {
+  if constexpr (Launch<N, TPB>::kWave) {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -107,12 +123,13 @@ __device__ __forceinline__ void cell_sync() {
 // + U' p (A^x A^x)_t), -div beta = dU/dt V A^x + U' (A^x A^x)_t - div U);
 // the p record then carries V, 1/V, -V (in the m/(gamma p) slot), q/(gamma m),
 // t_mom gamma m at the faces, and the extra record gamma m, p, p at the faces.
-template <int K, int LMAX, int NROT, bool ADJ, bool LINP = false>
+template <int K, int LMAX, int NROT, bool ADJ, bool LINP = false, int TPB = 0>
 __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
   constexpr int NB = K1 * K1;
-  constexpr int CPB = Launch<N>::kCells;
+  using LS = Launch<N, TPB>;
+  constexpr int CPB = LS::kCells;
   constexpr int XR = (ADJ ? 3 : 2) * K1;   // exchange rows per cell
   using CB = CBasis<K>;
   static_assert(K1 <= 3, "basis tables");
@@ -175,8 +192,11 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   // trace (continuous) below.
   double tn[2][2][K1];
   bool use_n[2][2];
-#pragma unroll
-  for (int ax = 0; ax < 2; ++ax)
+  // the ln p neighbours' traces matter only where the cell's x column has a
+  // flow gradient (elsewhere beta^{ln p} = 0 and the ln p flux vanishes);
+  // with VFP_LATE_PT they are loaded after the x faces, and only there
+  const bool cgrad = !VFP_LATE_PT || gp(F.xrec)[(size_t)ix * kRec + X_GRAD] != 0.0;
+  auto load_traces = [&](int ax) {
 #pragma unroll
     for (int side = 0; side < 2; ++side) {
       const int ia = ax ? ip : ix, na = ax ? np : nx, st = ax ? nx : 1;
@@ -186,12 +206,16 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
       ni = (ni + na) % na;
       const auto nb0 = gp(A.st.w_in) + (size_t)(cell + (ni - ia) * st) * NB * N + r;
       const int jn = side ? 0 : K;
+      const bool need = ax == 0 || cgrad;
 #pragma unroll
       for (int j = 0; j < K1; ++j) {
         const int node = ax ? (j + K1 * jn) : (jn + K1 * j);
-        tn[ax][side][j] = nb0[(size_t)node * N];   // a valid cell; unused where !use_n
+        tn[ax][side][j] = need ? nb0[(size_t)node * N] : 0.0;   // a valid cell; unused where !use_n
       }
     }
+  };
+  load_traces(0);
+  if constexpr (!VFP_LATE_PT) load_traces(1);
 
   // rows for the x faces
   int mem[LMAX + 1];
@@ -265,7 +289,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
         X[(K1 + q) * N + r] = b;
       }
     }
-    cell_sync<N>();
+    cell_sync<N, TPB>();
     double Jc[K1];
     const double UF = sc[X_UF + side];
 #pragma unroll
@@ -279,12 +303,12 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
       const double mu = fma(F.t_adv * lam, sc[P_V + q], UF);
       Jc[q] = fmax(mu, 0.0) * c1 + fmin(mu, 0.0) * c2;
     }
-    cell_sync<N>();
+    cell_sync<N, TPB>();
     if (in_grp) {
 #pragma unroll
       for (int q = 0; q < K1; ++q) X[q * N + r] = Jc[q];
     }
-    cell_sync<N>();
+    cell_sync<N, TPB>();
     double J[K1];
 #pragma unroll
     for (int q = 0; q < K1; ++q) {
@@ -304,18 +328,26 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
       for (int i0 = 0; i0 < K1; ++i0) res[i0 + K1 * i1] = fma(CB::lift[side][i0], jn, res[i0 + K1 * i1]);
     }
-    cell_sync<N>();
+    cell_sync<N, TPB>();
   }
 
   // Where the flow has no gradient (dU/dx = dU/dt = 0 at every Gauss point of
   // the x cell) beta^{ln p} vanishes and so do all momentum terms: the p-face
   // flux is zero and the volume drops those terms (exactly: they are products
-  // with zero).  The test is uniform over the workgroup (the records of all
-  // its cells are in LDS after the x faces), so every barrier below is taken
-  // by all lanes alike.
+  // with zero).  The test is uniform over the scope of the ordering points
+  // below -- the wavefront with wavefront-level ordering, else the workgroup
+  // -- whose cells' records are all in LDS after the x faces, so every
+  // ordering point is taken by all of its lanes alike.
   bool grad = false;
+  {
+    constexpr int CPW = LS::kCellsPerWave;
+    const int c0 = LS::kWave ? (tid / 64) * CPW : 0;
 #pragma unroll
-  for (int c2 = 0; c2 < CPB; ++c2) grad |= shs[c2 * SST + X_GRAD] != 0.0;
+    for (int c2 = 0; c2 < CPW; ++c2)
+      if (c0 + c2 < CPB) grad |= shs[(c0 + c2) * SST + X_GRAD] != 0.0;
+  }
+
+  if constexpr (VFP_LATE_PT) load_traces(1);
 
   // ---- ln p faces: beta^{ln p} = a1 A^x + a2 (A^x A^x)_t per point ---------
   const int axc0 = gp(T.ax_col)[r], axc1 = gp(T.ax_col)[N + r];
@@ -354,7 +386,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
         X[(K1 + q) * N + r] = b;
       }
     }
-    cell_sync<N>();
+    cell_sync<N, TPB>();
     const double iVf = sc[P_IVF + side];
     double J[K1];
 #pragma unroll
@@ -386,7 +418,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
       for (int i1 = 0; i1 < K1; ++i1) res[i0 + K1 * i1] = fma(CB::lift[side][i1], jn, res[i0 + K1 * i1]);
     }
-    cell_sync<N>();
+    cell_sync<N, TPB>();
   }
 
   // u (the stage base) is loaded now so that its latency hides behind the
@@ -394,6 +426,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   // keeps the in-place form w_out == u correct
   double uu[NB];
   const bool use_u = A.st.alpha != 0.0;
+#if !VFP_LATE_U
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
 #if VFP_NT_LOAD_U
@@ -402,12 +435,16 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
     uu[b] = use_u ? gp(A.st.u)[cbase + (size_t)b * N] : 0.0;
 #endif
   }
+#endif
   double ff[ADJ ? NB : 1];
   const bool use_g = ADJ && gp(A.adj.fwd) && gp(A.adj.grad_nu);
-  if constexpr (ADJ) {
+  auto load_ff = [&]() {
+    if constexpr (ADJ) {
 #pragma unroll
-    for (int b = 0; b < NB; ++b) ff[b] = use_g ? gp(A.adj.fwd)[cbase + (size_t)b * N] : 0.0;
-  }
+      for (int b = 0; b < NB; ++b) ff[b] = use_g ? gp(A.adj.fwd)[cbase + (size_t)b * N] : 0.0;
+    }
+  };
+  if constexpr (!VFP_LATE_U) load_ff();
 
   // ---- volume, one row of Gauss points (fixed q1) at a time -----------------
   if constexpr (!ADJ) {
@@ -451,7 +488,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
             X[q0 * N + r] = acc;
           }
         }
-        cell_sync<N>();
+        cell_sync<N, TPB>();
         const double pV = tas2hx * sc[P_V + q1];
         const double piV = sc[P_IV + q1];
         const double pid = sc[P_ID + q1];
@@ -508,7 +545,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
               if (CB::dtst[i1][q1] != 0.0) v = fma(CB::dtst[i1][q1], bc[i0], v);
             res[i0 + K1 * i1] = v;
           }
-        cell_sync<N>();
+        cell_sync<N, TPB>();
       }
     };
     if (grad) rows(std::true_type{});
@@ -564,7 +601,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
             if constexpr (GR) X[(2 * K1 + q0) * N + r] = dp;
           }
         }
-        cell_sync<N>();
+        cell_sync<N, TPB>();
         const double pV = tas2hx * sc[P_V + q1];
         const double piV = sc[P_IV + q1];
         const double pid = sc[P_ID + q1];
@@ -618,7 +655,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
           for (int i0 = 0; i0 < K1; ++i0)
             if (CB::tst[i1][q1] != 0.0) res[i0 + K1 * i1] = fma(CB::tst[i1][q1], ac[i0], res[i0 + K1 * i1]);
-        cell_sync<N>();
+        cell_sync<N, TPB>();
       }
     };
     if (grad) rows(std::true_type{});
@@ -649,6 +686,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
           v[i0 + K1 * i1] = acc;
         }
     };
+    if constexpr (VFP_LATE_U) load_ff();
     const double jac = 1.0 / (sc[X_S2H] * sc[P_S2H]);
     if (A.adj.mass_out) {
       ref_mass2(res);
@@ -663,7 +701,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
       for (int b = 0; b < NB; ++b) part = fma(w[b], ff[b], part);
       part *= gp(T.c_val)[r] * jac;
       if (in_grp) X[r] = part;
-      cell_sync<N>();
+      cell_sync<N, TPB>();
       if (act && r == 0) {
         double sum = 0.0;
         for (int j = 0; j < N; ++j) sum += X[j];
@@ -681,6 +719,10 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) res[b] += src[b];
   }
+#if VFP_LATE_U
+#pragma unroll
+  for (int b = 0; b < NB; ++b) uu[b] = use_u ? gp(A.st.u)[cbase + (size_t)b * N] : 0.0;
+#endif
   if (act) {
     const double al = A.st.alpha, be = A.st.beta;
 #pragma unroll

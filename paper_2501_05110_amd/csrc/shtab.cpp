@@ -179,10 +179,34 @@ void clean(Mat& M) {
 }  // namespace
 
 ShMatrices build_sh_matrices(int lmax) {
-  if (lmax < 0 || lmax > 8) throw std::invalid_argument("lmax");
+  if (lmax < 0 || lmax > kShAxisOnlyMaxLmax) throw std::invalid_argument("lmax");
   const int L = lmax + 1;
   const int n = (lmax + 1) * (lmax + 1);
   Mat Ax = ax_closed(L), Omx = omx_closed(L);
+  if (lmax > kShFullMaxLmax) {
+    // Above l_max = 7 only the x-axis matrices are built: the alternating
+    // factorial sums of eq. complex-rotation lose more digits than a 1e-12
+    // operator allows from l = 9 on.  A^x, Omega^x and (A^x A^x)_t carry
+    // runs along x with B along x (the closure example of Sec. 4.3); the
+    // other matrices stay zero and the library refuses runs that need them.
+    ShMatrices S;
+    S.lmax = lmax;
+    S.n = n;
+    S.A[0] = truncate(Ax, n);
+    S.A[1] = Mat(n);
+    S.A[2] = Mat(n);
+    S.Om[0] = truncate(Omx, n);
+    S.Om[1] = Mat(n);
+    S.Om[2] = Mat(n);
+    S.AXX = truncate(matmul(Ax, Ax), n);
+    S.G1 = Mat(n);
+    S.G2 = Mat(n);
+    clean(S.AXX);
+    S.C.resize(n);
+    for (int l = 0; l <= lmax; ++l)
+      for (int j = l * l; j < (l + 1) * (l + 1); ++j) S.C[j] = 0.5 * l * (l + 1);
+    return S;
+  }
   Mat Rz = rz_closed(L);
   Mat Rx = transpose(rx_printed(L));   // exp(+pi/2 Omega^x)
   Mat RzT = transpose(Rz), RxT = transpose(Rx);

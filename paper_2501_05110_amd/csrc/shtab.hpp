@@ -34,9 +34,15 @@ struct ShMatrices {
   std::vector<double> C;  // l(l+1)/2
 };
 
+// l_max up to which every matrix is built, and up to which the x-axis
+// matrices alone are (A^x, Omega^x, (A^x A^x)_t; the others zero).
+constexpr int kShFullMaxLmax = 7;
+constexpr int kShAxisOnlyMaxLmax = 11;
+
 // Builds every matrix for l_max from the closed forms: A^x and Omega^x
 // directly, A^{y,z} and Omega^{y,z} through the pi/2 rotation matrices, the
-// products at l_max+1 then truncated.
+// products at l_max+1 then truncated (above kShFullMaxLmax: the x-axis
+// matrices only).
 ShMatrices build_sh_matrices(int lmax);
 
 // Y[lms] = Y_lms(theta, phi) for lms < (lmax+1)^2 (App. A; theta from the x

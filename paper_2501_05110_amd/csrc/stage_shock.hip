@@ -8,19 +8,19 @@ namespace {
 
 using namespace shock;
 
-template <int K, int LMAX, int NROT, bool ADJ, bool LINP>
-__global__ __launch_bounds__(Launch<(LMAX + 1) * (LMAX + 1)>::kThreads) __attribute__((amdgpu_waves_per_eu(VFP_SHOCK_WAVES)))
+template <int K, int LMAX, int NROT, bool ADJ, bool LINP, int TPB>
+__global__ __launch_bounds__((Launch<(LMAX + 1) * (LMAX + 1), TPB>::kThreads)) __attribute__((amdgpu_waves_per_eu(VFP_SHOCK_WAVES)))
 void shock_kernel(KernelArgs A) {
   const int blk = A.tile_map ? xcd_tile(blockIdx.x, gridDim.x) : blockIdx.x;
-  shock_body<K, LMAX, NROT, ADJ, LINP>(A, blk);
+  shock_body<K, LMAX, NROT, ADJ, LINP, TPB>(A, blk);
 }
 
-template <int K, int LMAX, int NROT, bool ADJ, bool LINP>
+template <int K, int LMAX, int NROT, bool ADJ, bool LINP, int TPB = 0>
 void launch_shock_t(const KernelArgs& a, hipStream_t s) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
-  using L = Launch<N>;
+  using L = Launch<N, TPB>;
   const int blocks = (a.mesh.ncells + L::kCells - 1) / L::kCells;
-  hipLaunchKernelGGL((shock_kernel<K, LMAX, NROT, ADJ, LINP>), dim3(blocks), dim3(L::kThreads), 0, s, a);
+  hipLaunchKernelGGL((shock_kernel<K, LMAX, NROT, ADJ, LINP, TPB>), dim3(blocks), dim3(L::kThreads), 0, s, a);
 }
 
 template <int K, int NROT, bool ADJ, bool LINP>

@@ -211,6 +211,12 @@ Basis1D make_basis(int k) {
     for (int j = 0; j < K1; ++j) B.dphi[q][j] = dlag(j, g[q]);
   for (int i = 0; i < K1; ++i)
     for (int j = 0; j < K1; ++j) {
+      double acc = 0.0;
+      for (int q = 0; q < K1; ++q) acc += B.dtst[i][q] * B.phi[q][j];
+      B.dvol[i][j] = acc;
+    }
+  for (int i = 0; i < K1; ++i)
+    for (int j = 0; j < K1; ++j) {
       B.mass[i][j] = M1[i][j];
       B.imass[i][j] = Mi[i][j];
     }
@@ -252,13 +258,18 @@ struct vfp_ctx {
   bool have_Bpts = false;
   double nu0 = 0.0;
   bool have_nu_cell = false;
+  bool have_nu_pts = false;  // nu at the volume points (vfp_set_scattering_points)
   bool have_src = false;
+  bool pflow = false;        // U at the points (vfp_set_flow_points)
+  double pflow_umax[3] = {0, 0, 0};   // max |U^a| over the volume and face points
 
   // device data
   DevBuf d_s2h[3], d_u_vol, d_du_vol, d_a_vol, d_u_face;
   DevBuf d_V_vol, d_iV_vol, d_idiv_vol, d_ig_vol, d_iV_face, d_ca_vol, d_cu_vol, d_cu_face;
   DevBuf d_pf_code, d_pf_coded, d_pf_tab, d_pf_dtab, d_Bpts, d_nu, d_src;
   DevBuf d_itab, d_dtab, d_xrec, d_prec, d_prec2;
+  DevBuf d_u_pts, d_uf_pts[3], d_nu_pts;
+  DevBuf d_fg_support;      // x cells whose U' and dU/dt sensitivities are formed (vfp_field_grad_support)
   RowTables tab{};
   FieldArgs fld{};
   MeshArgs meshargs{};
@@ -273,6 +284,9 @@ struct vfp_ctx {
   bool force_general = false;
   bool shock = false;       // the (x, ln p) kernels are in use
   int tile_map = 0;         // XCD-range tile order for the (x, ln p) kernels (VFP_TILE_MAP=1)
+  int shape = 0;            // workgroup shape slot of the forward (x, ln p) kernel (vfp_autotune)
+  ResidentLauncher resident = nullptr;   // whole-run single-workgroup stepping (small runs on one axis)
+  uint64_t gen = 0;         // bumped by every set-up call; a batch bound to older data refuses to run
 };
 
 namespace {
@@ -392,11 +406,28 @@ int build_row_tables(vfp_ctx* c) {
     dv[o_lam + r] = lam[pos];
   }
 
+  // point flows: eigenvectors and eigenvalues of A^a per spatial axis (the
+  // characteristic speeds U^a + lambda V vary from face point to face point)
+  size_t o_wd[3] = {0, 0, 0}, o_lamd[3] = {0, 0, 0};
+  if (c->pflow) {
+    for (int ax = 0; ax < c->nspace; ++ax) {
+      std::vector<double> lam;
+      Mat W;
+      jacobi_eigh(S.A[c->axes[ax]], lam, W);
+      o_wd[ax] = dalloc((size_t)n * n);
+      o_lamd[ax] = dalloc(n);
+      for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k) dv[o_wd[ax] + (size_t)j * n + k] = W(j, k);
+      for (int k = 0; k < n; ++k) dv[o_lamd[ax] + k] = lam[k];
+    }
+  }
+
   // uniform-axis face matrices beta^a = U_a + V A^a and |beta^a| (no ln p axis)
   size_t o_fb[3] = {0, 0, 0}, o_fa[3] = {0, 0, 0}, o_fbv[3] = {0, 0, 0}, o_fav[3] = {0, 0, 0};
   int nfb[3] = {0, 0, 0}, nfa[3] = {0, 0, 0};
   const bool adv = c->terms & VFP_TERM_ADVECTION;
   for (int ax = 0; ax < c->nspace; ++ax) {
+    if (c->pflow) break;
     if (ax == 0 && c->planar) continue;
     if (c->mom) break;  // with a ln p axis only the profiled x axis is spatial
     const int comp = c->axes[ax];
@@ -495,6 +526,8 @@ int build_row_tables(vfp_ctx* c) {
   T.rot_val = db + c->o_rot[1];
   T.nrot = nrot;
   for (int ax = 0; ax < 3; ++ax) {
+    T.wd[ax] = (c->pflow && ax < c->nspace) ? db + o_wd[ax] : nullptr;
+    T.lamd[ax] = (c->pflow && ax < c->nspace) ? db + o_lamd[ax] : nullptr;
     T.nfb[ax] = nfb[ax];
     T.nfa[ax] = nfa[ax];
     T.fb_col[ax] = nfb[ax] ? ib + o_fb[ax] : nullptr;
@@ -891,6 +924,9 @@ int refresh(vfp_ctx* c, unsigned what) {
   F.B_pts = c->have_Bpts ? c->d_Bpts.as<double>() : nullptr;
   F.nu0 = c->nu0;
   F.nu_cell = c->have_nu_cell ? c->d_nu.as<double>() : nullptr;
+  F.nu_pts = c->have_nu_pts ? c->d_nu_pts.as<double>() : nullptr;
+  F.u_pts = c->pflow ? c->d_u_pts.as<double>() : nullptr;
+  for (int a = 0; a < 3; ++a) F.uf_pts[a] = c->pflow ? c->d_uf_pts[a].as<double>() : nullptr;
   F.src = c->have_src ? c->d_src.as<double>() : nullptr;
   F.t_adv = (c->terms & VFP_TERM_ADVECTION) ? 1.0 : 0.0;
   F.t_mom = (c->terms & VFP_TERM_MOMENTUM) ? 1.0 : 0.0;
@@ -903,16 +939,34 @@ int refresh(vfp_ctx* c, unsigned what) {
   }
   c->launcher = nullptr;
   c->shock = false;
-  const bool shock_ok = c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->force_general;
+  const bool shock_ok = c->naxes == 2 && c->mom && c->planar && !c->have_Bpts && !c->have_nu_pts &&
+                        !c->force_general;
   if (shock_ok) {
-    c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot, c->linp);
+    if (c->shape && !c->linp) c->launcher = find_shock_launcher_shape(c->k, c->lmax, c->tab.nrot, c->shape);
+    if (!c->launcher) {
+      c->shape = 0;
+      c->launcher = find_shock_launcher(c->k, c->lmax, c->tab.nrot, c->linp);
+    }
     c->shock = c->launcher != nullptr;
   }
-  if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
+  const int flow = c->pflow ? 2 : (c->planar ? 1 : 0);
+  if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, flow);
   c->adj_launcher = nullptr;
   if (shock_ok) c->adj_launcher = find_shock_adjoint_launcher(c->k, c->lmax, c->tab.nrot, c->linp);
-  if (!c->adj_launcher) c->adj_launcher = find_adjoint_launcher(c->naxes, c->k, c->lmax, c->mom, c->planar);
+  if (!c->adj_launcher) c->adj_launcher = find_adjoint_launcher(c->naxes, c->k, c->lmax, c->mom, flow);
   c->mass_launcher = find_mass_launcher(c->naxes, c->k);
+  // a small run on one axis with constant coefficients (uniform flow, fixed
+  // p, uniform B, nu per cell) steps inside one workgroup (VFP_RESIDENT=0
+  // turns this off)
+  c->resident = nullptr;
+  {
+    const char* rv = std::getenv("VFP_RESIDENT");
+    const bool allow = !(rv && std::atoi(rv) == 0);
+    const size_t lds = (size_t)3 * c->ncells * c->nb * c->n * sizeof(double);
+    if (allow && c->naxes == 1 && !c->mom && !c->planar && !c->pflow && !c->have_Bpts && !c->have_nu_pts &&
+        c->lmax <= kShFullMaxLmax && lds <= resident_max_lds())
+      c->resident = find_resident_launcher(c->k, c->lmax);
+  }
   return VFP_OK;
 }
 
@@ -921,8 +975,9 @@ int check_ready(const vfp_ctx* c) {
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
   if (!c->mom && !(c->p_fixed > 0)) return fail(VFP_ESTATE, "vfp_set_momentum has not been called");
   if (c->mom && !c->planar) return fail(VFP_ESTATE, "a ln p axis needs vfp_set_flow_planar (a constant profile for uniform flow)");
-  if (!c->launcher) return fail(VFP_EUNSUPPORTED, "no kernel built for naxes=%d k=%d lmax=%d lnp=%d planar=%d",
-                                c->naxes, c->k, c->lmax, (int)c->mom, (int)c->planar);
+  if (!c->launcher)
+    return fail(VFP_EUNSUPPORTED, "no kernel built for naxes=%d k=%d lmax=%d lnp=%d planar=%d point flow=%d",
+                c->naxes, c->k, c->lmax, (int)c->mom, (int)c->planar, (int)c->pflow);
   return VFP_OK;
 }
 
@@ -962,6 +1017,9 @@ int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
   if (nsp == 0) return fail(VFP_EINVAL, "at least one spatial axis is required");
   if ((naxes == 3 && k > 2) || (naxes == 2 && k > 3))
     return fail(VFP_EUNSUPPORTED, "k=%d is built for at most %d axes", k, k > 3 ? 1 : 2);
+  if (lmax > kShFullMaxLmax && (naxes != 1 || mom || k > 2))
+    return fail(VFP_EUNSUPPORTED, "l_max > %d is built for one spatial axis (x) at fixed p with k <= 2",
+                kShFullMaxLmax);
   vfp_ctx* c = new (std::nothrow) vfp_ctx();
   if (!c) return fail(VFP_ENOMEM, "context allocation");
   c->lmax = lmax;
@@ -985,6 +1043,8 @@ int vfp_create(vfp_ctx** out, int lmax, int k, int naxes, const int* axis_kinds,
     c->force_general = kv && std::strcmp(kv, "general") == 0;
     const char* tm = std::getenv("VFP_TILE_MAP");
     c->tile_map = tm ? (std::atoi(tm) != 0) : 0;
+    const char* sh = std::getenv("VFP_SHOCK_SHAPE");   // initial workgroup shape slot (tests)
+    c->shape = sh ? std::max(0, std::min(kShockShapes - 1, std::atoi(sh))) : 0;
   }
   c->S = build_sh_matrices(lmax);
   {
@@ -1002,6 +1062,7 @@ void vfp_destroy(vfp_ctx* c) { delete c; }
 int vfp_set_mesh(vfp_ctx* c, const int* ncells, const double* const* nodes, const int* bc_lo,
                  const int* bc_hi) {
   if (!c || !ncells || !nodes || !bc_lo || !bc_hi) return fail(VFP_EINVAL, "null argument");
+  ++c->gen;
   long long tot = 1;
   for (int a = 0; a < c->naxes; ++a) {
     if (ncells[a] < 1) return fail(VFP_EINVAL, "ncells[%d]=%d", a, ncells[a]);
@@ -1031,7 +1092,9 @@ int vfp_set_mesh(vfp_ctx* c, const int* ncells, const double* const* nodes, cons
   // reset fields
   c->planar = false;
   for (int i = 0; i < 3; ++i) c->U[i] = c->B[i] = 0.0;
-  c->have_Bpts = c->have_nu_cell = c->have_src = false;
+  c->have_Bpts = c->have_nu_cell = c->have_nu_pts = c->have_src = false;
+  c->pflow = false;
+  c->d_fg_support.release();
   c->nu0 = 0.0;
   c->u_vol.assign(c->ncell[0] * c->K1, 0.0);
   c->du_vol = c->a_vol = c->u_vol;
@@ -1064,6 +1127,7 @@ int vfp_set_mesh(vfp_ctx* c, const int* ncells, const double* const* nodes, cons
 
 int vfp_set_momentum(vfp_ctx* c, double p) {
   if (!c) return fail(VFP_EINVAL, "null context");
+  ++c->gen;
   if (c->mom) return fail(VFP_EINVAL, "context has a ln p axis; momentum is a coordinate");
   if (!(p > 0) || !std::isfinite(p)) return fail(VFP_EINVAL, "p=%g must be positive", p);
   c->p_fixed = p;
@@ -1094,10 +1158,12 @@ int vfp_query_points(const vfp_ctx* c, int which, int axis, double* coords, int6
 
 int vfp_set_flow_uniform(vfp_ctx* c, const double* U) {
   if (!c || !U) return fail(VFP_EINVAL, "null argument");
+  ++c->gen;
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
   for (int i = 0; i < 3; ++i)
     if (!std::isfinite(U[i])) return fail(VFP_EINVAL, "U not finite");
   for (int i = 0; i < 3; ++i) c->U[i] = U[i];
+  c->pflow = false;
   if (c->mom) {
     // stored as a constant x profile (grad U = 0, dU/dt = 0)
     std::fill(c->u_vol.begin(), c->u_vol.end(), U[0]);
@@ -1117,6 +1183,7 @@ int vfp_set_flow_uniform(vfp_ctx* c, const double* U) {
 int vfp_set_flow_planar(vfp_ctx* c, const double* u, const double* dudx, const double* dudt,
                         const double* u_face) {
   if (!c || !u || !dudx || !dudt || !u_face) return fail(VFP_EINVAL, "null argument");
+  ++c->gen;
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
   if (c->axes[0] != VFP_AXIS_X) return fail(VFP_EINVAL, "planar flow needs axis 0 = x");
   const int nq = c->ncell[0] * c->K1;
@@ -1129,6 +1196,7 @@ int vfp_set_flow_planar(vfp_ctx* c, const double* u, const double* dudx, const d
   c->u_face.assign(u_face, u_face + c->ncell[0] + 1);
   c->U[0] = 0.0;
   c->planar = true;
+  c->pflow = false;
   if (int e = upload_vec(c->d_u_vol, c->u_vol)) return e;
   if (int e = upload_vec(c->d_du_vol, c->du_vol)) return e;
   if (int e = upload_vec(c->d_a_vol, c->a_vol)) return e;
@@ -1138,7 +1206,10 @@ int vfp_set_flow_planar(vfp_ctx* c, const double* u, const double* dudx, const d
 
 int vfp_set_magnetic_uniform(vfp_ctx* c, const double* B) {
   if (!c || !B) return fail(VFP_EINVAL, "null argument");
+  ++c->gen;
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  if (c->lmax > kShFullMaxLmax && (B[1] != 0.0 || B[2] != 0.0))
+    return fail(VFP_EUNSUPPORTED, "l_max > %d: B must lie along x", kShFullMaxLmax);
   for (int i = 0; i < 3; ++i) c->B[i] = B[i];
   c->have_Bpts = false;
   return refresh(c, R_TAB);
@@ -1146,8 +1217,9 @@ int vfp_set_magnetic_uniform(vfp_ctx* c, const double* B) {
 
 int vfp_set_magnetic_points(vfp_ctx* c, const double* B) {
   if (!c || !B) return fail(VFP_EINVAL, "null argument");
+  ++c->gen;
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
-  if (c->mom) return fail(VFP_EUNSUPPORTED, "point-wise B with a ln p axis");
+  if (c->lmax > kShFullMaxLmax) return fail(VFP_EUNSUPPORTED, "l_max > %d: B must be uniform along x", kShFullMaxLmax);
   if (int e = upload(c->d_Bpts, B, (size_t)c->ncells * c->nb * 3 * sizeof(double))) return e;
   c->have_Bpts = true;
   for (int i = 0; i < 3; ++i) c->B[i] = 0.0;
@@ -1156,6 +1228,7 @@ int vfp_set_magnetic_points(vfp_ctx* c, const double* B) {
 
 int vfp_set_scattering(vfp_ctx* c, double nu, const double* nu_cell) {
   if (!c) return fail(VFP_EINVAL, "null context");
+  ++c->gen;
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
   if (nu_cell) {
     for (int i = 0; i < c->ncells; ++i)
@@ -1173,7 +1246,9 @@ int vfp_set_scattering(vfp_ctx* c, double nu, const double* nu_cell) {
     c->nu0 = nu;
     c->have_nu_cell = false;
   }
-  if (c->launcher) {
+  const bool had_pts = c->have_nu_pts;
+  c->have_nu_pts = false;
+  if (c->launcher && !had_pts) {
     // only the scattering fields change: no table rebuild
     c->fld.nu0 = c->nu0;
     c->fld.nu_cell = c->have_nu_cell ? c->d_nu.as<double>() : nullptr;
@@ -1182,8 +1257,91 @@ int vfp_set_scattering(vfp_ctx* c, double nu, const double* nu_cell) {
   return refresh(c, 0);
 }
 
+int vfp_set_scattering_points(vfp_ctx* c, const double* nu) {
+  if (!c || !nu) return fail(VFP_EINVAL, "null argument");
+  ++c->gen;
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  const size_t cnt = (size_t)c->ncells * c->nb;
+  for (size_t i = 0; i < cnt; ++i)
+    if (!std::isfinite(nu[i])) return fail(VFP_EINVAL, "nu[%zu] not finite", i);
+  if (int e = upload(c->d_nu_pts, nu, cnt * sizeof(double))) return e;
+  c->have_nu_pts = true;
+  c->have_nu_cell = false;
+  c->nu0 = 0.0;
+  return refresh(c, 0);
+}
+
+int vfp_set_flow_points(vfp_ctx* c, const double* U, const double* gradU, const double* const* U_face) {
+  if (!c || !U || !gradU || !U_face) return fail(VFP_EINVAL, "null argument");
+  ++c->gen;
+  if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
+  if (c->mom)
+    return fail(VFP_EUNSUPPORTED, "flow at the points with a momentum axis (use vfp_set_flow_planar)");
+  if (c->terms & VFP_TERM_MOMENTUM)
+    return fail(VFP_EUNSUPPORTED, "the flow-gradient terms of R need a momentum axis and a planar flow");
+  if (c->k > 2) return fail(VFP_EUNSUPPORTED, "flow at the points is built for k <= 2");
+  const int nb = c->nb, K1 = c->K1, D = c->naxes;
+  const size_t nq = (size_t)c->ncells * nb;
+  std::vector<double> up(nq * 4);
+  for (size_t i = 0; i < nq; ++i) {
+    double div = 0.0;
+    for (int a = 0; a < D; ++a) div += gradU[i * 9 + 4 * c->axes[a]];   // dU_a/dx^a
+    for (int b = 0; b < 3; ++b) up[i * 4 + b] = U[i * 3 + b];
+    up[i * 4 + 3] = div;
+    for (int b = 0; b < 4; ++b)
+      if (!std::isfinite(up[i * 4 + b])) return fail(VFP_EINVAL, "flow not finite at volume point %zu", i);
+  }
+  double umax[3] = {0, 0, 0};
+  for (size_t i = 0; i < nq; ++i)
+    for (int a = 0; a < D; ++a) umax[a] = std::max(umax[a], std::fabs(U[i * 3 + c->axes[a]]));
+  std::vector<double> uf[3];
+  for (int a = 0; a < D; ++a) {
+    if (!U_face[a]) return fail(VFP_EINVAL, "U_face[%d] is null", a);
+    size_t nf = 1;
+    for (int b = 0; b < D; ++b) nf *= (size_t)(c->ncell[b] + (b == a ? 1 : 0));
+    size_t nqf = 1;
+    for (int b = 0; b < D - 1; ++b) nqf *= K1;
+    uf[a].resize(nf * nqf);
+    for (size_t i = 0; i < nf * nqf; ++i) {
+      const double v = U_face[a][i * 3 + c->axes[a]];
+      if (!std::isfinite(v)) return fail(VFP_EINVAL, "flow not finite at face point %zu of axis %d", i, a);
+      uf[a][i] = v;
+      umax[a] = std::max(umax[a], std::fabs(v));
+    }
+    if (c->bc_lo[a] == VFP_BC_PERIODIC) {
+      // the wrap-around face is one face: both ends must carry the same flow
+      size_t stride = 1;
+      for (int b = 0; b < a; ++b) stride *= (size_t)c->ncell[b];
+      const size_t na = (size_t)c->ncell[a];
+      for (size_t f = 0; f < nf; ++f) {
+        if ((f / stride) % (na + 1) != 0) continue;
+        const size_t g = f + na * stride;
+        for (size_t q = 0; q < nqf; ++q) {
+          const double v0 = uf[a][f * nqf + q], v1 = uf[a][g * nqf + q];
+          if (std::fabs(v0 - v1) > 1e-12 * std::max(1.0, std::fabs(v0)))
+            return fail(VFP_EINVAL, "axis %d is periodic but the flow differs at its two ends (%g vs %g)", a, v0, v1);
+        }
+      }
+    }
+  }
+  if (int e = upload_vec(c->d_u_pts, up)) return e;
+  for (int a = 0; a < 3; ++a) {
+    if (a < D) {
+      if (int e = upload_vec(c->d_uf_pts[a], uf[a])) return e;
+    } else {
+      c->d_uf_pts[a].release();
+    }
+    c->pflow_umax[a] = a < D ? umax[a] : 0.0;
+  }
+  for (int i = 0; i < 3; ++i) c->U[i] = 0.0;
+  c->planar = false;
+  c->pflow = true;
+  return refresh(c, R_TAB);
+}
+
 int vfp_set_source_points(vfp_ctx* c, const double* s) {
   if (!c || !s) return fail(VFP_EINVAL, "null argument");
+  ++c->gen;
   if (!c->mesh_set) return fail(VFP_ESTATE, "vfp_set_mesh has not been called");
   // M^{-1} h per cell: the 000 component of the test contraction of
   // s_000 = sqrt(4 pi) s (the Jacobian cancels against M^{-1})
@@ -1232,7 +1390,7 @@ int vfp_cfl_dt(const vfp_ctx* c, double courant, double* dt) {
     if (c->mom && a == c->naxes - 1) {
       bmax = c->beta_pmax;
     } else if (adv) {
-      double umax = std::fabs(c->U[c->axes[a]]);
+      double umax = c->pflow ? c->pflow_umax[a] : std::fabs(c->U[c->axes[a]]);
       if (a == 0 && c->planar) {
         for (double v : c->u_vol) umax = std::max(umax, std::fabs(v));
         for (double v : c->u_face) umax = std::max(umax, std::fabs(v));
@@ -1280,6 +1438,64 @@ static int launch(vfp_ctx* c, const double* w_in, const double* u, double* w_out
   return VFP_OK;
 }
 
+int vfp_autotune(vfp_ctx* c, const double* u, double* work, int reps, int* chosen, void* stream) {
+  if (int e = check_ready(c)) return e;
+  if (!u || !work) return fail(VFP_EINVAL, "null state pointer");
+  int64_t N = 0;
+  vfp_ndofs(c, &N);
+  if (overlaps(u, N, work, N)) return fail(VFP_EINVAL, "work overlaps u");
+  if (reps < 1) reps = 3;
+  if (c->shock && !c->linp) {
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+      (void)hipEventDestroy(e0);
+      return fail(VFP_EDEVICE, "hipEventCreate");
+    }
+    float best = 1e30f;
+    int bs = c->shape, bt = c->tile_map;
+    int rc = VFP_OK;
+    for (int shape = 0; shape < kShockShapes && rc == VFP_OK; ++shape) {
+      StageLauncher L = shape ? find_shock_launcher_shape(c->k, c->lmax, c->tab.nrot, shape)
+                              : find_shock_launcher(c->k, c->lmax, c->tab.nrot, false);
+      if (!L) continue;
+      c->launcher = L;
+      for (int tm : {0, 1}) {
+        c->tile_map = tm;
+        // stage-1 form: reads u, writes work; u is unchanged
+        if ((rc = launch(c, u, u, work, 1.0, 1e-3, 1, stream))) break;
+        if (hipEventRecord(e0, (hipStream_t)stream) != hipSuccess) { rc = fail(VFP_EDEVICE, "event"); break; }
+        for (int i = 0; i < reps && rc == VFP_OK; ++i) rc = launch(c, u, u, work, 1.0, 1e-3, 1, stream);
+        if (rc) break;
+        float ms = 0.f;
+        if (hipEventRecord(e1, (hipStream_t)stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+          rc = fail(VFP_EDEVICE, "timing events");
+          break;
+        }
+        if (ms < best) {
+          best = ms;
+          bs = shape;
+          bt = tm;
+        }
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    c->shape = bs;
+    c->tile_map = bt;
+    c->launcher = bs ? find_shock_launcher_shape(c->k, c->lmax, c->tab.nrot, bs)
+                     : find_shock_launcher(c->k, c->lmax, c->tab.nrot, false);
+    if (rc) return rc;
+  }
+  if (chosen) {
+    chosen[0] = c->shock ? c->shape : 0;
+    chosen[1] = c->shock ? shock_shape_threads(c->lmax, c->shape) : stage_threads_general();
+    chosen[2] = c->shock ? c->tile_map : 0;
+  }
+  return VFP_OK;
+}
+
 int vfp_apply(vfp_ctx* c, const double* in, double* out, int with_source, void* stream) {
   if (int e = check_ready(c)) return e;
   if (!in || !out) return fail(VFP_EINVAL, "null state pointer");
@@ -1310,6 +1526,17 @@ int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, 
   double* wb = work + N;
   if ((u >= work && u < work + 2 * N) || (work >= u && work < u + N))
     return fail(VFP_EINVAL, "work overlaps u");
+  if (c->resident) {
+    if (nsteps == 0) return VFP_OK;
+    KernelArgs a{};
+    a.mesh = c->meshargs;
+    a.fld = c->fld;
+    a.tab = c->tab;
+    a.st.with_source = (c->terms & VFP_TERM_SOURCE) ? 1 : 0;
+    c->resident(a, dt, (long long)nsteps, u, (hipStream_t)stream);
+    HIP_TRY(hipGetLastError());
+    return VFP_OK;
+  }
   for (int64_t s = 0; s < nsteps; ++s) {
     if (int e = launch(c, u, u, wa, 1.0, stage_cdt(0, dt), 1, stream)) return e;
     if (int e = launch(c, wa, u, wb, 1.0, stage_cdt(1, dt), 1, stream)) return e;
@@ -1379,6 +1606,7 @@ int vfp_adjoint_stage(vfp_ctx* c, const double* mu_in, const double* acc_in, con
   if (!mu_in || !acc_in || !acc_out) return fail(VFP_EINVAL, "null state pointer");
   if (!std::isfinite(cdt)) return fail(VFP_EINVAL, "cdt not finite");
   if (grad_nu && !fwd) return fail(VFP_EINVAL, "grad_nu needs the forward stage input fwd");
+  if (grad_nu && c->have_nu_pts) return fail(VFP_EUNSUPPORTED, "dJ/dnu per cell with nu given at the points");
   int64_t N = 0;
   vfp_ndofs(c, &N);
   if (overlaps(acc_out, N, mu_in, N) || overlaps(t_out, N, mu_in, N) || overlaps(t_out, N, acc_in, N) ||
@@ -1422,9 +1650,23 @@ static int launch_fg(vfp_ctx* c, const double* mu, const double* fwd, double cdt
   a.mesh = c->meshargs;
   a.fld = c->fld;
   a.tab = c->tab;
-  fl(a, mu, fwd, cdt, slots, (hipStream_t)stream);
+  fl(a, mu, fwd, cdt, slots, c->d_fg_support.as<unsigned char>(), (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return VFP_OK;
+}
+
+int vfp_field_grad_support(vfp_ctx* c, const unsigned char* xcells) {
+  if (!c) return fail(VFP_EINVAL, "null context");
+  ++c->gen;
+  if (int e = check_ready(c)) return e;
+  if (int e = field_grad_ready(c)) return e;
+  if (!xcells) {
+    c->d_fg_support.release();
+    return VFP_OK;
+  }
+  std::vector<unsigned char> m(xcells, xcells + c->ncell[0]);
+  for (auto& v : m) v = v ? 1 : 0;
+  return upload_vec(c->d_fg_support, m);
 }
 
 int vfp_field_grad_size(const vfp_ctx* c, int64_t* n) {
@@ -1472,6 +1714,7 @@ int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double d
     return fail(VFP_EINVAL, "work / mu overlap the tape or each other");
   if (grad_nu && (overlaps(grad_nu, c->ncells, work, 3 * N) || overlaps(grad_nu, c->ncells, mu, N)))
     return fail(VFP_EINVAL, "grad_nu overlaps a state buffer");
+  if (grad_nu && c->have_nu_pts) return fail(VFP_EUNSUPPORTED, "dJ/dnu per cell with nu given at the points");
   if (field_slots) {
     if (int e = field_grad_ready(c)) return e;
     int64_t ns = 0;
@@ -1731,7 +1974,7 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
 extern "C" {
 
 int vfp_sh_eval(int lmax, int64_t ndir, const double* theta, const double* phi, double* Y) {
-  if (lmax < 0 || lmax > 7) return fail(VFP_EINVAL, "lmax must be in 0..7");
+  if (lmax < 0 || lmax > kMaxLmax) return fail(VFP_EINVAL, "lmax must be in 0..%d", kMaxLmax);
   if (ndir < 0 || (ndir > 0 && (!theta || !phi || !Y))) return fail(VFP_EINVAL, "bad direction arrays");
   const int n = (lmax + 1) * (lmax + 1);
   for (int64_t d = 0; d < ndir; ++d) real_sh_dir(lmax, theta[d], phi[d], Y + d * n);
@@ -1773,6 +2016,8 @@ int vfp_theta_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, const vf
   if (!(o->tol > 0.0)) return fail(VFP_EINVAL, "tol must be positive");
   if (o->restart < 1 || o->restart > 64) return fail(VFP_EINVAL, "restart must be in 1..64");
   if (o->max_iters < 1) return fail(VFP_EINVAL, "max_iters must be >= 1");
+  if (o->precond == VFP_PRECOND_COLLISION && c->have_nu_pts)
+    return fail(VFP_EUNSUPPORTED, "the collision preconditioner needs nu per cell (not at the points)");
   if (o->precond != VFP_PRECOND_NONE && o->precond != VFP_PRECOND_COLLISION)
     return fail(VFP_EINVAL, "precond %d unknown", o->precond);
   if (nsteps < 0 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps");
@@ -1828,11 +2073,13 @@ struct vfp_batch {
     DevBuf tile_run;                   // run (member index) of every tile
     int total = 0;                     // tiles = workgroups per launch
     int tile_map = 0;                  // tuned
+    int shape = 0;                     // tuned workgroup shape slot
   };
   std::vector<vfp_ctx*> runs;
   std::vector<Class> classes;
   std::vector<double*> u, work;
   std::vector<double> dt;
+  std::vector<uint64_t> gen;           // each run's set-up generation at vfp_batch_bind
   bool bound = false;
   bool use_graph = false;
   int device = -1;
@@ -1940,6 +2187,34 @@ int batch_step_branched(vfp_batch* b, hipStream_t st) {
   return VFP_OK;
 }
 
+// Tile tables of a batched class for its current kernel (cells per tile):
+// the first tile of every member and the member of every tile.
+int class_tiles(vfp_batch* b, vfp_batch::Class& cl) {
+  std::vector<int> st(cl.members.size() + 1, 0);
+  long long tot = 0;
+  for (size_t j = 0; j < cl.members.size(); ++j) {
+    st[j] = (int)tot;
+    tot += (b->runs[cl.members[j]]->ncells + cl.bk.cells_per_tile - 1) / cl.bk.cells_per_tile;
+    if (tot > (1LL << 30)) return fail(VFP_EINVAL, "batch too large (%lld tiles)", tot);
+  }
+  st.back() = (int)tot;
+  cl.total = (int)tot;
+  std::vector<int> tr((size_t)tot);
+  for (size_t j = 0; j < cl.members.size(); ++j) std::fill(tr.begin() + st[j], tr.begin() + st[j + 1], (int)j);
+  if (int e = upload_vec(cl.start, st)) return e;
+  return upload_vec(cl.tile_run, tr);
+}
+
+// The per-run stage descriptors copy field pointers and values at bind time;
+// a set-up call on a run afterwards may free or change them.
+int check_bound_current(const vfp_batch* b) {
+  if (!b->bound) return fail(VFP_ESTATE, "vfp_batch_bind has not been called");
+  for (size_t r = 0; r < b->runs.size(); ++r)
+    if (b->runs[r]->gen != b->gen[r])
+      return fail(VFP_ESTATE, "run %zu was set up again after vfp_batch_bind; bind again", r);
+  return VFP_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1995,26 +2270,7 @@ int vfp_batch_create(vfp_batch** out, vfp_ctx* const* runs, int nruns, unsigned 
   }
   for (auto& cl : b->classes) {
     if (!cl.batched) continue;
-    std::vector<int> st(cl.members.size() + 1, 0);
-    long long tot = 0;
-    for (size_t j = 0; j < cl.members.size(); ++j) {
-      st[j] = (int)tot;
-      tot += (runs[cl.members[j]]->ncells + cl.bk.cells_per_tile - 1) / cl.bk.cells_per_tile;
-      if (tot > (1LL << 30)) {
-        delete b;
-        return fail(VFP_EINVAL, "batch too large (%lld tiles)", tot);
-      }
-    }
-    st.back() = (int)tot;
-    cl.total = (int)tot;
-    std::vector<int> tr((size_t)tot);
-    for (size_t j = 0; j < cl.members.size(); ++j)
-      std::fill(tr.begin() + st[j], tr.begin() + st[j + 1], (int)j);
-    if (int e = upload_vec(cl.start, st)) {
-      delete b;
-      return e;
-    }
-    if (int e = upload_vec(cl.tile_run, tr)) {
+    if (int e = class_tiles(b, cl)) {
       delete b;
       return e;
     }
@@ -2038,6 +2294,8 @@ int vfp_batch_bind(vfp_batch* b, double* const* u, double* const* work, const do
   b->u.assign(u, u + nr);
   b->work.assign(work, work + nr);
   b->dt.assign(dt, dt + nr);
+  b->gen.resize(nr);
+  for (int r = 0; r < nr; ++r) b->gen[r] = b->runs[r]->gen;
   for (auto& cl : b->classes) {
     if (!cl.batched) continue;
     const size_t m = cl.members.size();
@@ -2063,7 +2321,7 @@ int vfp_batch_bind(vfp_batch* b, double* const* u, double* const* work, const do
 
 int vfp_batch_advance(vfp_batch* b, int64_t nsteps, void* stream) {
   if (!b) return fail(VFP_EINVAL, "null batch");
-  if (!b->bound) return fail(VFP_ESTATE, "vfp_batch_bind has not been called");
+  if (int e = check_bound_current(b)) return e;
   if (nsteps < 0) return fail(VFP_EINVAL, "nsteps < 0");
   hipStream_t st = (hipStream_t)stream;
   if (!b->use_graph) {
@@ -2107,33 +2365,45 @@ int vfp_batch_advance(vfp_batch* b, int64_t nsteps, void* stream) {
   return VFP_OK;
 }
 
+// Times every workgroup shape (cells per tile and lanes per workgroup) and
+// both tile orders of a class's batched kernel and keeps the fastest.
 static int tune_class(vfp_batch* b, vfp_batch::Class& cl, int reps, hipStream_t st, hipEvent_t e0,
                       hipEvent_t e1) {
   float best = 1e30f;
-  int bt = cl.tile_map;
-  for (int tm : {0, 1}) {
-    cl.tile_map = tm;
-    // stage 1 form (reads u, writes the first work vector): u is untouched
-    if (int e = batch_launch_stage(b, cl, 0, st)) return e;
-    HIP_TRY(hipEventRecord(e0, st));
-    for (int i = 0; i < reps; ++i)
+  int bt = cl.tile_map, bs = cl.shape;
+  for (int shape = 0; shape < kShockShapes; ++shape) {
+    BatchKernel bk = find_shock_batch_kernel(cl.k, cl.lmax, cl.nrot, shape);
+    if (!bk.launch) continue;
+    cl.bk = bk;
+    cl.shape = shape;
+    if (int e = class_tiles(b, cl)) return e;
+    for (int tm : {0, 1}) {
+      cl.tile_map = tm;
+      // stage 1 form (reads u, writes the first work vector): u is untouched
       if (int e = batch_launch_stage(b, cl, 0, st)) return e;
-    HIP_TRY(hipEventRecord(e1, st));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    if (ms < best) {
-      best = ms;
-      bt = tm;
+      HIP_TRY(hipEventRecord(e0, st));
+      for (int i = 0; i < reps; ++i)
+        if (int e = batch_launch_stage(b, cl, 0, st)) return e;
+      HIP_TRY(hipEventRecord(e1, st));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        bt = tm;
+        bs = shape;
+      }
     }
   }
   cl.tile_map = bt;
-  return VFP_OK;
+  cl.shape = bs;
+  cl.bk = find_shock_batch_kernel(cl.k, cl.lmax, cl.nrot, bs);
+  return class_tiles(b, cl);
 }
 
 int vfp_batch_autotune(vfp_batch* b, int reps, void* stream) {
   if (!b) return fail(VFP_EINVAL, "null batch");
-  if (!b->bound) return fail(VFP_ESTATE, "vfp_batch_bind has not been called");
+  if (int e = check_bound_current(b)) return e;
   if (reps < 1) reps = 3;
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
@@ -2164,7 +2434,7 @@ int vfp_batch_class_info(const vfp_batch* b, int i, int* info) {
   info[3] = (int)cl.members.size();
   info[4] = cl.batched ? 1 : 0;
   info[5] = cl.total;
-  info[6] = cl.total;
+  info[6] = cl.batched ? cl.bk.threads : 0;
   info[7] = cl.tile_map;
   return VFP_OK;
 }

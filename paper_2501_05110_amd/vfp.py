@@ -62,12 +62,15 @@ def load(path: str = None):
         "vfp_query_points": (I, [P, I, I, dp, C.POINTER(L)]),
         "vfp_set_flow_uniform": (I, [P, dp]),
         "vfp_set_flow_planar": (I, [P, dp, dp, dp, dp]),
+        "vfp_set_flow_points": (I, [P, dp, dp, C.POINTER(dp)]),
         "vfp_set_magnetic_uniform": (I, [P, dp]),
         "vfp_set_magnetic_points": (I, [P, dp]),
         "vfp_set_scattering": (I, [P, D, dp]),
+        "vfp_set_scattering_points": (I, [P, dp]),
         "vfp_set_source_points": (I, [P, dp]),
         "vfp_ndofs": (I, [P, C.POINTER(L)]),
         "vfp_cfl_dt": (I, [P, D, dp]),
+        "vfp_autotune": (I, [P, P, P, I, C.POINTER(I), P]),
         "vfp_apply": (I, [P, P, P, I, P]),
         "vfp_stage": (I, [P, P, P, P, D, P]),
         "vfp_advance": (I, [P, P, D, L, P, P]),
@@ -80,6 +83,7 @@ def load(path: str = None):
         "vfp_forward_checkpoints": (I, [P, P, D, L, L, P, P, P]),
         "vfp_adjoint_checkpointed": (I, [P, P, D, L, L, P, P, P, P, P, P]),
         "vfp_field_grad_size": (I, [P, C.POINTER(L)]),
+        "vfp_field_grad_support": (I, [P, C.POINTER(C.c_ubyte)]),
         "vfp_field_grad_stage": (I, [P, P, P, D, P, P]),
         "vfp_field_grad_reduce": (I, [P, P, P, P, P, P, P]),
         "vfp_sh_eval": (I, [I, L, dp, dp, dp]),
@@ -104,14 +108,15 @@ def load(path: str = None):
 
 def exported_symbols():
     return ["vfp_last_error", "vfp_create", "vfp_destroy", "vfp_set_mesh", "vfp_set_momentum",
-            "vfp_query_points", "vfp_set_flow_uniform", "vfp_set_flow_planar",
+            "vfp_query_points", "vfp_set_flow_uniform", "vfp_set_flow_planar", "vfp_set_flow_points",
             "vfp_set_magnetic_uniform", "vfp_set_magnetic_points", "vfp_set_scattering",
-            "vfp_set_source_points", "vfp_ndofs", "vfp_cfl_dt", "vfp_apply", "vfp_stage",
+            "vfp_set_scattering_points",
+            "vfp_set_source_points", "vfp_ndofs", "vfp_cfl_dt", "vfp_autotune", "vfp_apply", "vfp_stage",
             "vfp_advance", "vfp_mass", "vfp_apply_adjoint", "vfp_apply_adjoint_noalloc", "vfp_adjoint_stage", "vfp_advance_tape",
             "vfp_adjoint_steps", "vfp_forward_checkpoints", "vfp_adjoint_checkpointed",
             "vfp_batch_create", "vfp_batch_destroy", "vfp_batch_bind", "vfp_batch_advance",
             "vfp_batch_autotune", "vfp_batch_nclasses", "vfp_batch_class_info",
-            "vfp_field_grad_size", "vfp_field_grad_stage", "vfp_field_grad_reduce",
+            "vfp_field_grad_size", "vfp_field_grad_support", "vfp_field_grad_stage", "vfp_field_grad_reduce",
             "vfp_theta_work_size", "vfp_theta_advance", "vfp_sh_eval", "vfp_reconstruct"]
 
 
@@ -194,6 +199,32 @@ class Operator:
                 X[AXIS[name]] = v
         return X, p
 
+    def face_points(self, axis):
+        """Spatial coordinates X (3, nfaces*nqf) of the Gauss points of the
+        faces normal to `axis`, ordered [face][qf]: faces over (N_axis + 1)
+        positions on that axis and N_b cells on the others (axis 0 fastest),
+        qf over the other axes' Gauss points (first other axis fastest)."""
+        wl = self.wl
+        d = len(wl.axes)
+        K1 = wl.k + 1
+        ncx = list(wl.ncells_axis)
+        ext = [ncx[b] + (1 if b == axis else 0) for b in range(d)]
+        f_idx = np.indices(ext[::-1]).reshape(d, -1)[::-1]          # (d, nfaces), axis 0 fastest
+        others = [b for b in range(d) if b != axis]
+        q_idx = (np.indices((K1,) * len(others)).reshape(len(others), -1)[::-1]
+                 if others else np.zeros((0, 1), int))
+        nf, nqf = f_idx.shape[1], q_idx.shape[1]
+        X = np.zeros((3, nf * nqf))
+        for b, name in enumerate(wl.axes):
+            if b == axis:
+                v = np.repeat(self.points(PTS_FACE, b)[f_idx[b]], nqf)
+            else:
+                t = others.index(b)
+                vol = self.points(PTS_VOLUME, b).reshape(ncx[b], K1)
+                v = vol[f_idx[b][:, None], q_idx[t][None, :]].ravel()
+            X[AXIS[name]] = v
+        return X
+
     def _set_fields(self):
         wl, lib, ctx = self.wl, _lib, self._ctx
         kind = getattr(wl.flow, "kind", None)
@@ -213,6 +244,17 @@ class Operator:
             u, du, a = sample(xv)
             uf = sample(xf)[0]
             _check(lib.vfp_set_flow_planar(ctx, _dptr(u), _dptr(du), _dptr(a), _dptr(uf)))
+        elif kind[0] == "points":
+            X, _ = self.volume_points()
+            U, dU, _ = wl.flow(X)
+            Up = _f64(U.T)                                   # [cell*q][3]
+            G = _f64(np.transpose(dU, (2, 0, 1)))            # [cell*q][a][b]
+            self._uface = []
+            for a in range(len(wl.axes)):
+                Uf, _, _ = wl.flow(self.face_points(a))
+                self._uface.append(_f64(Uf.T))
+            fp = (C.POINTER(C.c_double) * len(self._uface))(*[_dptr(x) for x in self._uface])
+            _check(lib.vfp_set_flow_points(ctx, _dptr(Up), _dptr(G), fp))
         else:
             raise VFPError(f"flow kind {kind}")
         if wl.magnetic is not None:
@@ -223,7 +265,10 @@ class Operator:
                 X, _ = self.volume_points()
                 B = _f64(wl.magnetic(X).T)          # [cell*q][3]
                 _check(lib.vfp_set_magnetic_points(ctx, _dptr(B)))
-        if np.isscalar(wl.nu):
+        if callable(wl.nu):
+            X, p = self.volume_points()
+            _check(lib.vfp_set_scattering_points(ctx, _dptr(_f64(wl.nu(X, p)))))
+        elif np.isscalar(wl.nu):
             _check(lib.vfp_set_scattering(ctx, float(wl.nu), None))
         else:
             nu = _f64(wl.nu)
@@ -251,6 +296,14 @@ class Operator:
                 or not x.is_contiguous() or x.numel() < size:
             raise VFPError(f"{name} must be a contiguous float64 CUDA tensor of >= {size} elements")
         return C.c_void_p(x.data_ptr())
+
+    def autotune(self, u, work, reps=5, stream=None):
+        """Time the stage kernel's launch shapes (vfp_autotune) and keep the
+        fastest; returns {"shape", "lanes", "tile_map"}."""
+        ch = (C.c_int * 3)()
+        _check(_lib.vfp_autotune(self._ctx, self._t(u, "u"), self._t(work, "work"), int(reps), ch,
+                                 _stream_handle(stream)))
+        return {"shape": ch[0], "lanes": ch[1], "tile_map": ch[2]}
 
     def apply(self, zin, zout, with_source=True, stream=None):
         _check(_lib.vfp_apply(self._ctx, self._t(zin, "in"), self._t(zout, "out"),
@@ -368,6 +421,17 @@ class Operator:
                                       _stream_handle(stream)))
         return {"iterations": int(st.iterations), "residual": float(st.residual), "converged": bool(st.converged)}
 
+    def field_grad_support(self, xcells=None):
+        """Form the U' and dU/dt sensitivities only on the x cells marked
+        True (vfp_field_grad_support); None: everywhere."""
+        if xcells is None:
+            _check(_lib.vfp_field_grad_support(self._ctx, None))
+            return
+        m = np.ascontiguousarray(np.asarray(xcells, dtype=bool).astype(np.uint8))
+        if m.size != self.wl.ncells_axis[0]:
+            raise VFPError("one flag per x cell")
+        _check(_lib.vfp_field_grad_support(self._ctx, m.ctypes.data_as(C.POINTER(C.c_ubyte))))
+
     def set_flow_planar(self, u, dudx, dudt, u_face):
         """Replace the planar flow profile (host arrays at the x Gauss points
         and x faces)."""
@@ -427,7 +491,7 @@ class Batch:
         for i in range(_lib.vfp_batch_nclasses(self._b)):
             info = (C.c_int * 8)()
             _check(_lib.vfp_batch_class_info(self._b, i, info))
-            out.append(dict(zip(("k", "lmax", "nrot", "runs", "batched", "tiles", "grid", "tile_map"),
+            out.append(dict(zip(("k", "lmax", "nrot", "runs", "batched", "tiles", "lanes", "tile_map"),
                                 list(info))))
         return out
 
@@ -500,11 +564,26 @@ def planar_shock_fields(op: "Operator", U0, r, w):
     return u, du, u * du, uf
 
 
-def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: int = None, flow=None):
+def planar_shock_support(op: "Operator", w):
+    """x cells where the tanh shock of width w has a gradient at one of its
+    Gauss points with a wide margin (|x| < 25 w; beyond ~19 w, 1 - tanh^2
+    rounds to 0 in double precision, and with it U', U U' and all their
+    derivatives in the profile's parameters): the support for
+    field_grad_support."""
+    K1 = op.wl.k + 1
+    xv = op.points(PTS_VOLUME, 0).reshape(-1, K1)
+    return np.any(np.abs(xv) < 25.0 * float(w), axis=1)
+
+
+def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: int = None, flow=None,
+                      flow_support=None):
     """u_N = RK4^N(u0) with the scattering frequency nu_cell (one value per
     cell) and, optionally, the planar flow flow = (u, dudx, dudt, u_face) as
     differentiable inputs: backward returns their gradients from the discrete
     adjoint of the library (the flow sensitivities from vfp_field_grad_*).
+    flow_support: optional flags per x cell (vfp_field_grad_support) where
+    the flow's parameters move U' and dU/dt (planar_shock_support for the
+    tanh shock); the other cells skip those sensitivities.
     seg: steps per checkpoint segment; with seg >= nsteps the forward keeps
     the whole stage tape (4 nsteps vectors) and the reverse pass replays
     nothing.  Default: the whole tape when it fits in free device memory,
@@ -513,7 +592,7 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
     if _AdvanceFn.fn is None:
         class AdvanceFn(torch.autograd.Function):
             @staticmethod
-            def forward(ctx, u0, nu, u_q, du_q, a_q, u_f, op, dt, nsteps, seg, has_flow):
+            def forward(ctx, u0, nu, u_q, du_q, a_q, u_f, op, dt, nsteps, seg, has_flow, support):
                 if has_flow:
                     op.set_flow_planar(*(t.detach().cpu().numpy() for t in (u_q, du_q, a_q, u_f)))
                 op.set_scattering(nu.detach().cpu().numpy())
@@ -531,6 +610,7 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
                     work = torch.empty(2 * N, dtype=torch.float64, device=u.device)
                     op.forward_checkpoints(u, dt, nsteps, seg, ckpt, work)
                 ctx.op, ctx.dt, ctx.nsteps, ctx.seg, ctx.has_flow = op, dt, nsteps, seg, has_flow
+                ctx.support = support
                 ctx.nu = nu.detach().cpu().numpy().copy()
                 ctx.flow = tuple(t.detach().cpu().numpy().copy() for t in (u_q, du_q, a_q, u_f)) \
                     if has_flow else None
@@ -543,6 +623,7 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
                 op, N = ctx.op, ctx.op.ndofs
                 if ctx.has_flow:
                     op.set_flow_planar(*ctx.flow)
+                    op.field_grad_support(ctx.support)
                 op.set_scattering(ctx.nu)
                 dev = g.device
                 lam = g.detach().to(torch.float64).contiguous().clone()
@@ -567,11 +648,11 @@ def advance_with_grad(op: "Operator", u0, nu_cell, dt: float, nsteps: int, seg: 
                     gfc = torch.empty(op.wl.ncells_axis[0] + 1, dtype=torch.float64, device=dev)
                     op.field_grad_reduce(slots, gu, gd, ga, gfc)
                     gf = (gu, gd, ga, gfc)
-                return (lam, grad_nu) + gf + (None, None, None, None, None)
+                return (lam, grad_nu) + gf + (None, None, None, None, None, None)
         _AdvanceFn.fn = AdvanceFn
     import torch as _t
     seg = grad_segment(op, nsteps, u0.device) if seg is None else int(seg)
     if flow is None:
         z = _t.zeros(1, dtype=_t.float64, device=u0.device)
-        return _AdvanceFn.fn.apply(u0, nu_cell, z, z, z, z, op, float(dt), int(nsteps), seg, False)
-    return _AdvanceFn.fn.apply(u0, nu_cell, *flow, op, float(dt), int(nsteps), seg, True)
+        return _AdvanceFn.fn.apply(u0, nu_cell, z, z, z, z, op, float(dt), int(nsteps), seg, False, None)
+    return _AdvanceFn.fn.apply(u0, nu_cell, *flow, op, float(dt), int(nsteps), seg, True, flow_support)

@@ -85,6 +85,46 @@ def shock_flow(U0, r, w):
     return flow
 
 
+def swirl_flow(U0=(0.1, -0.05, 0.02), amp=0.15, length=2.0, stretch=1.0):
+    """A steady flow that varies along x and y:
+    U_x = U0_x + amp sin(2 pi y / L) + stretch amp x / (2L),
+    U_y = U0_y + amp cos(2 pi x / L) - 0.3 stretch amp y / L,
+    U_z = U0_z + amp/2 sin(2 pi (x + y) / L);
+    divergence-free in (x, y) for stretch = 0 (then also periodic in x and y
+    with period L).  Returns U, dU[a, b] = dU_b/dx^a and the material
+    derivative U.grad U."""
+    U0 = np.asarray(U0, dtype=float)
+    k = 2 * math.pi / length
+
+    def flow(X):
+        x, y = X[0], X[1]
+        N = X.shape[1]
+        U = np.zeros((3, N))
+        dU = np.zeros((3, 3, N))
+        U[0] = U0[0] + amp * np.sin(k * y) + stretch * amp * x / (2 * length)
+        U[1] = U0[1] + amp * np.cos(k * x) - 0.3 * stretch * amp * y / length
+        U[2] = U0[2] + 0.5 * amp * np.sin(k * (x + y))
+        dU[0, 0] = stretch * amp / (2 * length)
+        dU[1, 0] = amp * k * np.cos(k * y)
+        dU[0, 1] = -amp * k * np.sin(k * x)
+        dU[1, 1] = -0.3 * stretch * amp / length
+        dU[0, 2] = dU[1, 2] = 0.5 * amp * k * np.cos(k * (x + y))
+        a = np.einsum("an,abn->bn", U, dU)
+        return U, dU, a
+    flow.kind = ("points",)
+    return flow
+
+
+def varying_scattering(nu0=0.7, amp=0.4, length=2.0):
+    """nu(x, p) = nu0 (1 + amp sin(2 pi x / L) cos(2 pi y / L)) p^(-1/3):
+    varies inside every cell."""
+    k = 2 * math.pi / length
+
+    def nu(X, p):
+        return nu0 * (1 + amp * np.sin(k * X[0]) * np.cos(k * X[1])) * np.power(p, -1.0 / 3.0)
+    return nu
+
+
 def uniform_field(B):
     B = np.asarray(B, dtype=float)
 
@@ -158,7 +198,7 @@ class Workload:
     p_fixed: float = None       # momentum magnitude if there is no ln p axis
     flow: object = zero_flow
     magnetic: object = None
-    nu: object = 0.0            # float or per-cell array (len = ncells)
+    nu: object = 0.0            # float, per-cell array (len = ncells) or nu(X, p) at the points
     source: object = None
     mass: float = 1.0
     charge: float = 1.0
@@ -268,6 +308,43 @@ def shock_workload(name, nx, np_, k, lmax, U0=0.1, r=4.0, L=10.0, w_frac=0.01,
     if init:
         wl.meta["init"] = random_state(wl, SEED_BASE + seed, 1e-3)
     return wl
+
+
+def paper_shock_x_nodes(shock_halfwidth=0.04, dx_shock=0.01, grow=0.01, half_length=280.0):
+    """The stretched x grid of Sec. 4.4 (Fig. shock-grid): cells of
+    dx_shock across |x| <= shock_halfwidth, then cell i outside has width
+    sinh(grow i) (never below dx_shock), out to |x| = half_length."""
+    pos = list(np.arange(0.0, shock_halfwidth + 1e-12, dx_shock))
+    i = 1
+    while pos[-1] < half_length:
+        pos.append(pos[-1] + max(dx_shock, math.sinh(grow * i)))
+        i += 1
+    pos = np.array(pos)
+    pos[-1] = half_length
+    return np.concatenate([-pos[::-1], pos[1:]])
+
+
+def paper_dsa_workload(np_=256, k=1, dx_shock=0.01, grow=0.01):
+    """The diffusive-shock-acceleration run of Sec. 4.4 with the parameters
+    of Table sapphire-simulation-parameters: U1 = 1/60, r = 4, shock width
+    1/25 (tanh profile of eq. sapphire-velocity-profile), nu = 1, B = e_x,
+    Q = 0.1, p0 = 2, sigma_x = sigma_p = 1/8 (the source of
+    eq. monoenergetic-point-source, Gaussian in p), l_max = 1, the domain
+    [-280, 280] x [ln 0.1, ln 100] with the stretched x grid and np_ cells in
+    ln p; zero inflow upstream and at both p ends, "continuous" downstream."""
+    U1, r, Ls, Q, p0, sx, sp = 1.0 / 60.0, 4.0, 1.0 / 25.0, 0.1, 2.0, 1.0 / 8.0, 1.0 / 8.0
+
+    def source(X, p):
+        return (Q / (2 * math.pi * sx * sp) * np.exp(-X[0] ** 2 / (2 * sx * sx))
+                * np.exp(-(p - p0) ** 2 / (2 * sp * sp)))
+    xn = paper_shock_x_nodes(Ls, dx_shock, grow)
+    pn = uniform_nodes(math.log(0.1), math.log(100.0), np_)
+    return Workload(
+        name=f"dsa_paper_{len(xn) - 1}x{np_}_k{k}", lmax=1, k=k, axes=("x", "lnp"), nodes=(xn, pn),
+        bc=((ZERO_INFLOW, CONTINUOUS), (ZERO_INFLOW, ZERO_INFLOW)),
+        terms=frozenset({ADVECTION, MOMENTUM, ROTATION, COLLISION, SOURCE}),
+        flow=shock_flow(U1 / r, r, Ls), magnetic=uniform_field((1.0, 0.0, 0.0)), nu=1.0, source=source,
+        meta={"U1": U1, "r": r, "Q": Q, "p0": p0})
 
 
 # C2: 2-D (x, ln p) parallel shock, 1024 x 128, k=2, l_max=3

@@ -101,6 +101,58 @@ P_AXIS_CASES = {
     "shock_p_k2_l3_tiles": lambda: shock(16, 7, 2, 3, paxis="p", lnp=(-1.0, 2.5)),
 }
 
+def swirl(axes, n, k, lmax, bc, source=True):
+    """Spatial axes with the flow, and the scattering rate, given at the
+    points (both vary inside every cell), a uniform B and (optionally) a
+    source.  On a periodic axis the flow is periodic too (its period is that
+    axis' length, and it has no linear part); otherwise it also has a
+    divergence."""
+    lo, hi = (-1.2, -0.9, -0.6), (1.5, 1.4, 0.9)
+    nodes = tuple(np.linspace(lo[a], hi[a], n[a] + 1) ** 1.0 for a in range(len(axes)))
+    per = [a for a in range(len(axes)) if bc[a][0] == W.PERIODIC and a < 2]
+    length = hi[per[0]] - lo[per[0]] if per else 2.0
+    stretch = 0.0 if per else 1.0
+    return W.Workload(
+        name=f"swirl{len(axes)}d_k{k}_l{lmax}", lmax=lmax, k=k, axes=axes, nodes=nodes, bc=bc,
+        terms=frozenset({W.ADVECTION, W.ROTATION, W.COLLISION} | ({W.SOURCE} if source else set())),
+        p_fixed=1.3, flow=W.swirl_flow(U0=(0.12, -0.07, 0.05), amp=0.2, length=length, stretch=stretch),
+        magnetic=W.uniform_field((0.3, -0.6, 1.1)), nu=W.varying_scattering(0.7, 0.4, 2.0),
+        source=lambda X, p: np.exp(-(X[0] ** 2 + (X[1] - 0.1) ** 2 + X[2] ** 2)))
+
+
+def field_B(X):
+    """A magnetic field that varies along x."""
+    return np.stack([1.0 + 0.3 * np.sin(2.0 * X[0]), 0.2 * np.cos(1.5 * X[0]), 0.1 + 0.0 * X[0]])
+
+
+def shock_fields(nx, np_, k, lmax, B=True, nu=True, seed=2):
+    """The shock with B(x) at the points and/or nu(x, p) at the points."""
+    from dataclasses import replace
+    wl = shock(nx, np_, k, lmax, seed=seed)
+    kw = {}
+    if B:
+        kw["magnetic"] = field_B
+    if nu:
+        kw["nu"] = W.varying_scattering(1.0, 0.5, 7.0)
+    return replace(wl, name=wl.name + ("_B" if B else "") + ("_nu" if nu else ""), **kw)
+
+
+_ZI, _CO, _PE = W.ZERO_INFLOW, W.CONTINUOUS, W.PERIODIC
+
+# fields given at the points: flow on 1-3 spatial axes, B with a momentum
+# axis, nu inside the cells (general kernels, forward and adjoint)
+FIELD_CASES = {
+    "swirl1d_k2_l7": lambda: swirl(("x",), (21,), 2, 7, ((_ZI, _CO),)),
+    "swirl2d_k2_l3": lambda: swirl(("x", "y"), (13, 10), 2, 3, ((_ZI, _CO), (_PE, _PE))),
+    "swirl2d_k1_l5": lambda: swirl(("x", "y"), (17, 9), 1, 5, ((_ZI, _ZI), (_CO, _ZI))),
+    "swirl2d_k2_l3_tiles": lambda: swirl(("x", "y"), (40, 33), 2, 3, ((_ZI, _CO), (_ZI, _ZI))),
+    "swirl3d_k1_l3": lambda: swirl(("x", "y", "z"), (6, 5, 4), 1, 3, ((_ZI, _CO), (_PE, _PE), (_CO, _ZI))),
+    "swirl3d_k2_l2": lambda: swirl(("x", "y", "z"), (4, 4, 3), 2, 2, ((_PE, _PE), (_ZI, _CO), (_PE, _PE))),
+    "shock_B_k2_l3": lambda: shock_fields(13, 8, 2, 3, nu=False),
+    "shock_nu_k2_l3": lambda: shock_fields(12, 7, 2, 3, B=False),
+    "shock_B_nu_k1_l5": lambda: shock_fields(11, 6, 1, 5),
+}
+
 CASES = {
     "c1": lambda: W.config1(),
     "shock_k2_l3": lambda: shock(25, 11, 2, 3),

@@ -37,7 +37,7 @@ def _create(lib, lmax=3, k=2, axes=(0, 3), mask=31, mass=1.0, charge=1.0):
 
 
 @pytest.mark.parametrize("kw,needle", [
-    (dict(lmax=0), "lmax"), (dict(lmax=8), "lmax"), (dict(k=0), "k="), (dict(k=6), "k="),
+    (dict(lmax=0), "lmax"), (dict(lmax=12), "lmax"), (dict(k=0), "k="), (dict(k=6), "k="),
     (dict(axes=()), "naxes"), (dict(axes=(0, 1, 2, 3)), "naxes"), (dict(axes=(3, 0)), "ln p"),
     (dict(axes=(1,)), "x, y, z"), (dict(axes=(0, 1, 2, 3)[:3] + ()), None),
     (dict(mass=0.0), "mass"), (dict(mask=64), "term"), (dict(axes=(3,)), "spatial"),
@@ -50,6 +50,17 @@ def test_create_validation(lib, kw, needle):
         return
     assert rc == -1
     assert needle in lib.vfp_last_error().decode()
+
+
+@pytest.mark.parametrize("lmax,k,axes,rc_want", [
+    (11, 2, (0,), 0), (8, 1, (0,), 0), (9, 2, (0, 1), -5), (11, 2, (0, 3), -5), (9, 3, (0,), -5)])
+def test_create_high_lmax_scope(lib, lmax, k, axes, rc_want):
+    """l_max 8..11: one spatial axis x at fixed p with k <= 2 (VFP_EUNSUPPORTED
+    otherwise)."""
+    rc, ctx = _create(lib, lmax=lmax, k=k, axes=axes)
+    assert rc == rc_want, lib.vfp_last_error().decode()
+    if rc == 0:
+        lib.vfp_destroy(ctx)
 
 
 @pytest.mark.parametrize("k,axes,rc_want", [

@@ -86,3 +86,61 @@ def test_batch_sample_matches_oracle(lib, cuda):
         _say(f"[batch oracle] run {i}: rel_inf={err:.3e}")
         assert err <= STEPS_TOL
     b.close()
+
+
+def test_batch_refuses_runs_set_up_after_bind(lib, cuda):
+    """The stage descriptors copy each run's field pointers and values when
+    the batch is bound; a set-up call on a run afterwards (which may free
+    and reallocate those fields) makes advance and autotune refuse to launch
+    until the batch is bound again."""
+    import torch
+    from paper_2501_05110_amd.vfp import Batch, VFPError
+    wls = [shock(10, 4, 2, 3, seed=3), shock(9, 5, 1, 1, seed=4)]
+    ops, z0, dts, u, work = _setup(wls)
+    b = Batch(ops)
+    b.bind(u, work, dts)
+    b.advance(1)
+    ops[1].set_scattering(np.full(wls[1].ncells, 2.0))   # reallocates nu per cell
+    before = [x.clone() for x in u]
+    with pytest.raises(VFPError, match="bind again"):
+        b.advance(1)
+    with pytest.raises(VFPError, match="bind again"):
+        b.autotune(reps=1)
+    torch.cuda.synchronize()
+    assert all(torch.equal(x, y) for x, y in zip(u, before))
+    b.bind(u, work, dts)
+    b.advance(1)
+    torch.cuda.synchronize()
+    b.close()
+
+
+@pytest.mark.parametrize("shape", [0, 1, 2])
+@pytest.mark.parametrize("case", [(40, 9, 2, 3), (21, 7, 1, 5), (13, 6, 2, 1), (9, 5, 2, 7)])
+def test_workgroup_shapes_agree(lib, cuda, shape, case, monkeypatch):
+    """The (x, ln p) stage kernel in each workgroup shape (cells per tile,
+    lanes per workgroup) gives the default shape's results bit for bit
+    (apply and 20 steps); vfp_autotune keeps them too."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = shock(*case, seed=6)
+    z = torch.from_numpy(np.random.default_rng(3).standard_normal(wl.ndofs)).cuda()
+    outs = []
+    for sh in (0, shape):
+        monkeypatch.setenv("VFP_SHOCK_SHAPE", str(sh))
+        op = Operator(wl)
+        a = torch.empty_like(z)
+        op.apply(z, a)
+        u = z.clone()
+        work = torch.empty(2 * wl.ndofs, dtype=torch.float64, device="cuda")
+        op.advance(u, op.cfl_dt(0.2), 20, work)
+        torch.cuda.synchronize()
+        outs.append((a, u))
+        if sh == shape:
+            chosen = op.autotune(z, work[:wl.ndofs], reps=2)
+            _say(f"[shapes] {case} shape {shape}: autotune chose {chosen}")
+            b = torch.empty_like(z)
+            op.apply(z, b)
+            torch.cuda.synchronize()
+            assert torch.equal(a, b)
+        op.close()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])

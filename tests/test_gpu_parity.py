@@ -374,3 +374,39 @@ def test_advance_under_caller_graph_capture(lib, cuda):
         assert torch.equal(u, eager), (rep, float((u - eager).abs().max()))
         _ = (u * 2.0).sum().item()          # eager work between replays
     op.close()
+
+
+@pytest.mark.parametrize("case", ["c1", "line_k2_l5", "line_k1_l7_inflow"])
+def test_resident_stepping(lib, cuda, case, monkeypatch):
+    """Small runs on one axis step inside one workgroup (the whole state in
+    LDS, one launch for all steps): 200 steps against the oracle and against
+    the stage launches (VFP_RESIDENT=0), which differ only in rounding order."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    if case == "c1":
+        wl = W.config1()
+    else:
+        k, lmax = (2, 5) if case == "line_k2_l5" else (1, 7)
+        bc = (W.PERIODIC, W.PERIODIC) if case == "line_k2_l5" else (W.ZERO_INFLOW, W.CONTINUOUS)
+        nc = 9 if lmax == 5 else 7
+        wl = W.Workload(name=case, lmax=lmax, k=k, axes=("x",), nodes=(np.linspace(-1.0, 1.4, nc + 1),),
+                        bc=(bc,), terms=frozenset({W.ADVECTION, W.ROTATION, W.COLLISION, W.SOURCE}),
+                        p_fixed=1.7, flow=W.uniform_flow([0.15, 0.0, 0.0]),
+                        magnetic=W.uniform_field((0.4, -0.3, 0.8)),
+                        nu=np.linspace(0.2, 0.9, nc), source=lambda X, p: np.exp(-X[0] ** 2))
+    z = W.random_state(wl, 17).ravel()
+    outs = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("VFP_RESIDENT", mode)
+        op = Operator(wl)
+        dt = op.cfl_dt(0.2)
+        u = torch.from_numpy(z.copy()).cuda()
+        work = torch.empty(2 * wl.ndofs, dtype=torch.float64, device="cuda")
+        op.advance(u, dt, 200, work)
+        torch.cuda.synchronize()
+        outs[mode] = u.cpu().numpy()
+        op.close()
+    want = dg.rk4(dg.assemble(wl), z, dt, 200)
+    e1, e0 = rel_inf(outs["1"], want), rel_inf(outs["1"], outs["0"])
+    _say(f"[resident] {case}: ndofs={wl.ndofs} vs oracle {e1:.2e}, vs stage launches {e0:.2e}")
+    assert e1 <= STEPS_TOL and e0 <= 1e-12

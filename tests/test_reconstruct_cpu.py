@@ -85,7 +85,16 @@ def test_reconstruct_dipole():
     np.testing.assert_allclose(f, want, atol=1e-14)
 
 
-def test_library_rejects_lmax_8():
+def test_library_harmonics_to_lmax_11():
+    """The library's harmonics up to l_max = 11 (the closure example of
+    Sec. 4.3): orthonormal on a sphere rule exact to degree 24, equal to the
+    oracle's, and l_max = 12 is refused."""
     from paper_2501_05110_amd import vfp
+    pts, wts = sh.sphere_quadrature(24)
+    th = np.arccos(np.clip(pts[0], -1, 1))
+    ph = np.arctan2(pts[2], pts[1])
+    Y = _library_Y(11, th, ph)
+    np.testing.assert_allclose(Y.T @ (wts[:, None] * Y), np.eye(144), atol=1e-12)
+    np.testing.assert_allclose(Y, _oracle_Y(11, th, ph), atol=1e-12)
     with pytest.raises(vfp.VFPError):
-        vfp.sh_eval(8, [0.1], [0.2])
+        vfp.sh_eval(12, [0.1], [0.2])
