@@ -426,7 +426,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
   // keeps the in-place form w_out == u correct
   double uu[NB];
   const bool use_u = A.st.alpha != 0.0;
-#if !VFP_LATE_U
+  if constexpr (!(VFP_LATE_U || ADJ)) {
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
 #if VFP_NT_LOAD_U
@@ -435,7 +435,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
     uu[b] = use_u ? gp(A.st.u)[cbase + (size_t)b * N] : 0.0;
 #endif
   }
-#endif
+  }
   double ff[ADJ ? NB : 1];
   const bool use_g = ADJ && gp(A.adj.fwd) && gp(A.adj.grad_nu);
   auto load_ff = [&]() {
@@ -444,7 +444,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
       for (int b = 0; b < NB; ++b) ff[b] = use_g ? gp(A.adj.fwd)[cbase + (size_t)b * N] : 0.0;
     }
   };
-  if constexpr (!VFP_LATE_U) load_ff();
+  if constexpr (!(VFP_LATE_U || ADJ)) load_ff();
 
   // ---- volume, one row of Gauss points (fixed q1) at a time -----------------
   if constexpr (!ADJ) {
@@ -564,37 +564,34 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
     const double mom_s2hp = -F.t_mom * sc[P_S2H];
     const double t_adv = F.t_adv, t_mom = F.t_mom;
     const double tas2hx = t_adv * sc[X_S2H];
-    // along x once: values t and x-derivatives tx at [q0 + K1 j1]
-    double t[NB], tx[NB];
-#pragma unroll
-    for (int j1 = 0; j1 < K1; ++j1)
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        double a = 0.0, d = 0.0;
-#pragma unroll
-        for (int j0 = 0; j0 < K1; ++j0) {
-          a = fma(CB::phi[q0][j0], w[j0 + K1 * j1], a);
-          if (CB::dphi[q0][j0] != 0.0) d = fma(CB::dphi[q0][j0], w[j0 + K1 * j1], d);
-        }
-        t[q0 + K1 * j1] = a;
-        tx[q0 + K1 * j1] = d;
-      }
     auto rows = [&](auto gtag) {
       constexpr bool GR = decltype(gtag)::value;
 #pragma unroll
       for (int q1 = 0; q1 < K1; ++q1) {
         if (in_grp) {
+          // along ln p first for this row (values and, with a gradient,
+          // ln p derivatives per x node), then along x: few values live
+          double wy[K1], wdy[K1];
+#pragma unroll
+          for (int j0 = 0; j0 < K1; ++j0) {
+            double a = 0.0, d = 0.0;
+#pragma unroll
+            for (int j1 = 0; j1 < K1; ++j1) {
+              if (CB::phi[q1][j1] != 0.0) a = fma(CB::phi[q1][j1], w[j0 + K1 * j1], a);
+              if constexpr (GR)
+                if (CB::dphi[q1][j1] != 0.0) d = fma(CB::dphi[q1][j1], w[j0 + K1 * j1], d);
+            }
+            wy[j0] = a;
+            wdy[j0] = d;
+          }
 #pragma unroll
           for (int q0 = 0; q0 < K1; ++q0) {
             double f = 0.0, dx = 0.0, dp = 0.0;
 #pragma unroll
-            for (int j1 = 0; j1 < K1; ++j1) {
-              if (CB::phi[q1][j1] != 0.0) {
-                f = fma(CB::phi[q1][j1], t[q0 + K1 * j1], f);
-                dx = fma(CB::phi[q1][j1], tx[q0 + K1 * j1], dx);
-              }
-              if constexpr (GR)
-                if (CB::dphi[q1][j1] != 0.0) dp = fma(CB::dphi[q1][j1], t[q0 + K1 * j1], dp);
+            for (int j0 = 0; j0 < K1; ++j0) {
+              f = fma(CB::phi[q0][j0], wy[j0], f);
+              if (CB::dphi[q0][j0] != 0.0) dx = fma(CB::dphi[q0][j0], wy[j0], dx);
+              if constexpr (GR) dp = fma(CB::phi[q0][j0], wdy[j0], dp);
             }
             X[q0 * N + r] = f;
             X[(K1 + q0) * N + r] = dx;
@@ -686,7 +683,7 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
           v[i0 + K1 * i1] = acc;
         }
     };
-    if constexpr (VFP_LATE_U) load_ff();
+    if constexpr (VFP_LATE_U || ADJ) load_ff();
     const double jac = 1.0 / (sc[X_S2H] * sc[P_S2H]);
     if (A.adj.mass_out) {
       ref_mass2(res);
@@ -719,10 +716,12 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) res[b] += src[b];
   }
-#if VFP_LATE_U
+  // the adjoint loads its stage base and forward state last (fewer live
+  // registers through the volume; measured faster)
+  if constexpr (VFP_LATE_U || ADJ) {
 #pragma unroll
-  for (int b = 0; b < NB; ++b) uu[b] = use_u ? gp(A.st.u)[cbase + (size_t)b * N] : 0.0;
-#endif
+    for (int b = 0; b < NB; ++b) uu[b] = use_u ? gp(A.st.u)[cbase + (size_t)b * N] : 0.0;
+  }
   if (act) {
     const double al = A.st.alpha, be = A.st.beta;
 #pragma unroll
