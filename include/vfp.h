@@ -334,7 +334,12 @@ int vfp_adjoint_checkpointed(vfp_ctx* ctx, const double* ckpt, double dt, int64_
  * zeroed by the caller before the first stage); vfp_field_grad_reduce sums
  * the slots into g_u, g_dudx, g_dudt (N0 (k+1) doubles each) and g_uface
  * (N0 + 1 doubles), overwriting them.  VFP_EUNSUPPORTED for contexts without
- * an (x, ln p) planar flow. */
+ * an (x, ln p) planar flow.  The derivative tables of B_+ at the ln p faces
+ * are built by the context's first vfp_field_grad_support or field-gradient
+ * launch (vfp_field_grad_stage, or vfp_adjoint_steps /
+ * vfp_adjoint_checkpointed with field_slots): a synchronous host computation
+ * and allocation, so make that first call outside stream capture; later
+ * set-up calls keep the tables current. */
 int vfp_field_grad_size(const vfp_ctx* ctx, int64_t* n);
 /* Restrict the U' and dU/dt sensitivities (volume and ln p faces) to the x
  * cells with xcells[i] != 0 (host array of N0 flags; NULL: every cell, the

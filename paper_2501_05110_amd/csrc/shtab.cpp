@@ -52,18 +52,24 @@ void jacobi_eigh(const Mat& A0, std::vector<double>& lam, Mat& V) {
   Mat A = A0;
   V = Mat(n);
   for (int i = 0; i < n; ++i) V(i, i) = 1.0;
+  // Rotations keep the Frobenius norm; an off-diagonal entry below 1e-18 of
+  // it is set to zero (it moves no eigenvalue by more than that), and the
+  // iteration ends with the first sweep that rotates nothing.  (A relative
+  // test on the off-diagonal sum alone can stall at rounding level.)
+  double tot = 0.0;
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) tot += A(i, j) * A(i, j);
+  const double small = 1e-18 * std::sqrt(tot);
   for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        tot += A(i, j) * A(i, j);
-        if (i != j) off += A(i, j) * A(i, j);
-      }
-    if (off <= 1e-32 * tot || off == 0.0) break;
+    bool rotated = false;
     for (int p = 0; p < n - 1; ++p)
       for (int q = p + 1; q < n; ++q) {
         double apq = A(p, q);
-        if (apq == 0.0) continue;
+        if (std::fabs(apq) <= small) {
+          A(p, q) = A(q, p) = 0.0;
+          continue;
+        }
+        rotated = true;
         double app = A(p, p), aqq = A(q, q);
         double theta = (aqq - app) / (2.0 * apq);
         double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
@@ -84,6 +90,7 @@ void jacobi_eigh(const Mat& A0, std::vector<double>& lam, Mat& V) {
           V(k, q) = s * vkp + c * vkq;
         }
       }
+    if (!rotated) break;
   }
   lam.resize(n);
   for (int i = 0; i < n; ++i) lam[i] = A(i, i);

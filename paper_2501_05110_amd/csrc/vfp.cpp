@@ -287,6 +287,7 @@ struct vfp_ctx {
   int shape = 0;            // workgroup shape slot of the forward (x, ln p) kernel (vfp_autotune)
   ResidentLauncher resident = nullptr;   // whole-run single-workgroup stepping (small runs on one axis)
   uint64_t gen = 0;         // bumped by every set-up call; a batch bound to older data refuses to run
+  bool pf_dk = false;       // the p-face derivative tables (field gradients) are kept
 };
 
 namespace {
@@ -589,21 +590,26 @@ int build_momentum_data(vfp_ctx* c) {
 // Eigen-decomposition of a small symmetric matrix (cyclic Jacobi), in place:
 // on return a[i][i] are the eigenvalues and v the eigenvectors (columns).
 constexpr int kBlk = kMaxLmax + 1;
+// Converged as jacobi_eigh: off-diagonal entries below 1e-18 of the
+// Frobenius norm are set to zero, and the first sweep without a rotation ends.
 void small_eigh(int n, double (&a)[kBlk][kBlk], double (&v)[kBlk][kBlk]) {
+  double tot = 0.0;
   for (int i = 0; i < n; ++i)
-    for (int j = 0; j < n; ++j) v[i][j] = (i == j) ? 1.0 : 0.0;
+    for (int j = 0; j < n; ++j) {
+      v[i][j] = (i == j) ? 1.0 : 0.0;
+      tot += a[i][j] * a[i][j];
+    }
+  const double small = 1e-18 * std::sqrt(tot);
   for (int sweep = 0; sweep < 100; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int i = 0; i < n; ++i)
-      for (int j = 0; j < n; ++j) {
-        tot += a[i][j] * a[i][j];
-        if (i != j) off += a[i][j] * a[i][j];
-      }
-    if (off <= 1e-32 * tot || off == 0.0) break;
+    bool rotated = false;
     for (int p = 0; p < n - 1; ++p)
       for (int q = p + 1; q < n; ++q) {
         const double apq = a[p][q];
-        if (apq == 0.0) continue;
+        if (std::fabs(apq) <= small) {
+          a[p][q] = a[q][p] = 0.0;
+          continue;
+        }
+        rotated = true;
         const double theta = (a[q][q] - a[p][p]) / (2.0 * apq);
         const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
         const double cs = 1.0 / std::sqrt(t * t + 1.0), sn = t * cs;
@@ -623,6 +629,7 @@ void small_eigh(int n, double (&a)[kBlk][kBlk], double (&v)[kBlk][kBlk]) {
           v[k][q] = sn * vkp + cs * vkq;
         }
       }
+    if (!rotated) break;
   }
 }
 
@@ -638,9 +645,13 @@ int host_threads() {
 // p-face upwind data: beta^{ln p} = a1 A^x + a2 (A^x A^x)_t at each (x point,
 // p face); it keeps the (m,s) blocks of A^x (and the s = 0 and s = 1 blocks
 // of one m are equal), so each m block is diagonalised once.  Points where
-// beta^{ln p} vanishes (no flow gradient) are trivially code -1.
-int build_pface_data(vfp_ctx* c) {
+// beta^{ln p} vanishes (no flow gradient) are trivially code -1.  The
+// derivative tables of B_+ are built once field gradients have been asked
+// for (c->pf_dk); dk_only rebuilds just those (the codes and B_+ rows come
+// out the same and stay as uploaded).
+int build_pface_data(vfp_ctx* c, bool dk_only = false) {
   if (!c->mom || !c->mesh_set) return VFP_OK;
+  const bool dk = c->pf_dk;
   const int pa = c->naxes - 1, K1 = c->K1, n = c->n, L = c->lmax;
   const int nxp = c->ncell[0] * K1, npf = c->ncell[pa] + 1;
   const std::vector<double>& nd = c->nodes[pa];
@@ -725,29 +736,41 @@ int build_pface_data(vfp_ctx* c) {
           P.tab.insert(P.tab.end(), rows.begin(), rows.end());
           // derivatives of B_+ in the directions A^x and (A^xA^x)_t
           // (Daleckii-Krein): Q (Gamma o Q^T dB Q) Q^T with
-          // Gamma_kl = (l_k^+ - l_l^+) / (l_k - l_l), H(l_k) where equal
-          for (int dir = 0; dir < 2; ++dir) {
+          // Gamma_kl = (l_k^+ - l_l^+) / (l_k - l_l), H(l_k) where equal;
+          // only for field gradients (vfp_field_grad_*)
+          for (int dir = 0; dk && dir < 2; ++dir) {
             std::fill(drows.begin(), drows.end(), 0.0);
             for (int m = 0; m <= L; ++m) {
               const int bsz = L - m + 1;
               const double* db = (dir == 0 ? ab.data() : xb.data()) + (size_t)m * kBlk * kBlk;
-              double D[kBlk][kBlk];
-              for (int k = 0; k < bsz; ++k)
+              const double(&Q)[kBlk][kBlk] = vec[m];
+              double W[kBlk][kBlk], D[kBlk][kBlk];
+              for (int i = 0; i < bsz; ++i)          // W = dB Q
                 for (int l = 0; l < bsz; ++l) {
                   double acc = 0.0;
-                  for (int i = 0; i < bsz; ++i)
-                    for (int j = 0; j < bsz; ++j) acc += vec[m][i][k] * db[i * kBlk + j] * vec[m][j][l];
+                  for (int j = 0; j < bsz; ++j) acc += db[i * kBlk + j] * Q[j][l];
+                  W[i][l] = acc;
+                }
+              for (int k = 0; k < bsz; ++k)          // D = Gamma o (Q^T W)
+                for (int l = 0; l < bsz; ++l) {
+                  double acc = 0.0;
+                  for (int i = 0; i < bsz; ++i) acc += Q[i][k] * W[i][l];
                   const double lk = ev[m][k], ll = ev[m][l], dl = lk - ll;
                   const double gam = std::fabs(dl) > 1e-14 * (std::fabs(lk) + std::fabs(ll))
                                          ? (std::max(lk, 0.0) - std::max(ll, 0.0)) / dl
                                          : (lk > 0 ? 1.0 : (lk < 0 ? 0.0 : 0.5));
                   D[k][l] = gam * acc;
                 }
-              for (int i = 0; i < bsz; ++i)
+              for (int i = 0; i < bsz; ++i)          // W = Q D
+                for (int l = 0; l < bsz; ++l) {
+                  double acc = 0.0;
+                  for (int k = 0; k < bsz; ++k) acc += Q[i][k] * D[k][l];
+                  W[i][l] = acc;
+                }
+              for (int i = 0; i < bsz; ++i)          // rows of W Q^T
                 for (int j = 0; j < bsz; ++j) {
                   double acc = 0.0;
-                  for (int k = 0; k < bsz; ++k)
-                    for (int l = 0; l < bsz; ++l) acc += vec[m][i][k] * D[k][l] * vec[m][j][l];
+                  for (int l = 0; l < bsz; ++l) acc += W[i][l] * Q[j][l];
                   for (int s = 0; s <= (m ? 1 : 0); ++s)
                     drows[(size_t)lms_index(m + i, m, s) * (L + 1) + j] = acc;
                 }
@@ -782,13 +805,18 @@ int build_pface_data(vfp_ctx* c) {
     dtab.insert(dtab.end(), P.dtab.begin(), P.dtab.end());
     c->beta_pmax = std::max(c->beta_pmax, P.bmax);
   }
+  if (dk) {
+    if (dtab.empty()) dtab.assign(2 * rowsz, 0.0);
+    if (int e = upload_vec(c->d_pf_dtab, dtab)) return e;
+  } else {
+    c->d_pf_dtab.release();
+  }
+  if (dk_only) return VFP_OK;
   if (int e = upload_vec(c->d_pf_code, code)) return e;
   std::vector<double> coded(code.begin(), code.end());
   if (int e = upload_vec(c->d_pf_coded, coded)) return e;
   if (tab.empty()) tab.assign(rowsz, 0.0);
   if (int e = upload_vec(c->d_pf_tab, tab)) return e;
-  if (dtab.empty()) dtab.assign(2 * rowsz, 0.0);
-  if (int e = upload_vec(c->d_pf_dtab, dtab)) return e;
   return VFP_OK;
 }
 
@@ -1643,9 +1671,23 @@ static int field_grad_ready(const vfp_ctx* c) {
   return VFP_OK;
 }
 
+// Builds the p-face derivative tables on the first field-gradient call (a
+// host computation and an upload); later set-up calls keep them current.
+static int ensure_pf_dk(vfp_ctx* c) {
+  if (c->pf_dk) return VFP_OK;
+  c->pf_dk = true;
+  if (int e = build_pface_data(c, true)) {
+    c->pf_dk = false;
+    return e;
+  }
+  c->fld.pf_dtab = c->d_pf_dtab.as<double>();
+  return VFP_OK;
+}
+
 static int launch_fg(vfp_ctx* c, const double* mu, const double* fwd, double cdt, double* slots, void* stream) {
   FieldGradLauncher fl = find_field_grad_launcher(c->k, c->lmax);
   if (!fl) return fail(VFP_EUNSUPPORTED, "no field-gradient kernel for k=%d lmax=%d", c->k, c->lmax);
+  if (int e = ensure_pf_dk(c)) return e;
   KernelArgs a{};
   a.mesh = c->meshargs;
   a.fld = c->fld;
@@ -1660,6 +1702,7 @@ int vfp_field_grad_support(vfp_ctx* c, const unsigned char* xcells) {
   ++c->gen;
   if (int e = check_ready(c)) return e;
   if (int e = field_grad_ready(c)) return e;
+  if (int e = ensure_pf_dk(c)) return e;
   if (!xcells) {
     c->d_fg_support.release();
     return VFP_OK;
