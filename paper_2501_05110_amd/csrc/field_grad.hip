@@ -27,10 +27,12 @@
 //
 // Each cell accumulates into its own slots (no atomics): its x Gauss points
 // (summed over its p points), its lower x and ln p faces, and its upper faces
-// where they are the (non-periodic) end of the mesh.  All global loads are
-// issued first; the lanes of a cell exchange forward values through LDS for
-// the l-coupling and reduce once at the end.  fgrad_reduce sums the slots per
-// x point.
+// where they are the (non-periodic) end of the mesh.  The lanes of a cell
+// exchange forward values through a few LDS rows for the l-coupling and sum
+// their shares of the slots through the same rows.  fgrad_reduce sums the
+// slots per x point.
+#include <type_traits>
+
 #include "basis.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -61,20 +63,49 @@ struct GSlots {
 // Heaviside with H(0) = 1/2
 __device__ __forceinline__ double heav(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? 0.0 : 0.5); }
 
-template <int K, int LMAX>
-__global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const double* __restrict__ mu,
-                                                           const double* __restrict__ fwd, double cdt,
-                                                           double* __restrict__ slots,
-                                                           const unsigned char* __restrict__ support) {
+// The sensitivities split in two launches over the same cells, each with a
+// small live register set:
+//   PART 0: dJ/dU at the x Gauss points (volume) and dJ/dU_F (x faces), for
+//           every cell;
+//   PART 1: dJ/dU' and dJ/d(dU/dt) (volume and ln p faces), for the cells of
+//           the support only: a workgroup without a support cell returns at
+//           once (the decision is uniform over the workgroup).
+// They write disjoint slots of a cell.
+template <int K, int PART>
+struct FgRows {
+  static constexpr int K1 = K + 1;
+  // partial-sum rows reduced per cell at the end, and LDS rows per cell
+  static constexpr int NRED = PART == 0 ? K1 + 2 : 6 * K1;
+  static constexpr int NEX = PART == 0 ? 3 * K1 : 2 * K1;   // exchange rows of a face
+  static constexpr int XRW = NRED > NEX ? NRED : NEX;
+  // slot of reduction row j
+  __device__ static constexpr int slot(int j) {
+    using S = GSlots<K>;
+    if (PART == 0) return j < K1 ? S::VOL + 3 * j : S::XF + (j - K1);
+    return j < 2 * K1 ? S::VOL + 3 * (j >> 1) + 1 + (j & 1) : S::PF + (j - 2 * K1);
+  }
+};
+
+// waves per SIMD the register allocation aims for
+#ifndef VFP_FG_WAVES
+#define VFP_FG_WAVES 2
+#endif
+
+template <int K, int LMAX, int PART>
+__device__ __forceinline__ void fgrad_body(const KernelArgs& A, const double* __restrict__ mu,
+                                           const double* __restrict__ fwd, double cdt,
+                                           double* __restrict__ slots, const unsigned char* __restrict__ support,
+                                           double* lds, int blk) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
   constexpr int NB = K1 * K1;
   constexpr int CPB = (kFgThreads / N) > 0 ? kFgThreads / N : 1;
-  constexpr int XRW = 4 * K1;               // exchange rows per cell
   using CB = CBasis<K>;
   using S = GSlots<K>;
-  constexpr int NS = S::SIZE;               // partial-sum rows per cell
-  __shared__ double lds[CPB * (XRW + NS) * N];
+  using FR = FgRows<K, PART>;
+  constexpr int NS = S::SIZE;
+  constexpr int XRW = FR::XRW;
+  constexpr int ax = PART == 0 ? 0 : 1;     // the face axis of this part
 
   const int tid = threadIdx.x;
   const int cl = tid / N;
@@ -83,15 +114,24 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
   const MeshArgs& M = A.mesh;
   const FieldArgs& F = A.fld;
   const RowTables& T = A.tab;
-  const int cell0 = blockIdx.x * CPB + cl;
+  const int nx = M.n[0], np = M.n[1];
+  if constexpr (PART == 1) {
+    if (support) {
+      bool any = false;
+      for (int c2 = 0; c2 < CPB; ++c2) {
+        const int cc = blk * CPB + c2;
+        if (cc < M.ncells) any |= support[cc % nx] != 0;
+      }
+      if (!any) return;
+    }
+  }
+  const int cell0 = blk * CPB + cl;
   const bool act = in_grp && cell0 < M.ncells;
   const int cell = act ? cell0 : 0;
-  const int nx = M.n[0], np = M.n[1];
   const int ix = cell % nx, ip = cell / nx;
-  double* X = lds + (in_grp ? cl : 0) * (XRW + NS) * N;
-  double* Rd = X + XRW * N;
+  double* X = lds + (in_grp ? cl : 0) * XRW * N;
 
-  // ---- every global load first ---------------------------------------------
+  // ---- the cell's values and the neighbour traces along this part's axis
   const size_t cbase = (size_t)cell * NB * N + r;
   double w[NB], m[NB];
 #pragma unroll
@@ -99,83 +139,60 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
     w[b] = fwd[cbase + (size_t)b * N];
     m[b] = mu[cbase + (size_t)b * N];
   }
+  const int ia = ax ? ip : ix, na = ax ? np : nx;
+  double nf[2][K1], nm[2][K1];
+  bool usen[2];
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const int st = ax ? nx : 1;
+    int ni = side ? ia + 1 : ia - 1;
+    const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
+    usen[side] = (ni >= 0 && ni < na) || bc == 0;
+    ni = (ni + na) % na;
+    const size_t nb0 = (size_t)(cell + (ni - ia) * st) * NB * N + r;
+    const int jn = side ? 0 : K;
+#pragma unroll
+    for (int j = 0; j < K1; ++j) {
+      const int node = ax ? (j + K1 * jn) : (jn + K1 * j);
+      nf[side][j] = fwd[nb0 + (size_t)node * N];
+      nm[side][j] = mu[nb0 + (size_t)node * N];
+    }
+  }
   const double* xr = F.xrec + (size_t)ix * kRec;
   const double* pr = F.prec + (size_t)ip * kRec;
   const double s2hx = xr[11], s2hp = pr[14];
   const double jac = 1.0 / (s2hx * s2hp);
   const double t_adv = F.t_adv, t_mom = F.t_mom;
   const double gw[3] = {K == 1 ? 1.0 : 5.0 / 9.0, K == 1 ? 1.0 : 8.0 / 9.0, 5.0 / 9.0};
-  const int axc0 = T.ax_col[r], axc1 = T.ax_col[N + r];
-  const double axv0 = T.ax_val[r], axv1 = T.ax_val[N + r];
-  const int axxc0 = T.axx_col[r], axxc1 = T.axx_col[N + r];
-  const double axxv0 = T.axx_val[r], axxv1 = T.axx_val[N + r], axxv2 = T.axx_val[2 * N + r];
-  const double g1v0 = T.g1_val[r], g1v1 = T.g1_val[N + r];
-  const double g2v0 = T.g2_val[r], g2v1 = T.g2_val[N + r], g2v2 = T.g2_val[2 * N + r];
+  // the l-block of this lane's row (members, eigenvector column, eigenvalue
+  // of A^x) and, for the x faces, U at the faces and V at the p points
   int mem[LMAX + 1];
-  double wcol[LMAX + 1], wrow[LMAX + 1];
+  double wcol[LMAX + 1];
 #pragma unroll
   for (int i = 0; i <= LMAX; ++i) {
     mem[i] = T.blk_mem[i * N + r];
-    wcol[i] = T.w_col[i * N + r];
-    wrow[i] = T.w_row[i * N + r];
+    if constexpr (PART == 0) wcol[i] = T.w_col[i * N + r];
   }
-  const double lam = T.lam[r];
-  int pcode[2][K1];
+  double lam = 0.0, uxf[2] = {0.0, 0.0}, vq[K1];
+  if constexpr (PART == 0) {
+    lam = T.lam[r];
+    uxf[0] = xr[9];
+    uxf[1] = xr[10];
 #pragma unroll
-  for (int side = 0; side < 2; ++side)
-#pragma unroll
-    for (int q0 = 0; q0 < K1; ++q0) pcode[side][q0] = F.pf_code[(size_t)(ip + side) * (nx * K1) + ix * K1 + q0];
-
-  // this lane's share of every slot goes to row i of Rd; the volume rows are
-  // accumulated in registers first
-  double part[3 * K1];
-#pragma unroll
-  for (int i = 0; i < 3 * K1; ++i) part[i] = 0.0;
-
-  // The U' and dU/dt sensitivities (volume and ln p faces) are formed for
-  // the x cells the caller's support marks (all without one); the decision
-  // is uniform over the wavefront (the workgroup), whose LDS exchanges all
-  // lanes then take alike.  dJ/dU (volume and x faces) is formed everywhere.
-  bool full = support == nullptr;
-  if (!full) {
-    for (int c2 = 0; c2 < CPB; ++c2) {
-      const int cc = blockIdx.x * CPB + c2;
-      if (cc < M.ncells) full |= support[cc % nx] != 0;
-    }
+    for (int q = 0; q < K1; ++q) vq[q] = pr[q];
   }
-  if (!full) {
-    // dJ/dU at the x Gauss points: t_adv (2/h_x) (d_x mu) f, no exchange
+
+  // this lane's share of the reduction rows (FgRows::slot)
+  double red[FR::NRED];
 #pragma unroll
-    for (int q1 = 0; q1 < K1; ++q1) {
-      double wy[K1], my[K1];
-#pragma unroll
-      for (int j0 = 0; j0 < K1; ++j0) {
-        double a = 0.0, b = 0.0;
-#pragma unroll
-        for (int j1 = 0; j1 < K1; ++j1) {
-          a = fma(CB::phi[q1][j1], w[j0 + K1 * j1], a);
-          b = fma(CB::phi[q1][j1], m[j0 + K1 * j1], b);
-        }
-        wy[j0] = a;
-        my[j0] = b;
-      }
-#pragma unroll
-      for (int q0 = 0; q0 < K1; ++q0) {
-        double f = 0.0, mx = 0.0;
-#pragma unroll
-        for (int j0 = 0; j0 < K1; ++j0) {
-          f = fma(CB::phi[q0][j0], wy[j0], f);
-          mx = fma(CB::dphi[q0][j0], my[j0], mx);
-        }
-        const double wq = gw[q0] * gw[q1] * jac;
-        part[S::VOL + 3 * q0 + 0] += wq * (s2hx * t_adv * mx * f);
-      }
-    }
-  } else {
+  for (int i = 0; i < FR::NRED; ++i) red[i] = 0.0;
+
   // ---- volume, one row of Gauss points (fixed q1) at a time: interpolate
-  // along ln p first (K1 values per row), then along x
-#pragma unroll
+  // along ln p first (K1 values per row), then along x (a loop, not
+  // unrolled, so that the rows do not all stay live at once)
+#pragma unroll 1
   for (int q1 = 0; q1 < K1; ++q1) {
+    const double gw1 = (K == 1) ? 1.0 : (q1 == 1 ? 8.0 / 9.0 : 5.0 / 9.0);
     double wy[K1], my[K1], mdy[K1];
 #pragma unroll
     for (int j0 = 0; j0 < K1; ++j0) {
@@ -184,201 +201,185 @@ __global__ __launch_bounds__(kFgThreads) void fgrad_kernel(KernelArgs A, const d
       for (int j1 = 0; j1 < K1; ++j1) {
         a = fma(CB::phi[q1][j1], w[j0 + K1 * j1], a);
         b = fma(CB::phi[q1][j1], m[j0 + K1 * j1], b);
-        c = fma(CB::dphi[q1][j1], m[j0 + K1 * j1], c);
+        if constexpr (PART == 1) c = fma(CB::dphi[q1][j1], m[j0 + K1 * j1], c);
       }
       wy[j0] = a;
       my[j0] = b;
       mdy[j0] = c;
     }
-    double fq[K1];
+    if constexpr (PART == 0) {
+      // dJ/dU: t_adv (2/h_x) (d_x mu) f, no exchange
 #pragma unroll
-    for (int q0 = 0; q0 < K1; ++q0) {
-      double f = 0.0;
+      for (int q0 = 0; q0 < K1; ++q0) {
+        double f = 0.0, mx = 0.0;
 #pragma unroll
-      for (int j0 = 0; j0 < K1; ++j0) f = fma(CB::phi[q0][j0], wy[j0], f);
-      fq[q0] = f;
-      if (in_grp) X[q0 * N + r] = f;
-    }
-    wave_sync();
-    const double iV = pr[3 + q1], pid = pr[6 + q1];
-#pragma unroll
-    for (int q0 = 0; q0 < K1; ++q0) {
-      double mq = 0.0, mx = 0.0, mp = 0.0;
-#pragma unroll
-      for (int j0 = 0; j0 < K1; ++j0) {
-        mq = fma(CB::phi[q0][j0], my[j0], mq);
-        mx = fma(CB::dphi[q0][j0], my[j0], mx);
-        mp = fma(CB::phi[q0][j0], mdy[j0], mp);
+        for (int j0 = 0; j0 < K1; ++j0) {
+          f = fma(CB::phi[q0][j0], wy[j0], f);
+          mx = fma(CB::dphi[q0][j0], my[j0], mx);
+        }
+        red[q0] += gw[q0] * gw1 * jac * (s2hx * t_adv * mx * f);
       }
-      const double* P = X + q0 * N;
-      const double f = fq[q0];
-      const double Axf = fma(axv0, P[axc0], axv1 * P[axc1]);
-      const double A2f = fma(axxv0, P[axxc0], fma(axxv1, f, axxv2 * P[axxc1]));
-      const double G1f = fma(g1v0, P[axc0], g1v1 * P[axc1]);
-      const double G2f = fma(g2v0, P[axxc0], fma(g2v1, f, g2v2 * P[axxc1]));
-      const double wq = gw[q0] * gw[q1] * jac;
-      part[S::VOL + 3 * q0 + 0] += wq * (s2hx * t_adv * mx * f);
-      part[S::VOL + 3 * q0 + 1] += wq * (-mq * (t_mom * G2f - t_adv * f) - s2hp * t_mom * mp * A2f);
-      part[S::VOL + 3 * q0 + 2] +=
-          wq * (-mq * t_mom * (iV * G1f - pid * Axf) - s2hp * t_mom * t_mom * mp * iV * Axf);
+    } else {
+      // dJ/dU' and dJ/d(dU/dt): the momentum and divergence terms, with the
+      // l-coupling of f through LDS
+      const int axc0 = T.ax_col[r], axc1 = T.ax_col[N + r];
+      const double axv0 = T.ax_val[r], axv1 = T.ax_val[N + r];
+      const int axxc0 = T.axx_col[r], axxc1 = T.axx_col[N + r];
+      const double axxv0 = T.axx_val[r], axxv1 = T.axx_val[N + r], axxv2 = T.axx_val[2 * N + r];
+      const double g1v0 = T.g1_val[r], g1v1 = T.g1_val[N + r];
+      const double g2v0 = T.g2_val[r], g2v1 = T.g2_val[N + r], g2v2 = T.g2_val[2 * N + r];
+      double fq[K1];
+#pragma unroll
+      for (int q0 = 0; q0 < K1; ++q0) {
+        double f = 0.0;
+#pragma unroll
+        for (int j0 = 0; j0 < K1; ++j0) f = fma(CB::phi[q0][j0], wy[j0], f);
+        fq[q0] = f;
+        if (in_grp) X[q0 * N + r] = f;
+      }
+      wave_sync();
+      const double iV = pr[3 + q1], pid = pr[6 + q1];
+#pragma unroll
+      for (int q0 = 0; q0 < K1; ++q0) {
+        double mq = 0.0, mp = 0.0;
+#pragma unroll
+        for (int j0 = 0; j0 < K1; ++j0) {
+          mq = fma(CB::phi[q0][j0], my[j0], mq);
+          mp = fma(CB::phi[q0][j0], mdy[j0], mp);
+        }
+        const double* P = X + q0 * N;
+        const double f = fq[q0];
+        const double Axf = fma(axv0, P[axc0], axv1 * P[axc1]);
+        const double A2f = fma(axxv0, P[axxc0], fma(axxv1, f, axxv2 * P[axxc1]));
+        const double G1f = fma(g1v0, P[axc0], g1v1 * P[axc1]);
+        const double G2f = fma(g2v0, P[axxc0], fma(g2v1, f, g2v2 * P[axxc1]));
+        const double wq = gw[q0] * gw1 * jac;
+        red[2 * q0 + 0] += wq * (-mq * (t_mom * G2f - t_adv * f) - s2hp * t_mom * mp * A2f);
+        red[2 * q0 + 1] += wq * (-mq * t_mom * (iV * G1f - pid * Axf) - s2hp * t_mom * t_mom * mp * iV * Axf);
+      }
+      wave_sync();
     }
-    wave_sync();
   }
 
-  }
-
-  if (in_grp)
+  // ---- faces along this part's axis: the cell's lower face, and its upper
+  // face where it is the (non-periodic) end of the mesh; on a face from T1
+  // (below) to T2 (above) the pairing is int_F (mu_2 - mu_1) . dJ, with the
+  // trace of a cell outside the mesh counted as zero.  One side at a time:
+  // the side's f1, f2 rows go to rows [0, 2 K1) of X.
 #pragma unroll
-    for (int i = 0; i < 3 * K1; ++i) Rd[(S::VOL + i) * N + r] = part[i];
-
-  // neighbour traces [axis][side][j]: forward and adjoint values
-  // neighbour traces [axis][side][j]: forward and adjoint values
-  double nf[2][2][K1], nm[2][2][K1];
-  bool use_n[2][2];
+  for (int side = 0; side < 2; ++side) {
+    const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
+    const bool valid = act && (side == 0 || (ia == na - 1 && bc != 0));
+    double dmu[K1];
 #pragma unroll
-  for (int ax = 0; ax < 2; ++ax)
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int ia = ax ? ip : ix, na = ax ? np : nx, st = ax ? nx : 1;
-      int ni = side ? ia + 1 : ia - 1;
-      const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
-      use_n[ax][side] = (ni >= 0 && ni < na) || bc == 0;
-      ni = (ni + na) % na;
-      const size_t nb0 = (size_t)(cell + (ni - ia) * st) * NB * N + r;
-      const int jn = side ? 0 : K;
+    for (int q = 0; q < K1; ++q) {
+      double fo = 0.0, fn = 0.0, mo = 0.0, mn = 0.0;
 #pragma unroll
       for (int j = 0; j < K1; ++j) {
-        const int node = ax ? (j + K1 * jn) : (jn + K1 * j);
-        nf[ax][side][j] = fwd[nb0 + (size_t)node * N];
-        nm[ax][side][j] = mu[nb0 + (size_t)node * N];
+        const double ph = CB::phi[q][j];
+        const int node = ax ? (j + K1 * (side ? K : 0)) : ((side ? K : 0) + K1 * j);
+        fo = fma(ph, w[node], fo);
+        fn = fma(ph, nf[side][j], fn);
+        mo = fma(ph, m[node], mo);
+        mn = fma(ph, nm[side][j], mn);
       }
-    }
-
-  // ---- faces: this cell's lower faces, and its upper faces at the
-  // (non-periodic) end of the mesh; on a face from T1 (below) to T2 (above)
-  // the pairing is int_F (mu_2 - mu_1) . dJ, with the trace of a cell outside
-  // the mesh counted as zero
-#pragma unroll
-  for (int ax = 0; ax < 2; ++ax) {
-    if (ax == 1 && !full) {
-      // no U' and dU/dt sensitivities here: the ln p face slots stay zero
-      if (in_grp)
-#pragma unroll
-        for (int i = 0; i < 4 * K1; ++i) Rd[(S::PF + i) * N + r] = 0.0;
-      break;
-    }
-    const int ia = ax ? ip : ix, na = ax ? np : nx;
-    // f1, f2 rows of both sides: [side][f1 / f2][q] in X
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
-#pragma unroll
-      for (int q = 0; q < K1; ++q) {
-        double fo = 0.0, fn = 0.0;
-#pragma unroll
-        for (int j = 0; j < K1; ++j) {
-          const double ph = CB::phi[q][j];
-          const int node = ax ? (j + K1 * (side ? K : 0)) : ((side ? K : 0) + K1 * j);
-          fo = fma(ph, w[node], fo);
-          fn = fma(ph, nf[ax][side][j], fn);
-        }
-        if (!use_n[ax][side]) fn = (bc == 1) ? 0.0 : fo;   // exterior of zero inflow / continuous
-        if (in_grp) {
-          X[((side * 2 + 0) * K1 + q) * N + r] = side ? fo : fn;   // f1 (lower cell)
-          X[((side * 2 + 1) * K1 + q) * N + r] = side ? fn : fo;   // f2 (upper cell)
-        }
+      if (!usen[side]) {
+        fn = (bc == 1) ? 0.0 : fo;   // exterior of zero inflow / continuous
+        mn = 0.0;
+      }
+      dmu[q] = valid ? (side ? mn - mo : mo - mn) : 0.0;   // mu_2 - mu_1
+      if (in_grp) {
+        X[q * N + r] = side ? fo : fn;          // f1 (lower cell)
+        X[(K1 + q) * N + r] = side ? fn : fo;   // f2 (upper cell)
+        if constexpr (PART == 0) X[(2 * K1 + q) * N + r] = gw[q] * dmu[q];
       }
     }
     wave_sync();
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const int bc = side ? M.bc_hi[ax] : M.bc_lo[ax];
-      const bool valid = act && (side == 0 || (ia == na - 1 && bc != 0));
-      double dmu[K1];
+    const double* R1 = X;
+    const double* R2 = X + K1 * N;
+    if constexpr (PART == 0) {
+      // x face: dJ/dU_F = t_adv W (H(m) c1 + (1 - H(m)) c2), c = W^T f, paired
+      // with mu_2 - mu_1 over the lanes: sum_r dmu_r (W d)_r = sum_k d_k
+      // (W^T dmu)_k, so lane k forms d_k (W^T dmu)_k and the cell's
+      // reduction sums them (rows [2 K1, 3 K1) hold gw dmu)
+      const double* Rm = X + 2 * K1 * N;
+      double acc = 0.0;
 #pragma unroll
       for (int q = 0; q < K1; ++q) {
-        double mo = 0.0, mn = 0.0;
+        double c1 = 0.0, c2 = 0.0, cm = 0.0;
 #pragma unroll
-        for (int j = 0; j < K1; ++j) {
-          const double ph = CB::phi[q][j];
-          const int node = ax ? (j + K1 * (side ? K : 0)) : ((side ? K : 0) + K1 * j);
-          mo = fma(ph, m[node], mo);
-          mn = fma(ph, nm[ax][side][j], mn);
+        for (int j = 0; j <= LMAX; ++j) {
+          c1 = fma(wcol[j], R1[q * N + mem[j]], c1);
+          c2 = fma(wcol[j], R2[q * N + mem[j]], c2);
+          cm = fma(wcol[j], Rm[q * N + mem[j]], cm);
         }
-        if (!use_n[ax][side]) mn = 0.0;
-        dmu[q] = valid ? (side ? mn - mo : mo - mn) : 0.0;   // mu_2 - mu_1
+        const double h = heav(uxf[side] + t_adv * lam * vq[q]);
+        acc = fma(t_adv * (h * c1 + (1.0 - h) * c2), cm, acc);
       }
-      const double* R1 = X + (side * 2 + 0) * K1 * N;
-      const double* R2 = X + (side * 2 + 1) * K1 * N;
-      if (ax == 0) {
-        // x face: dJ/dU_F = t_adv W (H(m) c1 + (1 - H(m)) c2), c = W^T f
-        double d[K1];
+      red[K1 + side] = acc / s2hp;
+    } else {
+      // ln p face: dJ = dB_+ (f1 - f2) + dB f2 (dB f1 where B >= 0)
+      const int axc0 = T.ax_col[r], axc1 = T.ax_col[N + r];
+      const double axv0 = T.ax_val[r], axv1 = T.ax_val[N + r];
+      const int axxc0 = T.axx_col[r], axxc1 = T.axx_col[N + r];
+      const double axxv0 = T.axx_val[r], axxv1 = T.axx_val[N + r], axxv2 = T.axx_val[2 * N + r];
+      const double tmv = pr[12 + side];     // t_mom / V at this face
 #pragma unroll
-        for (int q = 0; q < K1; ++q) {
-          double c1 = 0.0, c2 = 0.0;
+      for (int q = 0; q < K1; ++q) {
+        const int code = F.pf_code[(size_t)(ip + side) * (nx * K1) + ix * K1 + q];
+        const double* Pu = (code == -1) ? R1 + q * N : R2 + q * N;
+        double ja = -t_mom * tmv * fma(axv0, Pu[axc0], axv1 * Pu[axc1]);
+        double ju = -t_mom * fma(axxv0, Pu[axxc0], fma(axxv1, Pu[r], axxv2 * Pu[axxc1]));
+        if (code >= 0) {
+          // dB_+ (f1 - f2) from the rows of the derivative tables of B_+
+          const double* ta = F.pf_dtab + ((size_t)code * 2 * N + r) * (LMAX + 1);
+          const double* tx = ta + (size_t)N * (LMAX + 1);
+          double dkA = 0.0, dkX = 0.0;
 #pragma unroll
-          for (int j = 0; j <= LMAX; ++j) {
-            c1 = fma(wcol[j], R1[q * N + mem[j]], c1);
-            c2 = fma(wcol[j], R2[q * N + mem[j]], c2);
+          for (int i = 0; i <= LMAX; ++i) {
+            const double dfi = R1[q * N + mem[i]] - R2[q * N + mem[i]];
+            dkA = fma(ta[i], dfi, dkA);
+            dkX = fma(tx[i], dfi, dkX);
           }
-          const double h = heav(xr[9 + side] + t_adv * lam * pr[0 + q]);
-          d[q] = t_adv * (h * c1 + (1.0 - h) * c2);
+          ja = fma(-t_mom * tmv, dkA, ja);
+          ju = fma(-t_mom, dkX, ju);
         }
-        wave_sync();
-        if (in_grp)
-#pragma unroll
-          for (int q = 0; q < K1; ++q) X[((side * 2 + 0) * K1 + q) * N + r] = d[q];
-        wave_sync();
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < K1; ++q) {
-          double dj = 0.0;
-#pragma unroll
-          for (int i = 0; i <= LMAX; ++i) dj = fma(wrow[i], R1[q * N + mem[i]], dj);
-          acc = fma(gw[q] * dmu[q], dj, acc);
-        }
-        if (in_grp) Rd[(S::XF + side) * N + r] = acc / s2hp;
-      } else {
-        // ln p face: dJ = dB_+ (f1 - f2) + dB f2 (dB f1 where B >= 0)
-        const double tmv = pr[12 + side];     // t_mom / V at this face
-#pragma unroll
-        for (int q = 0; q < K1; ++q) {
-          const int code = pcode[side][q];
-          const double* Pu = (code == -1) ? R1 + q * N : R2 + q * N;
-          double ja = -t_mom * tmv * fma(axv0, Pu[axc0], axv1 * Pu[axc1]);
-          double ju = -t_mom * fma(axxv0, Pu[axxc0], fma(axxv1, Pu[r], axxv2 * Pu[axxc1]));
-          if (code >= 0) {
-            // dB_+ (f1 - f2) from the rows of the derivative tables of B_+
-            const double* ta = F.pf_dtab + ((size_t)code * 2 * N + r) * (LMAX + 1);
-            const double* tx = ta + (size_t)N * (LMAX + 1);
-            double dkA = 0.0, dkX = 0.0;
-#pragma unroll
-            for (int i = 0; i <= LMAX; ++i) {
-              const double dfi = R1[q * N + mem[i]] - R2[q * N + mem[i]];
-              dkA = fma(ta[i], dfi, dkA);
-              dkX = fma(tx[i], dfi, dkX);
-            }
-            ja = fma(-t_mom * tmv, dkA, ja);
-            ju = fma(-t_mom, dkX, ju);
-          }
-          if (in_grp) {
-            Rd[(S::PF + side * 2 * K1 + 2 * q + 0) * N + r] = gw[q] * dmu[q] * ja / s2hx;
-            Rd[(S::PF + side * 2 * K1 + 2 * q + 1) * N + r] = gw[q] * dmu[q] * ju / s2hx;
-          }
-        }
+        red[2 * K1 + side * 2 * K1 + 2 * q + 0] = gw[q] * dmu[q] * ja / s2hx;
+        red[2 * K1 + side * 2 * K1 + 2 * q + 1] = gw[q] * dmu[q] * ju / s2hx;
       }
     }
     wave_sync();
   }
 
-  // ---- one reduction over the cell's lanes for every slot --------------------
+  // ---- one reduction over the cell's lanes for this part's slots
+  if (in_grp)
+#pragma unroll
+    for (int i = 0; i < FR::NRED; ++i) X[i * N + r] = red[i];
   wave_sync();
   if (act)
-    for (int o = r; o < NS; o += N) {
+    for (int j = r; j < FR::NRED; j += N) {
       double sum = 0.0;
-      for (int j = 0; j < N; ++j) sum += Rd[o * N + j];
-      slots[(size_t)cell * NS + o] += cdt * sum;
+      for (int l = 0; l < N; ++l) sum += X[j * N + l];
+      slots[(size_t)cell * NS + FR::slot(j)] += cdt * sum;
     }
+}
+
+// Both parts in one launch: even workgroups take part 0 and odd ones part 1
+// of the same cells, so that the two interleave on the machine (each is
+// bound by memory latency, not bandwidth).
+template <int K, int LMAX>
+__global__ __launch_bounds__(kFgThreads) __attribute__((amdgpu_waves_per_eu(VFP_FG_WAVES)))
+void fgrad_kernel(KernelArgs A, const double* __restrict__ mu, const double* __restrict__ fwd, double cdt,
+                  double* __restrict__ slots, const unsigned char* __restrict__ support) {
+  constexpr int N = (LMAX + 1) * (LMAX + 1);
+  constexpr int CPB = (kFgThreads / N) > 0 ? kFgThreads / N : 1;
+  constexpr int X0 = FgRows<K, 0>::XRW, X1 = FgRows<K, 1>::XRW;
+  __shared__ double lds[CPB * (X0 > X1 ? X0 : X1) * N];
+  const int blk = blockIdx.x >> 1;
+  if (blockIdx.x & 1)
+    fgrad_body<K, LMAX, 1>(A, mu, fwd, cdt, slots, support, lds, blk);
+  else
+    fgrad_body<K, LMAX, 0>(A, mu, fwd, cdt, slots, support, lds, blk);
 }
 
 // g_u, g_dudx, g_dudt at the nx (k+1) x Gauss points and g_uface at the nx+1
@@ -421,7 +422,7 @@ void launch_fg_t(const KernelArgs& a, const double* mu, const double* fwd, doubl
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int CPB = (kFgThreads / N) > 0 ? kFgThreads / N : 1;
   const int blocks = (a.mesh.ncells + CPB - 1) / CPB;
-  hipLaunchKernelGGL((fgrad_kernel<K, LMAX>), dim3(blocks), dim3(kFgThreads), 0, s, a, mu, fwd, cdt, slots,
+  hipLaunchKernelGGL((fgrad_kernel<K, LMAX>), dim3(2 * blocks), dim3(kFgThreads), 0, s, a, mu, fwd, cdt, slots,
                      support);
 }
 
