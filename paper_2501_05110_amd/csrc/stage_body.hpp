@@ -441,15 +441,22 @@ __device__ __forceinline__ void adj_flux_axis(const KernelArgs& A, const LaneRow
   contract_add<D, K, -1>(tmp, res, A.mesh.s2h[AX][ic[AX]]);
 }
 
-// At least two waves per SIMD: the 3-D, k = 2 instantiations otherwise take
-// every register for one wave (27 nodes per lane); the few spills cost less
-// than the lost latency hiding.
+// Waves per SIMD the register allocation aims for: two.  The 3-D, k = 2
+// instantiations (27 nodes per lane) need about 400 registers; at two waves
+// the excess goes to scratch memory (several GB of HBM traffic per launch at
+// 48^3 cells), at one wave to the accumulation registers, which measured
+// slower (less latency hiding).  VFP_GENERAL_WAVES_3D selects it for them.
 #ifndef VFP_GENERAL_WAVES
 #define VFP_GENERAL_WAVES 2
 #endif
+#ifndef VFP_GENERAL_WAVES_3D
+#define VFP_GENERAL_WAVES_3D 2
+#endif
+template <int D, int K>
+constexpr int general_waves() { return (D == 3 && K == 2) ? VFP_GENERAL_WAVES_3D : VFP_GENERAL_WAVES; }
 
 template <int D, int K, int LMAX, bool MOM, int FL, bool ADJ>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(VFP_GENERAL_WAVES)))
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(general_waves<D, K>())))
 void stage_kernel(KernelArgs A) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
