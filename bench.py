@@ -535,6 +535,20 @@ def main():
         print("state is not finite after the timed steps", file=sys.stderr)
         sys.exit(1)
 
+    # context for the roofline: what a plain streaming kernel (torch.mul on
+    # 1 GiB, reading 1 GiB and writing 1 GiB) reaches on this GPU
+    a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    torch.mul(a, 1.0, out=b)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(5):
+        torch.mul(a, 1.0, out=b)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 5 * 2 * a.numel() * 8 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del a, b
+
     secs = gpu_ms / 1e3
     launches = 4 * args.steps
     per_launch_s = secs / launches
@@ -567,7 +581,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
                      "kernel": "shock_kernel<2,3,1,false,false>",
-                     "bytes_per_launch": bytes_per_launch, "us_per_launch": per_launch_s * 1e6},
+                     "bytes_per_launch": bytes_per_launch, "us_per_launch": per_launch_s * 1e6,
+                     "copy_GBs": copy_gbs},
     }
     if not args.no_adjoint:
         out["adjoint"] = adjoint_timing()
