@@ -396,6 +396,15 @@ int vfp_reconstruct(const vfp_ctx* ctx, const double* zeta, const double* Y, int
 #define VFP_PRECOND_COLLISION 1   /* right preconditioner 1 / (1 + dt Theta nu_c l(l+1)/2) per
                                      DoF: the exact inverse of the scattering part of the
                                      system (the inverse mass reduces it to that factor) */
+#define VFP_PRECOND_XLINE     2   /* right preconditioner: the exact inverse of the system's
+                                     block-tridiagonal part along axis 0 (each cell's own
+                                     block and its blocks towards its two neighbours along
+                                     axis 0; a periodic wrap is left out), one block
+                                     recurrence per line of cells along axis 0.  The blocks
+                                     are taken from the operator itself at the start of the
+                                     call (3 ncolours (k+1)^d n stage applications) and
+                                     factorised on the device.  Needs (k+1)^d n <= 48 and
+                                     vfp_theta_precond_size extra doubles of work */
 
 typedef struct vfp_theta_opts {
   double theta;       /* in [0, 1]                                            */
@@ -415,9 +424,17 @@ typedef struct vfp_theta_stats {
  * (restart + 5) ndofs plus a fixed reduction area. */
 int vfp_theta_work_size(const vfp_ctx* ctx, int restart, int64_t* n);
 
+/* Extra doubles of work a preconditioner needs, after the vfp_theta_work_size
+ * part: 0 for VFP_PRECOND_NONE and VFP_PRECOND_COLLISION; for
+ * VFP_PRECOND_XLINE three b x b blocks per cell (b = (k+1)^d n) and a flag per
+ * line; VFP_EUNSUPPORTED where b > 48. */
+int vfp_theta_precond_size(const vfp_ctx* ctx, int precond, int64_t* n);
+
 /* Advance u (device, ndofs doubles, in place) by nsteps Theta-method steps.
- * work: device, at least vfp_theta_work_size doubles (work_len), disjoint
- * from u.  Unlike the other compute calls this one synchronises `stream`
+ * work: device, at least vfp_theta_work_size + vfp_theta_precond_size doubles
+ * (work_len), disjoint from u; with VFP_PRECOND_XLINE the call first builds
+ * the preconditioner for its dt and Theta (synchronising `stream` once) and
+ * fails with VFP_EDEVICE if a block is singular.  Unlike the other compute calls this one synchronises `stream`
  * once per Krylov iteration (the Hessenberg least-squares problem is solved
  * on the host; the first call on a context also allocates a 1.7 KB pinned
  * host buffer for those read-backs, kept until vfp_destroy).  stats (host,

@@ -25,7 +25,7 @@ DEVICE = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-munsafe-fp-atomics", "-ffp-contract=fast"]
 SOURCES = ["shtab.cpp", "vfp.cpp", "stage.hip", "stage_gen_1f.hip", "stage_gen_1a.hip", "stage_gen_2f.hip",
            "stage_gen_2a.hip", "stage_gen_3f.hip", "stage_gen_3a.hip", "stage_shock.hip", "stage_shock_shapes.hip", "stage_batch.hip", "stage_batch_shapes.hip", "field_grad.hip",
-           "krylov.hip", "reconstruct.hip", "noalloc.hip", "resident.hip"]
+           "krylov.hip", "reconstruct.hip", "noalloc.hip", "resident.hip", "xline.hip"]
 
 
 def _hipcc():

@@ -77,6 +77,19 @@ void kry_lincomb(double* out, double a, const double* x, double b, const double*
 void kry_coll_precond(double* out, const double* in, const double* nu, double nu0, const double* cval, double s,
                       int64_t ncells, int nb, int n, hipStream_t st);
 
+// Block-tridiagonal preconditioner along axis 0 (xline.hip).  Blocks of
+// b = nb n unknowns per cell (b <= kXlMaxBlock), three per cell, column-major:
+// D (own), L (towards ix - 1), U (towards ix + 1).  Lines are the cells
+// line nx .. line nx + nx - 1.  wrapc: axis 0 periodic with nx % 3 != 0 (the
+// last cell gets a colour of its own).
+constexpr int kXlMaxBlock = 48;
+void xl_probe_set(double* v, int64_t ndofs, int nx, int b, int wrapc, int color, int j, hipStream_t s);
+void xl_probe_get(const double* w, double* D, double* L, double* U, int64_t ndofs, int nx, int b, int wrapc,
+                  int color, int j, hipStream_t s);
+void xl_factor(double* D, const double* L, double* U, int nlines, int nx, int b, int* fail, hipStream_t s);
+void xl_apply(const double* r, double* x, const double* D, const double* L, const double* U, int nlines, int nx,
+              int b, hipStream_t s);
+
 // out[row][d] = sum_j zeta[row][j] Y[d][j] for rows x ndir outputs, n <= 64.
 void launch_reconstruct(const double* zeta, int64_t rows, int n, const double* Y, int64_t ndir, double* out,
                         hipStream_t s);

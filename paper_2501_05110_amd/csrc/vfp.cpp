@@ -1884,15 +1884,70 @@ int theta_op(vfp_ctx* c, const double* x, double* w, double dt, double theta, vo
 
 // One Theta step in place on u by restarted GMRES (iterate from u).
 // it: Krylov iterations (accumulated); res: final true relative residual.
+// The x-line preconditioner's blocks in the work tail (see xline.hip).
+struct XLine {
+  double *D = nullptr, *L = nullptr, *U = nullptr;
+  int* fail = nullptr;
+  int nx = 0, nlines = 0, b = 0, wrapc = 0;
+};
+
+XLine xline_layout(const vfp_ctx* c, double* tail) {
+  XLine x;
+  x.nx = c->ncell[0];
+  x.nlines = c->ncells / x.nx;
+  x.b = c->nb * c->n;
+  x.wrapc = (c->bc_lo[0] == VFP_BC_PERIODIC && x.nx % 3 != 0) ? 1 : 0;
+  const int64_t blk = (int64_t)c->ncells * x.b * x.b;
+  if (tail) {
+    x.D = tail;
+    x.L = tail + blk;
+    x.U = tail + 2 * blk;
+    x.fail = reinterpret_cast<int*>(tail + 3 * blk);
+  }
+  return x;
+}
+
+int64_t xline_len(const vfp_ctx* c) {
+  const XLine x = xline_layout(c, nullptr);
+  return 3 * (int64_t)c->ncells * x.b * x.b + (x.nlines + 1) / 2 + 1;
+}
+
+// Blocks of A = I - dt Theta L0 by probing (one colour and one local unknown
+// at a time, into t.z, output in t.w), then the block factorisation per line.
+int xline_build(vfp_ctx* c, const XLine& x, double dt, double theta, const ThetaWork& t, int64_t N, void* stream) {
+  hipStream_t st = (hipStream_t)stream;
+  const int ncol = x.wrapc ? 4 : std::min(3, x.nx);
+  // the coupling blocks stay zero where no neighbour exists
+  HIP_TRY(hipMemsetAsync(x.L, 0, (size_t)c->ncells * x.b * x.b * sizeof(double), st));
+  HIP_TRY(hipMemsetAsync(x.U, 0, (size_t)c->ncells * x.b * x.b * sizeof(double), st));
+  for (int col = 0; col < ncol; ++col)
+    for (int j = 0; j < x.b; ++j) {
+      xl_probe_set(t.z, N, x.nx, x.b, x.wrapc, col, j, st);
+      if (int e = theta_op(c, t.z, t.w, dt, theta, stream)) return e;
+      xl_probe_get(t.w, x.D, x.L, x.U, N, x.nx, x.b, x.wrapc, col, j, st);
+    }
+  xl_factor(x.D, x.L, x.U, x.nlines, x.nx, x.b, x.fail, st);
+  HIP_TRY(hipGetLastError());
+  std::vector<int> fl(x.nlines);
+  HIP_TRY(hipMemcpyAsync(fl.data(), x.fail, x.nlines * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  for (int l = 0; l < x.nlines; ++l)
+    if (fl[l]) return fail(VFP_EDEVICE, "x-line preconditioner: singular block on line %d", l);
+  return VFP_OK;
+}
+
 int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const ThetaWork& t, int64_t N,
-               bool have_s, void* stream, int64_t& it, double& res, bool& conv) {
+               bool have_s, const XLine& xl, void* stream, int64_t& it, double& res, bool& conv) {
   hipStream_t st = (hipStream_t)stream;
   const int m = o.restart;
   const double th = o.theta;
-  const bool pre = o.precond == VFP_PRECOND_COLLISION;
+  const bool pre = o.precond != VFP_PRECOND_NONE;
   const double sp = dt * th * ((c->terms & VFP_TERM_COLLISION) ? 1.0 : 0.0);
   auto precond = [&](double* out, const double* in) {
-    kry_coll_precond(out, in, c->fld.nu_cell, c->fld.nu0, c->tab.c_val, sp, c->ncells, c->nb, c->n, st);
+    if (o.precond == VFP_PRECOND_XLINE)
+      xl_apply(in, out, xl.D, xl.L, xl.U, xl.nlines, xl.nx, xl.b, st);
+    else
+      kry_coll_precond(out, in, c->fld.nu_cell, c->fld.nu0, c->tab.c_val, sp, c->ncells, c->nb, c->n, st);
   };
   // right-hand side b = u + dt (1 - Theta) L(u) + dt Theta M^{-1} h
   if (th < 1.0) {
@@ -2051,6 +2106,21 @@ int vfp_theta_work_size(const vfp_ctx* c, int restart, int64_t* n) {
   return VFP_OK;
 }
 
+int vfp_theta_precond_size(const vfp_ctx* c, int precond, int64_t* n) {
+  if (int e = check_ready(c)) return e;
+  if (!n) return fail(VFP_EINVAL, "null argument");
+  *n = 0;
+  if (precond == VFP_PRECOND_XLINE) {
+    const int b = c->nb * c->n;
+    if (b > kXlMaxBlock)
+      return fail(VFP_EUNSUPPORTED, "x-line preconditioner: %d unknowns per cell (at most %d)", b, kXlMaxBlock);
+    *n = xline_len(c);
+  } else if (precond != VFP_PRECOND_NONE && precond != VFP_PRECOND_COLLISION) {
+    return fail(VFP_EINVAL, "precond %d unknown", precond);
+  }
+  return VFP_OK;
+}
+
 int vfp_theta_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, const vfp_theta_opts* o, double* work,
                       int64_t work_len, vfp_theta_stats* stats, void* stream) {
   if (int e = check_ready(c)) return e;
@@ -2061,16 +2131,23 @@ int vfp_theta_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, const vf
   if (o->max_iters < 1) return fail(VFP_EINVAL, "max_iters must be >= 1");
   if (o->precond == VFP_PRECOND_COLLISION && c->have_nu_pts)
     return fail(VFP_EUNSUPPORTED, "the collision preconditioner needs nu per cell (not at the points)");
-  if (o->precond != VFP_PRECOND_NONE && o->precond != VFP_PRECOND_COLLISION)
+  if (o->precond != VFP_PRECOND_NONE && o->precond != VFP_PRECOND_COLLISION && o->precond != VFP_PRECOND_XLINE)
     return fail(VFP_EINVAL, "precond %d unknown", o->precond);
   if (nsteps < 0 || !std::isfinite(dt)) return fail(VFP_EINVAL, "bad dt / nsteps");
+  int64_t pc_len = 0;
+  if (int e = vfp_theta_precond_size(c, o->precond, &pc_len)) return e;
   int64_t N = 0;
   vfp_ndofs(c, &N);
-  const int64_t need = theta_work_len(N, o->restart);
+  const int64_t need = theta_work_len(N, o->restart) + pc_len;
   if (work_len < need) return fail(VFP_EINVAL, "work holds %lld doubles, %lld needed", (long long)work_len,
                                    (long long)need);
   if (overlaps(u, N, work, need)) return fail(VFP_EINVAL, "work overlaps u");
   const ThetaWork t = theta_split(work, N, o->restart);
+  XLine xl;
+  if (o->precond == VFP_PRECOND_XLINE && nsteps > 0 && o->theta > 0.0) {
+    xl = xline_layout(c, work + theta_work_len(N, o->restart));
+    if (int e = xline_build(c, xl, dt, o->theta, t, N, stream)) return e;
+  }
   hipStream_t st = (hipStream_t)stream;
   if (!c->h_kry.p && hipHostMalloc((void**)&c->h_kry.p, 3 * kKryMaxVectors * sizeof(double), hipHostMallocDefault) !=
                          hipSuccess) {
@@ -2089,7 +2166,7 @@ int vfp_theta_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, const vf
   for (int64_t n = 0; n < nsteps; ++n) {
     double res = 0.0;
     bool conv = false;
-    if (int e = theta_step(c, u, dt, *o, t, N, have_s, stream, it, res, conv)) return e;
+    if (int e = theta_step(c, u, dt, *o, t, N, have_s, xl, stream, it, res, conv)) return e;
     worst = std::max(worst, res);
     all = all && conv;
   }

@@ -1,0 +1,248 @@
+// Block-tridiagonal ("x-line") preconditioner for the Theta-method system
+// A = I - dt Theta L0 (eq. system-matrix-rhs after the cell-wise inverse
+// mass).  A couples a cell only to its face neighbours; keeping, for every
+// cell, the block acting on its own unknowns and the two blocks acting on
+// its neighbours along axis 0 gives a block-tridiagonal matrix per line of
+// cells along axis 0 (cells ix = 0 .. nx-1 at fixed indices of the other
+// axes), which a block Thomas recurrence inverts exactly.  Upwinding along
+// axis 0 at large Courant numbers (the transport that makes the unpreconditioned
+// GMRES slow) is then solved directly; the coupling along the other axes, and
+// across a periodic wrap of axis 0, is left to the Krylov iteration.
+//
+// Blocks are extracted from the operator itself, with no assembly: with a
+// unit vector e_j in the local unknown j of every cell of one colour (colour
+// ix mod 3, so no two cells of one colour are neighbours along axis 0, and
+// cells of one colour differ in ix from every neighbour along the other
+// axes), A's output at a coloured cell is column j of its own block, and at
+// its neighbours along axis 0 column j of their blocks towards it.
+//
+// Storage per cell, b = (k+1)^d n unknowns: three b x b blocks, column-major
+// (entry (row, col) at col b + row): D (own), L (towards ix - 1), U (towards
+// ix + 1).  xl_factor overwrites D with S^{-1} and U with G = S^{-1} U, where
+// S_i = D_i - L_i G_{i-1} (block LU along the line, pivoting inside each
+// block by Gauss-Jordan with partial pivoting).
+#include <hip/hip_runtime.h>
+
+#include "launch.hpp"
+
+namespace vfp {
+namespace {
+
+constexpr int kXlThreads = 256;
+constexpr int kXlApplyThreads = 64;
+
+__device__ __forceinline__ int xl_color(int ix, int nx, int wrapc) { return (wrapc && ix == nx - 1) ? 3 : ix % 3; }
+
+__global__ __launch_bounds__(kXlThreads) void xl_probe_set_kernel(double* v, int64_t ndofs, int nx, int b, int wrapc,
+                                                                 int color, int j) {
+  const int64_t t = (int64_t)blockIdx.x * kXlThreads + threadIdx.x;
+  if (t >= ndofs) return;
+  const int64_t cell = t / b;
+  const int loc = (int)(t - cell * b);
+  const int ix = (int)(cell % nx);
+  v[t] = (loc == j && xl_color(ix, nx, wrapc) == color) ? 1.0 : 0.0;
+}
+
+__global__ __launch_bounds__(kXlThreads) void xl_probe_get_kernel(const double* __restrict__ w, double* D, double* L,
+                                                                 double* U, int64_t ndofs, int nx, int b, int wrapc,
+                                                                 int color, int j) {
+  const int64_t t = (int64_t)blockIdx.x * kXlThreads + threadIdx.x;
+  if (t >= ndofs) return;
+  const int64_t cell = t / b;
+  const int row = (int)(t - cell * b);
+  const int ix = (int)(cell % nx);
+  if (xl_color(ix, nx, wrapc) != color) return;
+  const int64_t bb = (int64_t)b * b;
+  D[cell * bb + (int64_t)j * b + row] = w[t];
+  if (ix + 1 < nx) L[(cell + 1) * bb + (int64_t)j * b + row] = w[t + b];   // A(ix+1, ix) e_j
+  if (ix > 0) U[(cell - 1) * bb + (int64_t)j * b + row] = w[t - b];        // A(ix-1, ix) e_j
+}
+
+// In-place inverse of the b x b matrix S (column-major, in LDS) by
+// Gauss-Jordan elimination with partial pivoting; every thread of the
+// workgroup takes part.  Returns false (to every thread) if a pivot is 0.
+__device__ bool xl_invert(double* S, int b, int* perm, int* sh_piv, double* sh_val) {
+  const int tid = threadIdx.x;
+  bool ok = true;
+  for (int k = 0; k < b; ++k) {
+    if (tid == 0) {
+      int p = k;
+      double best = fabs(S[k * b + k]);
+      for (int r = k + 1; r < b; ++r) {
+        const double a = fabs(S[k * b + r]);
+        if (a > best) {
+          best = a;
+          p = r;
+        }
+      }
+      perm[k] = p;
+      *sh_piv = p;
+    }
+    __syncthreads();
+    const int p = *sh_piv;
+    if (p != k)
+      for (int c = tid; c < b; c += blockDim.x) {
+        const double a = S[c * b + k];
+        S[c * b + k] = S[c * b + p];
+        S[c * b + p] = a;
+      }
+    __syncthreads();
+    if (tid == 0) *sh_val = S[k * b + k];
+    __syncthreads();
+    const double pv = *sh_val;
+    if (pv == 0.0) ok = false;
+    const double ipv = 1.0 / pv;
+    // row k scaled: S[k][k] = 1/pv, S[k][c] /= pv
+    for (int c = tid; c < b; c += blockDim.x) S[c * b + k] = (c == k) ? ipv : S[c * b + k] * ipv;
+    __syncthreads();
+    // the other rows: S[r][c] -= S[r][k] S[k][c] (c != k), then S[r][k] = -S[r][k] / pv
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      const int c = e / b, r = e - c * b;
+      if (r != k && c != k) S[e] = fma(-S[k * b + r], S[c * b + k], S[e]);
+    }
+    __syncthreads();
+    for (int r = tid; r < b; r += blockDim.x)
+      if (r != k) S[k * b + r] = -S[k * b + r] * ipv;
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = b - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int r = tid; r < b; r += blockDim.x) {
+        const double a = S[k * b + r];
+        S[k * b + r] = S[p * b + r];
+        S[p * b + r] = a;
+      }
+    __syncthreads();
+  }
+  return ok;
+}
+
+// One workgroup per line: S_i = D_i - L_i G_{i-1}, D_i <- S_i^{-1},
+// U_i <- G_i = S_i^{-1} U_i.  fail[line] = 1 if a block was singular.
+__global__ __launch_bounds__(kXlThreads) void xl_factor_kernel(double* D, const double* L, double* U, int nx, int b,
+                                                              int* fail) {
+  __shared__ double S[kXlMaxBlock * kXlMaxBlock];
+  __shared__ double G[kXlMaxBlock * kXlMaxBlock];
+  __shared__ int perm[kXlMaxBlock];
+  __shared__ int sh_piv;
+  __shared__ double sh_val;
+  const int tid = threadIdx.x;
+  const int line = blockIdx.x;
+  const int64_t bb = (int64_t)b * b;
+  bool ok = true;
+  for (int i = 0; i < nx; ++i) {
+    const int64_t cell = (int64_t)line * nx + i;
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      double s = D[cell * bb + e];
+      if (i > 0) {
+        // (L G)[r][c] = sum_k L[r][k] G[k][c]
+        const int c = e / b, r = e - c * b;
+        const double* Lc = L + cell * bb;
+        double acc = 0.0;
+        for (int k = 0; k < b; ++k) acc = fma(Lc[k * b + r], G[c * b + k], acc);
+        s -= acc;
+      }
+      S[e] = s;
+    }
+    __syncthreads();
+    ok = xl_invert(S, b, perm, &sh_piv, &sh_val) && ok;
+    for (int e = tid; e < b * b; e += blockDim.x) D[cell * bb + e] = S[e];
+    if (i + 1 < nx) {
+      const double* Uc = U + cell * bb;
+      for (int e = tid; e < b * b; e += blockDim.x) {
+        const int c = e / b, r = e - c * b;
+        double acc = 0.0;
+        for (int k = 0; k < b; ++k) acc = fma(S[k * b + r], Uc[c * b + k], acc);
+        G[e] = acc;
+      }
+      __syncthreads();
+      for (int e = tid; e < b * b; e += blockDim.x) U[cell * bb + e] = G[e];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) fail[line] = ok ? 0 : 1;
+}
+
+// x = P^{-1} r along each line (x may be r): forward y_i = S_i^{-1}(r_i -
+// L_i y_{i-1}), backward x_i = y_i - G_i x_{i+1}.  One 64-lane workgroup per
+// line, lane = row; the next cell's block columns are loaded while the
+// current cell is worked on.
+__global__ __launch_bounds__(kXlApplyThreads) void xl_apply_kernel(const double* r, double* x,
+                                                                  const double* __restrict__ D,
+                                                                  const double* __restrict__ L,
+                                                                  const double* __restrict__ U, int nx, int b) {
+  __shared__ double v[kXlMaxBlock];
+  const int row = threadIdx.x;
+  const bool on = row < b;
+  const int line = blockIdx.x;
+  const int64_t bb = (int64_t)b * b;
+  const int64_t c0 = (int64_t)line * nx;
+  double prev = 0.0;     // y_{i-1} at this row
+  for (int i = 0; i < nx; ++i) {
+    const int64_t cell = c0 + i;
+    double t = on ? r[cell * b + row] : 0.0;
+    if (i > 0) {
+      __syncthreads();
+      if (on) v[row] = prev;
+      __syncthreads();
+      if (on) {
+        const double* Lc = L + cell * bb;
+        double acc = 0.0;
+        for (int k = 0; k < b; ++k) acc = fma(Lc[k * b + row], v[k], acc);
+        t -= acc;
+      }
+    }
+    __syncthreads();
+    if (on) v[row] = t;
+    __syncthreads();
+    double y = 0.0;
+    if (on) {
+      const double* Dc = D + cell * bb;
+      for (int k = 0; k < b; ++k) y = fma(Dc[k * b + row], v[k], y);
+      x[cell * b + row] = y;
+    }
+    prev = y;
+  }
+  // backward: prev holds x_{nx-1} = y_{nx-1}
+  for (int i = nx - 2; i >= 0; --i) {
+    const int64_t cell = c0 + i;
+    __syncthreads();
+    if (on) v[row] = prev;
+    __syncthreads();
+    if (on) {
+      const double* Gc = U + cell * bb;
+      double acc = 0.0;
+      for (int k = 0; k < b; ++k) acc = fma(Gc[k * b + row], v[k], acc);
+      prev = x[cell * b + row] - acc;
+      x[cell * b + row] = prev;
+    }
+  }
+}
+
+}  // namespace
+
+void xl_probe_set(double* v, int64_t ndofs, int nx, int b, int wrapc, int color, int j, hipStream_t s) {
+  const int64_t blocks = (ndofs + kXlThreads - 1) / kXlThreads;
+  hipLaunchKernelGGL(xl_probe_set_kernel, dim3((unsigned)blocks), dim3(kXlThreads), 0, s, v, ndofs, nx, b, wrapc,
+                     color, j);
+}
+
+void xl_probe_get(const double* w, double* D, double* L, double* U, int64_t ndofs, int nx, int b, int wrapc,
+                  int color, int j, hipStream_t s) {
+  const int64_t blocks = (ndofs + kXlThreads - 1) / kXlThreads;
+  hipLaunchKernelGGL(xl_probe_get_kernel, dim3((unsigned)blocks), dim3(kXlThreads), 0, s, w, D, L, U, ndofs, nx, b,
+                     wrapc, color, j);
+}
+
+void xl_factor(double* D, const double* L, double* U, int nlines, int nx, int b, int* fail, hipStream_t s) {
+  hipLaunchKernelGGL(xl_factor_kernel, dim3(nlines), dim3(kXlThreads), 0, s, D, L, U, nx, b, fail);
+}
+
+void xl_apply(const double* r, double* x, const double* D, const double* L, const double* U, int nlines, int nx,
+              int b, hipStream_t s) {
+  hipLaunchKernelGGL(xl_apply_kernel, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
+}
+
+}  // namespace vfp

@@ -89,6 +89,7 @@ def load(path: str = None):
         "vfp_sh_eval": (I, [I, L, dp, dp, dp]),
         "vfp_reconstruct": (I, [P, P, P, L, P, P]),
         "vfp_theta_work_size": (I, [P, I, C.POINTER(L)]),
+        "vfp_theta_precond_size": (I, [P, I, C.POINTER(L)]),
         "vfp_theta_advance": (I, [P, P, D, L, C.POINTER(ThetaOpts), P, L, C.POINTER(ThetaStats), P]),
         "vfp_batch_create": (I, [C.POINTER(P), C.POINTER(P), I, U]),
         "vfp_batch_destroy": (None, [P]),
@@ -117,7 +118,8 @@ def exported_symbols():
             "vfp_batch_create", "vfp_batch_destroy", "vfp_batch_bind", "vfp_batch_advance",
             "vfp_batch_autotune", "vfp_batch_nclasses", "vfp_batch_class_info",
             "vfp_field_grad_size", "vfp_field_grad_support", "vfp_field_grad_stage", "vfp_field_grad_reduce",
-            "vfp_theta_work_size", "vfp_theta_advance", "vfp_sh_eval", "vfp_reconstruct"]
+            "vfp_theta_work_size", "vfp_theta_precond_size", "vfp_theta_advance", "vfp_sh_eval",
+            "vfp_reconstruct"]
 
 
 def _check(rc):
@@ -403,17 +405,24 @@ class Operator:
         _check(_lib.vfp_theta_work_size(self._ctx, int(restart), C.byref(n)))
         return n.value
 
+    def theta_precond_size(self, precond):
+        n = C.c_int64()
+        pc = {None: 0, "none": 0, "collision": 1, "xline": 2}.get(precond, precond)
+        _check(_lib.vfp_theta_precond_size(self._ctx, int(pc), C.byref(n)))
+        return n.value
+
     def theta_advance(self, u, dt, nsteps, theta=0.5, tol=1e-12, restart=30, max_iters=1000, work=None,
                       precond=None, stream=None):
         """nsteps Theta-method steps in place on u (vfp_theta_advance);
         returns {"iterations", "residual", "converged"}.  work: device
-        tensor of >= theta_work_size(restart) doubles (allocated if None);
-        precond: None or "collision" (VFP_PRECOND_COLLISION)."""
+        tensor of >= theta_work_size(restart) + theta_precond_size(precond)
+        doubles (allocated if None); precond: None, "collision"
+        (VFP_PRECOND_COLLISION) or "xline" (VFP_PRECOND_XLINE)."""
         import torch
-        need = self.theta_work_size(restart)
+        pc = {None: 0, "none": 0, "collision": 1, "xline": 2}.get(precond, precond)
+        need = self.theta_work_size(restart) + self.theta_precond_size(pc)
         if work is None:
             work = torch.empty(need, dtype=torch.float64, device=u.device)
-        pc = {None: 0, "none": 0, "collision": 1}.get(precond, precond)
         opts = ThetaOpts(float(theta), float(tol), int(restart), int(max_iters), int(pc))
         st = ThetaStats()
         _check(_lib.vfp_theta_advance(self._ctx, self._t(u, "u"), float(dt), int(nsteps), C.byref(opts),
