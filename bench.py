@@ -259,6 +259,55 @@ def batch_timing(full=False, steps=None):
                     "per run"}
 
 
+def dsa_paper_timing():
+    """The run of Sec. 4.4 on the paper's grid (410 x 256 cells, k = 1,
+    1,679,360 DoF) by implicit steps with the x-line preconditioner: Crank-
+    Nicolson with the paper's dt = 1 (20 steps from f = 0), and backward Euler
+    with dt = 1e7 until the state is stationary (the steady state whose
+    spectrum the paper reports; tests/test_gpu_dsa.py checks it against the
+    oracle's)."""
+    import torch
+    from paper_2501_05110_amd import vfp, workloads as W
+
+    wl = W.paper_dsa_workload()
+    t0 = time.perf_counter()
+    op = vfp.Operator(wl)
+    t_setup = time.perf_counter() - t0
+    N = op.ndofs
+    work = torch.empty(op.theta_work_size(64) + op.theta_precond_size("xline"), dtype=torch.float64, device="cuda")
+    u = torch.zeros(N, dtype=torch.float64, device="cuda")
+    op.theta_advance(u, 1.0, 1, theta=0.5, tol=1e-10, restart=40, max_iters=400, work=work, precond="xline")
+    u.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cn = op.theta_advance(u, 1.0, 20, theta=0.5, tol=1e-10, restart=40, max_iters=400, work=work, precond="xline")
+    torch.cuda.synchronize()
+    t_cn = (time.perf_counter() - t0) / 20
+    u.zero_()
+    prev = u.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    its, steps = 0, 0
+    for steps in range(1, 13):
+        st = op.theta_advance(u, 1e7, 1, theta=1.0, tol=1e-11, restart=64, max_iters=3000, work=work,
+                              precond="xline")
+        its += st["iterations"]
+        change = float((u - prev).abs().max() / u.abs().max())
+        prev.copy_(u)
+        if change == 0.0:
+            break
+    torch.cuda.synchronize()
+    t_ss = time.perf_counter() - t0
+    op.close()
+    return {"workload": wl.name, "ndofs": N, "setup_s": t_setup,
+            "crank_nicolson_dt1": {"s_per_step": t_cn, "iterations_per_step": cn["iterations"] / 20,
+                                   "converged": cn["converged"]},
+            "steady_state_backward_euler_dt1e7": {"steps": steps, "iterations": its, "s": t_ss,
+                                                  "stationary": change == 0.0},
+            "note": "x-line block-tridiagonal preconditioner (VFP_PRECOND_XLINE), GMRES restart 40/64, "
+                    "tol 1e-10 / 1e-11"}
+
+
 def extension_timing():
     """The rows beyond the explicit (x, ln p) path, each with its HBM roofline
     fraction (algorithmic bytes per launch / launch time / 8 TB/s):
@@ -594,6 +643,7 @@ def main():
         out["other_configs"] = other_configs()
     if not args.no_theta:
         out["theta"] = theta_timing()
+        out["dsa_paper"] = dsa_paper_timing()
     if not args.no_other:
         out["extensions"] = extension_timing()
     if not args.no_cpu:

@@ -166,9 +166,34 @@ __global__ __launch_bounds__(kXlThreads) void xl_factor_kernel(double* D, const 
 }
 
 // x = P^{-1} r along each line (x may be r): forward y_i = S_i^{-1}(r_i -
-// L_i y_{i-1}), backward x_i = y_i - G_i x_{i+1}.  One 64-lane workgroup per
-// line, lane = row; the next cell's block columns are loaded while the
-// current cell is worked on.
+// L_i y_{i-1}), backward x_i = y_i - G_i x_{i+1}.  One 64-lane workgroup (one
+// wavefront, so LDS ordering needs only a wavefront-level fence) per line,
+// lane = row.  The recurrence is a chain of dependent block products, so the
+// kernel is bound by latency: each lane keeps its rows of the next cell's
+// blocks in registers (BM >= b entries per block), loaded while the current
+// cell is worked on, and the products run as four interleaved partial sums.
+__device__ __forceinline__ void xl_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int BM>
+__device__ __forceinline__ double xl_rowdot(const double (&m)[BM], const double* v, int b) {
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < BM; ++k)
+    if (k < b) a[k & 3] = fma(m[k], v[k], a[k & 3]);
+  return (a[0] + a[1]) + (a[2] + a[3]);
+}
+
+template <int BM>
+__device__ __forceinline__ void xl_load_row(double (&m)[BM], const double* blk, int row, int b, bool on) {
+#pragma unroll
+  for (int k = 0; k < BM; ++k) m[k] = (on && k < b) ? blk[k * b + row] : 0.0;
+}
+
+template <int BM>
 __global__ __launch_bounds__(kXlApplyThreads) void xl_apply_kernel(const double* r, double* x,
                                                                   const double* __restrict__ D,
                                                                   const double* __restrict__ L,
@@ -179,45 +204,58 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply_kernel(const double*
   const int line = blockIdx.x;
   const int64_t bb = (int64_t)b * b;
   const int64_t c0 = (int64_t)line * nx;
+  double mL[BM] = {}, mD[BM], nL[BM] = {}, nD[BM] = {};
+  xl_load_row<BM>(mD, D + c0 * bb, row, b, on);
+  double rc = on ? r[c0 * b + row] : 0.0;
   double prev = 0.0;     // y_{i-1} at this row
   for (int i = 0; i < nx; ++i) {
     const int64_t cell = c0 + i;
-    double t = on ? r[cell * b + row] : 0.0;
+    // the next cell's rows and right-hand side, in flight during this cell
+    double rn = 0.0;
+    if (i + 1 < nx) {
+      xl_load_row<BM>(nL, L + (cell + 1) * bb, row, b, on);
+      xl_load_row<BM>(nD, D + (cell + 1) * bb, row, b, on);
+      rn = on ? r[(cell + 1) * b + row] : 0.0;
+    }
+    double t = rc;
     if (i > 0) {
-      __syncthreads();
-      if (on) v[row] = prev;
-      __syncthreads();
-      if (on) {
-        const double* Lc = L + cell * bb;
-        double acc = 0.0;
-        for (int k = 0; k < b; ++k) acc = fma(Lc[k * b + row], v[k], acc);
-        t -= acc;
-      }
+      xl_wave_sync();
+      v[row] = prev;
+      xl_wave_sync();
+      t -= xl_rowdot<BM>(mL, v, b);
     }
-    __syncthreads();
-    if (on) v[row] = t;
-    __syncthreads();
-    double y = 0.0;
-    if (on) {
-      const double* Dc = D + cell * bb;
-      for (int k = 0; k < b; ++k) y = fma(Dc[k * b + row], v[k], y);
-      x[cell * b + row] = y;
-    }
+    xl_wave_sync();
+    v[row] = t;
+    xl_wave_sync();
+    const double y = xl_rowdot<BM>(mD, v, b);
+    if (on) x[cell * b + row] = y;
     prev = y;
+#pragma unroll
+    for (int k = 0; k < BM; ++k) {
+      mL[k] = nL[k];
+      mD[k] = nD[k];
+    }
+    rc = rn;
   }
   // backward: prev holds x_{nx-1} = y_{nx-1}
+  double mG[BM] = {}, nG[BM] = {};
+  if (nx >= 2) xl_load_row<BM>(mG, U + (c0 + nx - 2) * bb, row, b, on);
+  double yc = (nx >= 2 && on) ? x[(c0 + nx - 2) * b + row] : 0.0;
   for (int i = nx - 2; i >= 0; --i) {
     const int64_t cell = c0 + i;
-    __syncthreads();
-    if (on) v[row] = prev;
-    __syncthreads();
-    if (on) {
-      const double* Gc = U + cell * bb;
-      double acc = 0.0;
-      for (int k = 0; k < b; ++k) acc = fma(Gc[k * b + row], v[k], acc);
-      prev = x[cell * b + row] - acc;
-      x[cell * b + row] = prev;
+    double yn = 0.0;
+    if (i >= 1) {
+      xl_load_row<BM>(nG, U + (cell - 1) * bb, row, b, on);
+      yn = on ? x[(cell - 1) * b + row] : 0.0;
     }
+    xl_wave_sync();
+    v[row] = prev;
+    xl_wave_sync();
+    prev = yc - xl_rowdot<BM>(mG, v, b);
+    if (on) x[cell * b + row] = prev;
+#pragma unroll
+    for (int k = 0; k < BM; ++k) mG[k] = nG[k];
+    yc = yn;
   }
 }
 
@@ -242,7 +280,13 @@ void xl_factor(double* D, const double* L, double* U, int nlines, int nx, int b,
 
 void xl_apply(const double* r, double* x, const double* D, const double* L, const double* U, int nlines, int nx,
               int b, hipStream_t s) {
-  hipLaunchKernelGGL(xl_apply_kernel, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
+  if (b <= 16)
+    hipLaunchKernelGGL(xl_apply_kernel<16>, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
+  else if (b <= 32)
+    hipLaunchKernelGGL(xl_apply_kernel<32>, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
+  else
+    hipLaunchKernelGGL(xl_apply_kernel<kXlMaxBlock>, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx,
+                       b);
 }
 
 }  // namespace vfp

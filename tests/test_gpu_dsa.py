@@ -6,6 +6,7 @@ within 2 %.  Scattering nu = 10 shortens the acceleration time (kappa =
 V^2/(3 nu)) while keeping the shock width w far below kappa/U."""
 
 import math
+import os
 
 import numpy as np
 import pytest
@@ -125,3 +126,64 @@ def test_paper_grid_full_size_sampled_rows(lib, cuda):
     err = rel_inf(got[cells], want[cells])
     _say(f"[dsa paper grid] {wl.name}: ndofs={wl.ndofs}, {len(cells)} sampled cells rel_inf={err:.3e}")
     assert err <= APPLY_TOL
+
+
+def _golden_dsa():
+    out = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "dsa_paper_steady.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split()
+                out[k] = float(v)
+    return out
+
+
+def test_paper_run_by_implicit_steps(lib, cuda):
+    """The run of Sec. 4.4 on the paper's own grid (410 x 256 cells, k = 1,
+    1,679,360 DoF) advanced by the library's implicit steps with the x-line
+    preconditioner: Crank-Nicolson with the paper's dt = 1 from f = 0 (every
+    step converged), then backward Euler with dt = 1e7 until the state stops
+    changing; the spectrum at the shock then has the index and normalisation
+    of the oracle's steady state on the same grid (tests/golden,
+    make_dsa_paper_steady.py) and, within the spread of the grids, the
+    paper's printed |alpha - 4| = 1.5e-3 and N = 12.14."""
+    import time
+    import torch
+    from oracle import dsa_paper
+    from paper_2501_05110_amd.vfp import Operator
+    wl = W.paper_dsa_workload()
+    op = Operator(wl)
+    N = op.ndofs
+    work = torch.empty(op.theta_work_size(64) + op.theta_precond_size("xline"), dtype=torch.float64,
+                       device="cuda")
+    u = torch.zeros(N, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = op.theta_advance(u, 1.0, 10, theta=0.5, tol=1e-10, restart=40, max_iters=400, work=work, precond="xline")
+    torch.cuda.synchronize()
+    t_cn = (time.perf_counter() - t0) / 10
+    _say(f"[dsa paper run] {wl.name}: Crank-Nicolson dt=1: {st['iterations'] / 10:.1f} iterations and "
+         f"{t_cn * 1e3:.1f} ms per step")
+    assert st["converged"] and st["iterations"] <= 10 * 15
+    prev = u.clone()
+    for n in range(12):
+        st = op.theta_advance(u, 1e7, 1, theta=1.0, tol=1e-11, restart=64, max_iters=3000, work=work,
+                              precond="xline")
+        assert st["converged"]
+        torch.cuda.synchronize()
+        d = float((u - prev).abs().max() / u.abs().max())
+        prev.copy_(u)
+        if d == 0.0:
+            break
+    _say(f"   backward Euler dt=1e7: stationary after {n + 1} steps")
+    assert d == 0.0
+    p, f = dsa_paper.spectrum_at_shock(wl, u.cpu().numpy())
+    a, Nn = dsa_paper.index_and_normalisation(p, f)
+    g = _golden_dsa()
+    _say(f"   |alpha - 4| = {abs(a - 4):.4e} (oracle {abs(g['alpha'] - 4):.4e}, paper 1.5e-3), "
+         f"N = {Nn:.5f} (oracle {g['N']:.5f}, paper 12.14)")
+    # each implicit step is solved to a relative residual of 1e-11 and the
+    # oracle's steady state by sparse LU: the states differ by ~1e-9, the
+    # index and normalisation read off them by ~1e-8
+    assert abs(a - g["alpha"]) <= 1e-6 and abs(Nn / g["N"] - 1) <= 1e-6
+    assert abs(abs(a - 4) - 1.5e-3) < 1e-3 and abs(Nn - 12.14) < 0.1
