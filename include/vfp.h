@@ -229,7 +229,11 @@ int vfp_stage(vfp_ctx* ctx, const double* w_in, const double* u, double* w_out,
  * (the four-stage form w_i = u + c_i dt L(w_{i-1}), c = 1/4, 1/3, 1/2, 1,
  * whose step map on this linear, autonomous system is the degree-4 Taylor
  * polynomial of exp(dt L), as for classical RK4).  work: device scratch of
- * 2*ndofs doubles.  u is updated in place. */
+ * 2*ndofs doubles.  u is updated in place.
+ * With VFP_CHECK_FINITE=1 in the environment, vfp_advance and
+ * vfp_theta_advance check the state for NaN or Inf after their last step
+ * (one extra kernel, then a synchronisation of `stream`) and return
+ * VFP_EDEVICE if one is found; unset (the default) they do not synchronise. */
 int vfp_advance(vfp_ctx* ctx, double* u, double dt, int64_t nsteps,
                 double* work, void* stream);
 

@@ -177,6 +177,21 @@ void kry_coll_precond(double* out, const double* in, const double* nu, double nu
                      per_cell, n, total);
 }
 
+namespace {
+// flag[0] = 1 if any x[i] is NaN or infinite (every writer stores the same
+// value, so the race is benign)
+__global__ __launch_bounds__(kKryThreads) void nonfinite_kernel(const double* __restrict__ x, int64_t n, int* flag) {
+  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
+  bool bad = false;
+  for (int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; i < n; i += stride) bad |= !isfinite(x[i]);
+  if (bad) flag[0] = 1;
+}
+}  // namespace
+
+void kry_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(nonfinite_kernel, dim3(grid_for(n)), dim3(kKryThreads), 0, s, x, n, flag);
+}
+
 void kry_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t s) {
   hipLaunchKernelGGL(lincomb_kernel, dim3(grid_for(n)), dim3(kKryThreads), 0, s, out, a, x, b, y ? y : x, n);
 }

@@ -73,6 +73,8 @@ void kry_mdot(const double* V, int64_t ldv, int k, const double* w, int64_t n, d
 void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coef, double sign, int64_t n,
                hipStream_t s, double* partial = nullptr, double* norm2 = nullptr);
 void kry_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t s);
+// flag[0] = 1 if x (n doubles) holds a NaN or an infinity (flag left as is otherwise)
+void kry_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);
 // out = in / (1 + s nu_c c_lms) on a [cell][nb][n] vector (nu per cell, or nu0 if null)
 void kry_coll_precond(double* out, const double* in, const double* nu, double nu0, const double* cval, double s,
                       int64_t ncells, int nb, int n, hipStream_t st);

@@ -270,6 +270,7 @@ struct vfp_ctx {
   DevBuf d_itab, d_dtab, d_xrec, d_prec, d_prec2;
   DevBuf d_u_pts, d_uf_pts[3], d_nu_pts;
   DevBuf d_fg_support;      // x cells whose U' and dU/dt sensitivities are formed (vfp_field_grad_support)
+  DevBuf d_flag;            // one int: the finiteness check of vfp_advance (VFP_CHECK_FINITE)
   RowTables tab{};
   FieldArgs fld{};
   MeshArgs meshargs{};
@@ -837,7 +838,8 @@ int ensure_device(vfp_ctx* c) {
     g_basis_ready[dev] = true;
   }
   c->device = dev;
-  return VFP_OK;
+  const int zero = 0;
+  return upload(c->d_flag, &zero, sizeof(int));
 }
 
 // Packed per-x-cell and per-p-cell scalar records (see FieldArgs::xrec).
@@ -1544,6 +1546,23 @@ int vfp_stage(vfp_ctx* c, const double* w_in, const double* u, double* w_out, do
   return launch(c, w_in, u, w_out, 1.0, cdt, 1, stream);
 }
 
+// Opt-in guard (VFP_CHECK_FINITE=1 in the environment): after a compute call
+// that advances the state, check it for NaN / Inf on the device and report
+// VFP_EDEVICE; synchronises the stream.  Off, it costs one getenv.
+static int check_finite(vfp_ctx* c, const double* u, int64_t N, void* stream, const char* who) {
+  const char* ev = std::getenv("VFP_CHECK_FINITE");
+  if (!(ev && std::atoi(ev) != 0)) return VFP_OK;
+  hipStream_t st = (hipStream_t)stream;
+  int* flag = c->d_flag.as<int>();
+  HIP_TRY(hipMemsetAsync(flag, 0, sizeof(int), st));
+  kry_nonfinite(u, N, flag, st);
+  int h = 0;
+  HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h) return fail(VFP_EDEVICE, "%s: the state holds NaN or Inf values (VFP_CHECK_FINITE)", who);
+  return VFP_OK;
+}
+
 int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, void* stream) {
   if (int e = check_ready(c)) return e;
   if (!u || !work) return fail(VFP_EINVAL, "null state pointer");
@@ -1563,7 +1582,7 @@ int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, 
     a.st.with_source = (c->terms & VFP_TERM_SOURCE) ? 1 : 0;
     c->resident(a, dt, (long long)nsteps, u, (hipStream_t)stream);
     HIP_TRY(hipGetLastError());
-    return VFP_OK;
+    return check_finite(c, u, N, stream, "vfp_advance");
   }
   for (int64_t s = 0; s < nsteps; ++s) {
     if (int e = launch(c, u, u, wa, 1.0, stage_cdt(0, dt), 1, stream)) return e;
@@ -1571,7 +1590,7 @@ int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, 
     if (int e = launch(c, wb, u, wa, 1.0, stage_cdt(2, dt), 1, stream)) return e;
     if (int e = launch(c, wa, u, u, 1.0, stage_cdt(3, dt), 1, stream)) return e;
   }
-  return VFP_OK;
+  return check_finite(c, u, N, stream, "vfp_advance");
 }
 
 static int launch_adj(vfp_ctx* c, const double* mu_in, const double* acc_in, double* acc_out, double alpha,
@@ -2175,7 +2194,7 @@ int vfp_theta_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, const vf
     stats->residual = worst;
     stats->converged = all ? 1 : 0;
   }
-  return VFP_OK;
+  return check_finite(c, u, N, stream, "vfp_theta_advance");
 }
 
 }  // extern "C"

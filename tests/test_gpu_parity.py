@@ -410,3 +410,29 @@ def test_resident_stepping(lib, cuda, case, monkeypatch):
     e1, e0 = rel_inf(outs["1"], want), rel_inf(outs["1"], outs["0"])
     _say(f"[resident] {case}: ndofs={wl.ndofs} vs oracle {e1:.2e}, vs stage launches {e0:.2e}")
     assert e1 <= STEPS_TOL and e0 <= 1e-12
+
+
+def test_finite_guard_and_refused_allocation(lib, cuda, monkeypatch):
+    """VFP_CHECK_FINITE=1: vfp_advance reports a state that holds NaN (and
+    leaves a finite one alone); unset, it does not look.  VFP_FAIL_ALLOC:
+    set-up calls report a refused device allocation as VFP_ENOMEM."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator, VFPError
+    wl = CASES["c1"]()
+    op = Operator(wl)
+    dt = op.cfl_dt(0.2)
+    work = torch.empty(2 * op.ndofs, dtype=torch.float64, device="cuda")
+    u = torch.from_numpy(np.ascontiguousarray(W.random_state(wl, 3)).ravel()).cuda()
+    monkeypatch.setenv("VFP_CHECK_FINITE", "1")
+    op.advance(u, dt, 2, work)                    # finite: no error
+    u[17] = float("nan")
+    with pytest.raises(VFPError, match="NaN or Inf"):
+        op.advance(u, dt, 2, work)
+    monkeypatch.delenv("VFP_CHECK_FINITE")
+    op.advance(u, dt, 1, work)                    # unchecked
+    torch.cuda.synchronize()
+    monkeypatch.setenv("VFP_FAIL_ALLOC", "1")
+    with pytest.raises(VFPError, match="refused"):
+        Operator(shock(6, 3, 1, 1))
+    monkeypatch.delenv("VFP_FAIL_ALLOC")
+    Operator(shock(6, 3, 1, 1)).close()
