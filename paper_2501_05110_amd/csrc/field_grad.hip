@@ -360,7 +360,9 @@ __device__ __forceinline__ void fgrad_body(const KernelArgs& A, const double* __
     for (int j = r; j < FR::NRED; j += N) {
       double sum = 0.0;
       for (int l = 0; l < N; ++l) sum += X[j * N + l];
-      slots[(size_t)cell * NS + FR::slot(j)] += cdt * sum;
+      // one add per slot and launch, in stream order across launches (so the
+      // sum is reproducible); no returned value, so nothing waits for it
+      atomicAdd(&slots[(size_t)cell * NS + FR::slot(j)], cdt * sum);
     }
 }
 

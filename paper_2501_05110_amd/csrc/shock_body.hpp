@@ -702,7 +702,9 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
       if (act && r == 0) {
         double sum = 0.0;
         for (int j = 0; j < N; ++j) sum += X[j];
-        gp(A.adj.grad_nu)[cell] -= A.st.beta * F.t_col * sum;
+        // one add per cell and launch, so stream order keeps the sum
+        // reproducible; nothing waits for the old value
+        atomicAdd(&A.adj.grad_nu[cell], -A.st.beta * F.t_col * sum);
       }
     }
     if (act && gp(A.adj.t_out)) {

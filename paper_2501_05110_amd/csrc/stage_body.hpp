@@ -692,7 +692,8 @@ void stage_kernel(KernelArgs A) {
       if (act && r == 0) {
         double sum = 0.0;
         for (int j = 0; j < N; ++j) sum += shc[j];
-        A.adj.grad_nu[cell] -= A.st.beta * F.t_col * sum;
+        // one add per cell and launch (reproducible in stream order)
+        atomicAdd(&A.adj.grad_nu[cell], -A.st.beta * F.t_col * sum);
       }
     }
     if (act && A.adj.t_out) {
