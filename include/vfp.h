@@ -347,7 +347,10 @@ int vfp_adjoint_checkpointed(vfp_ctx* ctx, const double* ckpt, double dt, int64_
 int vfp_field_grad_size(const vfp_ctx* ctx, int64_t* n);
 /* Restrict the U' and dU/dt sensitivities (volume and ln p faces) to the x
  * cells with xcells[i] != 0 (host array of N0 flags; NULL: every cell, the
- * default); dJ/dU and dJ/dU_face are formed everywhere.  For a caller whose
+ * default): they are formed on every such cell and on the cells that share
+ * a kernel tile (a run of consecutive cells) with one, and the slots of the
+ * other cells are left untouched; dJ/dU and dJ/dU_face are formed
+ * everywhere.  For a caller whose
  * parameters move U' and dU/dt only on some cells (a tanh shock: its U' and
  * every parameter derivative of U' and U U' vanish exactly where
  * 1 - tanh^2(x/w) rounds to 0), the skipped contributions are multiplied

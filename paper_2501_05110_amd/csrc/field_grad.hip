@@ -25,12 +25,14 @@
 // On a face from T1 (below) to T2 (above) the pairing is  int_F (mu_2 - mu_1).J
 // (the trace of a cell outside the mesh counts as zero).
 //
-// Each cell accumulates into its own slots (no atomics): its x Gauss points
+// Each cell accumulates into its own slots: its x Gauss points
 // (summed over its p points), its lower x and ln p faces, and its upper faces
 // where they are the (non-periodic) end of the mesh.  The lanes of a cell
 // exchange forward values through a few LDS rows for the l-coupling and sum
-// their shares of the slots through the same rows.  fgrad_reduce sums the
-// slots per x point.
+// their shares of the slots through the same rows, and one lane adds each
+// slot's sum with an atomic add that nothing waits for (a slot receives one
+// add per launch, so launches in stream order give a reproducible sum).
+// fgrad_reduce sums the slots per x point.
 #include <type_traits>
 
 #include "basis.hpp"
@@ -63,8 +65,8 @@ struct GSlots {
 // Heaviside with H(0) = 1/2
 __device__ __forceinline__ double heav(double x) { return x > 0.0 ? 1.0 : (x < 0.0 ? 0.0 : 0.5); }
 
-// The sensitivities split in two launches over the same cells, each with a
-// small live register set:
+// The sensitivities split in two parts over the same cells (workgroups of
+// one launch):
 //   PART 0: dJ/dU at the x Gauss points (volume) and dJ/dU_F (x faces), for
 //           every cell;
 //   PART 1: dJ/dU' and dJ/d(dU/dt) (volume and ln p faces), for the cells of
@@ -366,22 +368,30 @@ __device__ __forceinline__ void fgrad_body(const KernelArgs& A, const double* __
     }
 }
 
-// Both parts in one launch: even workgroups take part 0 and odd ones part 1
-// of the same cells, so that the two interleave on the machine (each is
-// bound by memory latency, not bandwidth).
+// Both parts in one launch, spread evenly over the grid so that the two
+// interleave on the machine (each is bound by memory latency, not
+// bandwidth): of the nblk + np1 workgroups, workgroup i takes part 1 where
+// floor((i + 1) np1 / total) steps past floor(i np1 / total), and part 0
+// otherwise.  p1_blocks lists the tiles that hold a support cell (np1 of
+// them), so that no workgroup is spent on a tile without one; null means
+// every tile (np1 = nblk: even workgroups part 0, odd ones part 1), and
+// then part 1 checks the support itself.
 template <int K, int LMAX>
 __global__ __launch_bounds__(kFgThreads) __attribute__((amdgpu_waves_per_eu(VFP_FG_WAVES)))
 void fgrad_kernel(KernelArgs A, const double* __restrict__ mu, const double* __restrict__ fwd, double cdt,
-                  double* __restrict__ slots, const unsigned char* __restrict__ support) {
+                  double* __restrict__ slots, const unsigned char* __restrict__ support,
+                  const int* __restrict__ p1_blocks, int nblk, int np1) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int CPB = (kFgThreads / N) > 0 ? kFgThreads / N : 1;
   constexpr int X0 = FgRows<K, 0>::XRW, X1 = FgRows<K, 1>::XRW;
   __shared__ double lds[CPB * (X0 > X1 ? X0 : X1) * N];
-  const int blk = blockIdx.x >> 1;
-  if (blockIdx.x & 1)
-    fgrad_body<K, LMAX, 1>(A, mu, fwd, cdt, slots, support, lds, blk);
+  const long long total = (long long)nblk + np1, i = blockIdx.x;
+  const int c0 = (int)(i * np1 / total), c1 = (int)((i + 1) * np1 / total);
+  if (c1 > c0)
+    fgrad_body<K, LMAX, 1>(A, mu, fwd, cdt, slots, p1_blocks ? nullptr : support, lds,
+                           p1_blocks ? p1_blocks[c0] : c0);
   else
-    fgrad_body<K, LMAX, 0>(A, mu, fwd, cdt, slots, support, lds, blk);
+    fgrad_body<K, LMAX, 0>(A, mu, fwd, cdt, slots, support, lds, (int)i - c0);
 }
 
 // g_u, g_dudx, g_dudt at the nx (k+1) x Gauss points and g_uface at the nx+1
@@ -420,12 +430,12 @@ __global__ void fgrad_reduce_kernel(MeshArgs M, const double* __restrict__ slots
 
 template <int K, int LMAX>
 void launch_fg_t(const KernelArgs& a, const double* mu, const double* fwd, double cdt, double* slots,
-                 const unsigned char* support, hipStream_t s) {
-  constexpr int N = (LMAX + 1) * (LMAX + 1);
-  constexpr int CPB = (kFgThreads / N) > 0 ? kFgThreads / N : 1;
-  const int blocks = (a.mesh.ncells + CPB - 1) / CPB;
-  hipLaunchKernelGGL((fgrad_kernel<K, LMAX>), dim3(2 * blocks), dim3(kFgThreads), 0, s, a, mu, fwd, cdt, slots,
-                     support);
+                 const unsigned char* support, const int* p1_blocks, int np1, hipStream_t s) {
+  const int blocks = field_grad_tiles(a.mesh.ncells, LMAX);
+  if (!p1_blocks) np1 = blocks;
+  if (blocks + np1 == 0) return;
+  hipLaunchKernelGGL((fgrad_kernel<K, LMAX>), dim3(blocks + np1), dim3(kFgThreads), 0, s, a, mu, fwd, cdt, slots,
+                     support, p1_blocks, blocks, np1);
 }
 
 template <int K>
@@ -465,5 +475,15 @@ FieldGradReduce find_field_grad_reduce(int k) {
 }
 
 int field_grad_slots_per_cell(int k) { return k == 1 ? GSlots<1>::SIZE : GSlots<2>::SIZE; }
+
+int field_grad_tile_cells(int lmax) {
+  const int n = (lmax + 1) * (lmax + 1);
+  return kFgThreads / n > 0 ? kFgThreads / n : 1;
+}
+
+int field_grad_tiles(int ncells, int lmax) {
+  const int c = field_grad_tile_cells(lmax);
+  return (ncells + c - 1) / c;
+}
 
 }  // namespace vfp

@@ -50,14 +50,19 @@ int shock_cells_per_tile(int lmax);
 // slots to dJ/dU, dJ/dU', dJ/d(dU/dt) at the x Gauss points and dJ/dU at the
 // x faces.
 // support: per x cell, 0 where the U' and dU/dt sensitivities are not
-// wanted (null: everywhere).
+// wanted (null: everywhere).  p1_blocks: the np1 tiles (field_grad_tiles
+// numbering) that hold a support cell, or null for every tile.
 using FieldGradLauncher = void (*)(const KernelArgs&, const double* mu, const double* fwd, double cdt,
-                                   double* slots, const unsigned char* support, hipStream_t);
+                                   double* slots, const unsigned char* support, const int* p1_blocks, int np1,
+                                   hipStream_t);
 using FieldGradReduce = void (*)(const MeshArgs&, const double* slots, double* g_u, double* g_du, double* g_a,
                                  double* g_uf, hipStream_t);
 FieldGradLauncher find_field_grad_launcher(int k, int lmax);
 FieldGradReduce find_field_grad_reduce(int k);
 int field_grad_slots_per_cell(int k);
+// cells per tile of the field-gradient kernel, and tiles of a mesh
+int field_grad_tile_cells(int lmax);
+int field_grad_tiles(int ncells, int lmax);
 
 // Krylov-basis vector arithmetic (restarted GMRES of the Theta-method).
 // Vectors j of a basis are V + j ldv.  kry_mdot: out[j] = V_j . w for j < k,

@@ -270,6 +270,8 @@ struct vfp_ctx {
   DevBuf d_itab, d_dtab, d_xrec, d_prec, d_prec2;
   DevBuf d_u_pts, d_uf_pts[3], d_nu_pts;
   DevBuf d_fg_support;      // x cells whose U' and dU/dt sensitivities are formed (vfp_field_grad_support)
+  DevBuf d_fg_blocks;       // the field-gradient tiles holding a support cell
+  int fg_nblocks = 0;
   DevBuf d_flag;            // one int: the finiteness check of vfp_advance (VFP_CHECK_FINITE)
   RowTables tab{};
   FieldArgs fld{};
@@ -1125,6 +1127,8 @@ int vfp_set_mesh(vfp_ctx* c, const int* ncells, const double* const* nodes, cons
   c->have_Bpts = c->have_nu_cell = c->have_nu_pts = c->have_src = false;
   c->pflow = false;
   c->d_fg_support.release();
+  c->d_fg_blocks.release();
+  c->fg_nblocks = 0;
   c->nu0 = 0.0;
   c->u_vol.assign(c->ncell[0] * c->K1, 0.0);
   c->du_vol = c->a_vol = c->u_vol;
@@ -1711,7 +1715,9 @@ static int launch_fg(vfp_ctx* c, const double* mu, const double* fwd, double cdt
   a.mesh = c->meshargs;
   a.fld = c->fld;
   a.tab = c->tab;
-  fl(a, mu, fwd, cdt, slots, c->d_fg_support.as<unsigned char>(), (hipStream_t)stream);
+  const bool listed = c->d_fg_support.as<unsigned char>() != nullptr;
+  fl(a, mu, fwd, cdt, slots, c->d_fg_support.as<unsigned char>(), listed ? c->d_fg_blocks.as<int>() : nullptr,
+     listed ? c->fg_nblocks : 0, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return VFP_OK;
 }
@@ -1722,12 +1728,28 @@ int vfp_field_grad_support(vfp_ctx* c, const unsigned char* xcells) {
   if (int e = check_ready(c)) return e;
   if (int e = field_grad_ready(c)) return e;
   if (int e = ensure_pf_dk(c)) return e;
+  c->d_fg_blocks.release();
+  c->fg_nblocks = 0;
   if (!xcells) {
     c->d_fg_support.release();
     return VFP_OK;
   }
   std::vector<unsigned char> m(xcells, xcells + c->ncell[0]);
   for (auto& v : m) v = v ? 1 : 0;
+  // the tiles (runs of consecutive cells) that hold at least one support cell
+  const int tc = field_grad_tile_cells(c->lmax), nt = field_grad_tiles((int)c->ncells, c->lmax);
+  std::vector<int> blocks;
+  for (int t = 0; t < nt; ++t)
+    for (int j = 0; j < tc; ++j) {
+      const int64_t cell = (int64_t)t * tc + j;
+      if (cell < c->ncells && m[cell % c->ncell[0]]) {
+        blocks.push_back(t);
+        break;
+      }
+    }
+  if (!blocks.empty())
+    if (int e = upload_vec(c->d_fg_blocks, blocks)) return e;
+  c->fg_nblocks = (int)blocks.size();
   return upload_vec(c->d_fg_support, m);
 }
 

@@ -320,3 +320,47 @@ def test_support_keeps_profile_gradient(lib, cuda):
     assert abs(out[0][1] - out[1][1]) <= 1e-12 * abs(out[0][1])
     np.testing.assert_allclose(out[1][2], out[0][2], rtol=1e-12, atol=0)
     op.close()
+
+
+@pytest.mark.parametrize("nx,npc,k,lmax", [(40, 6, 2, 3), (37, 5, 2, 3), (29, 4, 1, 1)])
+def test_support_tiles_bit_identical(lib, cuda, nx, npc, k, lmax):
+    """With a support set, only the tiles that hold a support cell run the
+    U'/dU/dt part: every slot of a support cell and every U / U_face slot is
+    bit-identical to the run without a support; the U'/dU/dt slots of the
+    other cells are either that same value (a tile shared with a support
+    cell) or untouched (zero), and some are untouched.  Odd nx puts tiles
+    across p rows and leaves a partial last tile."""
+    import torch
+    from paper_2501_05110_amd import vfp
+    wl = W.shock_workload("tiles", nx, npc, k, lmax, w_frac=0.02, seed=9)
+    op = vfp.Operator(wl)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    mu = torch.randn(op.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    fwd = torch.randn(op.ndofs, dtype=torch.float64, device="cuda", generator=g)
+    support = vfp.planar_shock_support(op, wl.meta["w"])
+    assert 0 < support.sum() < support.size
+    got = []
+    for sup in (None, support):
+        op.field_grad_support(sup)
+        slots = torch.zeros(op.field_grad_size(), dtype=torch.float64, device="cuda")
+        op.field_grad_stage(mu, fwd, 0.25, slots)
+        op.field_grad_stage(fwd, mu, -0.5, slots)
+        torch.cuda.synchronize()
+        got.append(slots.cpu().numpy().reshape(op.ncells, -1))
+    full, part = got
+    K1 = k + 1
+    ns = full.shape[1]
+    assert ns == 7 * K1 + 2
+    p1 = np.zeros(ns, bool)                     # the U' / dU/dt slots
+    for q in range(K1):
+        p1[3 * q + 1] = p1[3 * q + 2] = True
+    p1[3 * K1 + 2:] = True
+    on = np.asarray(support, bool)[np.arange(op.ncells) % nx]
+    keep = ~p1[None, :] | on[:, None]
+    _say(f"[tiles] {nx}x{npc} k={k} l_max={lmax}: {int(support.sum())}/{nx} x cells in the support")
+    assert np.array_equal(part[keep], full[keep])
+    rest, ref = part[~keep], full[~keep]
+    assert np.all((rest == 0) | (rest == ref))
+    assert np.any((rest == 0) & (ref != 0))
+    assert np.abs(full[on][:, p1]).max() > 0
+    op.close()
