@@ -1930,6 +1930,7 @@ struct XLine {
   double *D = nullptr, *L = nullptr, *U = nullptr;
   int* fail = nullptr;
   int nx = 0, nlines = 0, b = 0, wrapc = 0;
+  bool rowwise = false;   // VFP_XLINE_ROWS=1: the one-lane-per-row solve for every block size (tests)
 };
 
 XLine xline_layout(const vfp_ctx* c, double* tail) {
@@ -1938,6 +1939,8 @@ XLine xline_layout(const vfp_ctx* c, double* tail) {
   x.nlines = c->ncells / x.nx;
   x.b = c->nb * c->n;
   x.wrapc = (c->bc_lo[0] == VFP_BC_PERIODIC && x.nx % 3 != 0) ? 1 : 0;
+  const char* rw = std::getenv("VFP_XLINE_ROWS");
+  x.rowwise = rw && std::atoi(rw) != 0;
   const int64_t blk = (int64_t)c->ncells * x.b * x.b;
   if (tail) {
     x.D = tail;
@@ -1986,7 +1989,7 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
   const double sp = dt * th * ((c->terms & VFP_TERM_COLLISION) ? 1.0 : 0.0);
   auto precond = [&](double* out, const double* in) {
     if (o.precond == VFP_PRECOND_XLINE)
-      xl_apply(in, out, xl.D, xl.L, xl.U, xl.nlines, xl.nx, xl.b, st);
+      xl_apply(in, out, xl.D, xl.L, xl.U, xl.nlines, xl.nx, xl.b, xl.rowwise, st);
     else
       kry_coll_precond(out, in, c->fld.nu_cell, c->fld.nu0, c->tab.c_val, sp, c->ncells, c->nb, c->n, st);
   };

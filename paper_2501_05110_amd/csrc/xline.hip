@@ -259,6 +259,121 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply_kernel(const double*
   }
 }
 
+// The same recurrences for b <= 16 with every lane of the wavefront busy and
+// the loads kept well ahead of the chain.  Four lanes share a row (lane =
+// 4 row + q); lane q holds the entries k = q, q + 4, q + 8, q + 12 of its
+// row of each block, so its product over them is the partial sum a[q] of
+// xl_rowdot, and two butterfly exchanges inside the lane quad give every
+// lane of the row (a0 + a1) + (a2 + a3): the same rounding as the kernel
+// above, bit for bit.  The rows of the next kXlRing cells sit in a ring of
+// registers (a loop unrolled by kXlRing, so every slot index is a constant):
+// the loads of cell i + kXlRing are issued as cell i is done, so about
+// kXlRing steps of the recurrence hide each load's latency.
+constexpr int kXlRing = 8;
+
+// v from lane (lane ^ 1) and (lane ^ 2) of the same quad (DPP quad_perm)
+template <int CTRL>
+__device__ __forceinline__ double xl_quad_swap(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffffLL), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double xl_quad_sum(double a) {
+  a = a + xl_quad_swap<0xB1>(a);   // quad_perm [1, 0, 3, 2]: a0 + a1, a2 + a3
+  return a + xl_quad_swap<0x4E>(a);  // quad_perm [2, 3, 0, 1]
+}
+
+__global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(const double* r, double* x,
+                                                                    const double* __restrict__ D,
+                                                                    const double* __restrict__ L,
+                                                                    const double* __restrict__ U, int nx, int b) {
+  __shared__ double v[16];
+  const int lane = threadIdx.x;
+  const int row = lane >> 2, q = lane & 3;
+  const bool on = row < b;
+  const int line = blockIdx.x;
+  const int64_t bb = (int64_t)b * b;
+  const int64_t c0 = (int64_t)line * nx;
+  if (lane < 16) v[lane] = 0.0;
+  double p1[kXlRing][4], p2[kXlRing][4], pv[kXlRing];
+  // cell i of the line into ring slot s: rows of blocks A (and B) and the
+  // row's entry of vector w.  The loads are unconditional, so that no branch
+  // stands between a load and its use and the in-order wait counts stay
+  // exact; an index outside the line, the block or the rows is clamped to an
+  // entry that exists, and what is read there is never used (entries k >= b
+  // are skipped in prod, rows >= b and cells past the line's end are not
+  // stored).
+  const int rr = on ? row : 0;
+  auto fetch = [&](double (&a)[4], double (&bm)[4], double& w, const double* A, const double* B, const double* vec,
+                   int i) {
+    const int64_t cell = c0 + ((i >= 0 && i < nx) ? i : 0);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = (q + 4 * m < b) ? q + 4 * m : 0;
+      a[m] = A[cell * bb + (int64_t)k * b + rr];
+      if (B) bm[m] = B[cell * bb + (int64_t)k * b + rr];
+    }
+    w = vec[cell * b + rr];
+  };
+  auto prod = [&](const double (&a)[4]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (q + 4 * m < b) acc = fma(a[m], v[q + 4 * m], acc);
+    return xl_quad_sum(acc);
+  };
+  // forward: y_i = S_i^{-1}(r_i - L_i y_{i-1}); p1 = L rows, p2 = S^{-1} rows
+#pragma unroll
+  for (int s = 0; s < kXlRing; ++s) fetch(p1[s], p2[s], pv[s], L, D, r, s);
+  double prev = 0.0;
+  for (int i0 = 0; i0 < nx; i0 += kXlRing) {
+#pragma unroll
+    for (int s = 0; s < kXlRing; ++s) {
+      const int i = i0 + s;
+      if (i < nx) {
+        double t = pv[s];
+        if (i > 0) {
+          xl_wave_sync();
+          if (q == 0 && on) v[row] = prev;
+          xl_wave_sync();
+          t -= prod(p1[s]);
+        }
+        xl_wave_sync();
+        if (q == 0 && on) v[row] = t;
+        xl_wave_sync();
+        const double y = prod(p2[s]);
+        if (q == 0 && on) x[(c0 + i) * b + row] = y;
+        prev = y;
+      }
+      fetch(p1[s], p2[s], pv[s], L, D, r, i + kXlRing);
+    }
+  }
+  // backward: x_i = y_i - G_i x_{i+1}, i = nx-2 .. 0; p1 = G rows, pv = y.
+  // The y rows were stored above by the quad's lane 0 and are read back by
+  // all four lanes: order those stores before these loads
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+#pragma unroll
+  for (int s = 0; s < kXlRing; ++s) fetch(p1[s], p2[s], pv[s], U, nullptr, x, nx - 2 - s);
+  for (int j0 = 0; j0 < nx - 1; j0 += kXlRing) {
+#pragma unroll
+    for (int s = 0; s < kXlRing; ++s) {
+      const int i = nx - 2 - (j0 + s);
+      if (i >= 0) {
+        xl_wave_sync();
+        if (q == 0 && on) v[row] = prev;
+        xl_wave_sync();
+        prev = pv[s] - prod(p1[s]);
+        if (q == 0 && on) x[(c0 + i) * b + row] = prev;
+      }
+      fetch(p1[s], p2[s], pv[s], U, nullptr, x, i - kXlRing);
+    }
+  }
+}
+
 }  // namespace
 
 void xl_probe_set(double* v, int64_t ndofs, int nx, int b, int wrapc, int color, int j, hipStream_t s) {
@@ -279,8 +394,10 @@ void xl_factor(double* D, const double* L, double* U, int nlines, int nx, int b,
 }
 
 void xl_apply(const double* r, double* x, const double* D, const double* L, const double* U, int nlines, int nx,
-              int b, hipStream_t s) {
-  if (b <= 16)
+              int b, bool rowwise, hipStream_t s) {
+  if (b <= 16 && !rowwise)
+    hipLaunchKernelGGL(xl_apply16_kernel, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
+  else if (b <= 16)
     hipLaunchKernelGGL(xl_apply_kernel<16>, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
   else if (b <= 32)
     hipLaunchKernelGGL(xl_apply_kernel<32>, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);

@@ -175,6 +175,31 @@ def test_xline_preconditioner_dsa_paper_setup(lib, cuda):
     assert st["iterations"] * 5 <= st0["iterations"]
 
 
+@pytest.mark.parametrize("nx,k,lmax", [(37, 1, 1), (5, 3, 1), (23, 2, 1)])
+def test_xline_quad_lanes_match_rowwise(lib, cuda, monkeypatch, nx, k, lmax):
+    """Blocks of at most 16 unknowns are solved with four lanes per row and
+    a ring of prefetched cells; that solve rounds exactly as the one lane
+    per row solve (VFP_XLINE_ROWS=1), so the Theta steps agree bit for bit
+    (b = 8, 16 and 12; a line shorter than the ring; lengths that are not a
+    multiple of it), and both match the oracle's sparse-LU step."""
+    from paper_2501_05110_amd.vfp import Operator
+    wl = _x_transport(nx=nx, k=k, lmax=lmax)
+    op = Operator(wl)
+    dt = 30.0 * op.cfl_dt(1.0)
+    z = W.random_state(wl, 47)
+    want = dg.theta_step(dg.assemble(wl), z, dt, 0.5, 2)
+    out = {}
+    for rows in ("0", "1"):
+        monkeypatch.setenv("VFP_XLINE_ROWS", rows)
+        out[rows] = _gpu_theta(op, z, dt, 0.5, 2, tol=1e-13, restart=30, max_iters=500, precond="xline")
+    (g0, s0), (g1, s1) = out["0"], out["1"]
+    b = (k + 1) * (lmax + 1) ** 2
+    _say(f"[xline lanes] nx={nx} b={b}: iterations {s0['iterations']} / {s1['iterations']}, "
+         f"rel_inf={rel_inf(g0, want):.3e}")
+    assert np.array_equal(g0, g1) and s0["iterations"] == s1["iterations"]
+    assert s0["converged"] and rel_inf(g0, want) <= THETA_TOL
+
+
 def test_xline_preconditioner_periodic_and_rejected(lib, cuda):
     """A periodic axis 0 whose length is not a multiple of 3 (the wrap left
     out of the preconditioner, the last cell probed with a colour of its
