@@ -37,7 +37,37 @@ __device__ __forceinline__ double block_sum(double v) {
 // partial[j][blockIdx.x] = sum over this block's elements of V_j . w, for the
 // kDotChunk vectors j = blockIdx.y kDotChunk + c < k; with self != 0 the
 // first block row also writes w . w as row k (the norm that the Gram-Schmidt
-// step needs, from the same pass over w)
+// step needs, from the same pass over w).  C = the vectors of this block row
+// (a compile-time count, so every load is unconditional); each thread takes
+// its elements two strides at a time with all loads issued before the FMAs,
+// in the same order as one at a time.
+template <int C>
+__device__ __forceinline__ void mdot_rows(const double* __restrict__ V, int64_t ldv, int j0,
+                                          const double* __restrict__ w, int64_t n, bool do_self,
+                                          double (&acc)[kDotChunk], double& ws) {
+  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
+  int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x;
+  const double* Vj = V + (int64_t)j0 * ldv;
+  for (; i + stride < n; i += 2 * stride) {
+    const double wa = w[i], wb = w[i + stride];
+    double va[C], vb[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+      va[c] = Vj[(int64_t)c * ldv + i];
+      vb[c] = Vj[(int64_t)c * ldv + i + stride];
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = fma(vb[c], wb, fma(va[c], wa, acc[c]));
+    if (do_self) ws = fma(wb, wb, fma(wa, wa, ws));
+  }
+  if (i < n) {
+    const double wa = w[i];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = fma(Vj[(int64_t)c * ldv + i], wa, acc[c]);
+    if (do_self) ws = fma(wa, wa, ws);
+  }
+}
+
 __global__ __launch_bounds__(kKryThreads) void mdot_partial_kernel(const double* __restrict__ V, int64_t ldv,
                                                                     int k, const double* __restrict__ w,
                                                                     int64_t n, double* __restrict__ partial,
@@ -47,13 +77,15 @@ __global__ __launch_bounds__(kKryThreads) void mdot_partial_kernel(const double*
   double acc[kDotChunk], ws = 0.0;
 #pragma unroll
   for (int c = 0; c < kDotChunk; ++c) acc[c] = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
-  for (int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; i < n; i += stride) {
-    const double wi = w[i];
-#pragma unroll
-    for (int c = 0; c < kDotChunk; ++c)
-      if (j0 + c < k) acc[c] = fma(V[(int64_t)(j0 + c) * ldv + i], wi, acc[c]);
-    if (do_self) ws = fma(wi, wi, ws);
+  switch (k - j0 < kDotChunk ? k - j0 : kDotChunk) {
+    case 1: mdot_rows<1>(V, ldv, j0, w, n, do_self, acc, ws); break;
+    case 2: mdot_rows<2>(V, ldv, j0, w, n, do_self, acc, ws); break;
+    case 3: mdot_rows<3>(V, ldv, j0, w, n, do_self, acc, ws); break;
+    case 4: mdot_rows<4>(V, ldv, j0, w, n, do_self, acc, ws); break;
+    case 5: mdot_rows<5>(V, ldv, j0, w, n, do_self, acc, ws); break;
+    case 6: mdot_rows<6>(V, ldv, j0, w, n, do_self, acc, ws); break;
+    case 7: mdot_rows<7>(V, ldv, j0, w, n, do_self, acc, ws); break;
+    default: mdot_rows<kDotChunk>(V, ldv, j0, w, n, do_self, acc, ws); break;
   }
   __shared__ double red[kDotChunk + 1][kKryThreads / 64];
   const int lane = threadIdx.x % 64, wave = threadIdx.x / 64;
