@@ -93,7 +93,7 @@ constexpr int kXlMaxBlock = 48;
 void xl_probe_set(double* v, int64_t ndofs, int nx, int b, int wrapc, int color, int j, hipStream_t s);
 void xl_probe_get(const double* w, double* D, double* L, double* U, int64_t ndofs, int nx, int b, int wrapc,
                   int color, int j, hipStream_t s);
-void xl_factor(double* D, const double* L, double* U, int nlines, int nx, int b, int* fail, hipStream_t s);
+void xl_factor(double* D, double* L, double* U, int nlines, int nx, int b, int* fail, hipStream_t s);
 // rowwise: one lane per row for every b (else four lanes per row where b <= 16)
 void xl_apply(const double* r, double* x, const double* D, const double* L, const double* U, int nlines, int nx,
               int b, bool rowwise, hipStream_t s);

@@ -18,9 +18,13 @@
 //
 // Storage per cell, b = (k+1)^d n unknowns: three b x b blocks, column-major
 // (entry (row, col) at col b + row): D (own), L (towards ix - 1), U (towards
-// ix + 1).  xl_factor overwrites D with S^{-1} and U with G = S^{-1} U, where
+// ix + 1).  xl_factor overwrites D with S^{-1}, U with G = S^{-1} U and,
+// past the first cell of each line, L with M = S^{-1} L, where
 // S_i = D_i - L_i G_{i-1} (block LU along the line, pivoting inside each
-// block by Gauss-Jordan with partial pivoting).
+// block by Gauss-Jordan with partial pivoting).  The solve is then
+// y_i = S_i^{-1} r_i - M_i y_{i-1} forward and x_i = y_i - G_i x_{i+1}
+// backward: one block product per cell on each recurrence chain, the
+// products S_i^{-1} r_i standing apart from it.
 #include <hip/hip_runtime.h>
 
 #include "launch.hpp"
@@ -120,11 +124,13 @@ __device__ bool xl_invert(double* S, int b, int* perm, int* sh_piv, double* sh_v
 }
 
 // One workgroup per line: S_i = D_i - L_i G_{i-1}, D_i <- S_i^{-1},
-// U_i <- G_i = S_i^{-1} U_i.  fail[line] = 1 if a block was singular.
-__global__ __launch_bounds__(kXlThreads) void xl_factor_kernel(double* D, const double* L, double* U, int nx, int b,
+// U_i <- G_i = S_i^{-1} U_i, L_i <- M_i = S_i^{-1} L_i (i > 0).
+// fail[line] = 1 if a block was singular.
+__global__ __launch_bounds__(kXlThreads) void xl_factor_kernel(double* D, double* L, double* U, int nx, int b,
                                                               int* fail) {
   __shared__ double S[kXlMaxBlock * kXlMaxBlock];
   __shared__ double G[kXlMaxBlock * kXlMaxBlock];
+  __shared__ double Mt[kXlMaxBlock * kXlMaxBlock];
   __shared__ int perm[kXlMaxBlock];
   __shared__ int sh_piv;
   __shared__ double sh_val;
@@ -149,6 +155,18 @@ __global__ __launch_bounds__(kXlThreads) void xl_factor_kernel(double* D, const 
     __syncthreads();
     ok = xl_invert(S, b, perm, &sh_piv, &sh_val) && ok;
     for (int e = tid; e < b * b; e += blockDim.x) D[cell * bb + e] = S[e];
+    if (i > 0) {
+      // M_i = S_i^{-1} L_i, staged in LDS: every thread still reads L_i
+      const double* Lc = L + cell * bb;
+      for (int e = tid; e < b * b; e += blockDim.x) {
+        const int c = e / b, r = e - c * b;
+        double acc = 0.0;
+        for (int k = 0; k < b; ++k) acc = fma(S[k * b + r], Lc[c * b + k], acc);
+        Mt[e] = acc;
+      }
+      __syncthreads();
+      for (int e = tid; e < b * b; e += blockDim.x) L[cell * bb + e] = Mt[e];
+    }
     if (i + 1 < nx) {
       const double* Uc = U + cell * bb;
       for (int e = tid; e < b * b; e += blockDim.x) {
@@ -165,8 +183,8 @@ __global__ __launch_bounds__(kXlThreads) void xl_factor_kernel(double* D, const 
   if (tid == 0) fail[line] = ok ? 0 : 1;
 }
 
-// x = P^{-1} r along each line (x may be r): forward y_i = S_i^{-1}(r_i -
-// L_i y_{i-1}), backward x_i = y_i - G_i x_{i+1}.  One 64-lane workgroup (one
+// x = P^{-1} r along each line (x may be r): forward y_i = S_i^{-1} r_i -
+// M_i y_{i-1}, backward x_i = y_i - G_i x_{i+1}.  One 64-lane workgroup (one
 // wavefront, so LDS ordering needs only a wavefront-level fence) per line,
 // lane = row.  The recurrence is a chain of dependent block products, so the
 // kernel is bound by latency: each lane keeps its rows of the next cell's
@@ -217,17 +235,16 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply_kernel(const double*
       xl_load_row<BM>(nD, D + (cell + 1) * bb, row, b, on);
       rn = on ? r[(cell + 1) * b + row] : 0.0;
     }
-    double t = rc;
+    xl_wave_sync();
+    v[row] = rc;
+    xl_wave_sync();
+    double y = xl_rowdot<BM>(mD, v, b);
     if (i > 0) {
       xl_wave_sync();
       v[row] = prev;
       xl_wave_sync();
-      t -= xl_rowdot<BM>(mL, v, b);
+      y -= xl_rowdot<BM>(mL, v, b);
     }
-    xl_wave_sync();
-    v[row] = t;
-    xl_wave_sync();
-    const double y = xl_rowdot<BM>(mD, v, b);
     if (on) x[cell * b + row] = y;
     prev = y;
 #pragma unroll
@@ -265,11 +282,18 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply_kernel(const double*
 // row of each block, so its product over them is the partial sum a[q] of
 // xl_rowdot, and two butterfly exchanges inside the lane quad give every
 // lane of the row (a0 + a1) + (a2 + a3): the same rounding as the kernel
-// above, bit for bit.  The rows of the next kXlRing cells sit in a ring of
-// registers (a loop unrolled by kXlRing, so every slot index is a constant):
-// the loads of cell i + kXlRing are issued as cell i is done, so about
-// kXlRing steps of the recurrence hide each load's latency.
-constexpr int kXlRing = 8;
+// above, bit for bit.  The products S_i^{-1} r_i come first, for every cell
+// at once (xl_diag16_kernel, into x); the sweep then keeps the rows of the
+// next kXlRing cells in a ring of registers (a loop unrolled by kXlRing, so
+// every slot index is a constant): the loads of cell i + kXlRing are issued
+// as cell i is done, so about kXlRing steps of the recurrence hide each
+// load's latency.
+#ifndef VFP_XL_RING
+#define VFP_XL_RING 12
+#endif
+constexpr int kXlRing = VFP_XL_RING;
+constexpr int kXlDiagWaves = 4;     // wavefronts per workgroup of xl_diag16_kernel
+constexpr int kXlDiagPerWave = 4;   // cells per wavefront
 
 // v from lane (lane ^ 1) and (lane ^ 2) of the same quad (DPP quad_perm)
 template <int CTRL>
@@ -285,9 +309,45 @@ __device__ __forceinline__ double xl_quad_sum(double a) {
   return a + xl_quad_swap<0x4E>(a);  // quad_perm [2, 3, 0, 1]
 }
 
-__global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(const double* r, double* x,
-                                                                    const double* __restrict__ D,
-                                                                    const double* __restrict__ L,
+// x_i = S_i^{-1} r_i for every cell (x may be r: a wavefront reads its
+// cells' r before any of its lanes stores), kXlDiagPerWave cells per
+// wavefront with every load issued before the first product
+__global__ __launch_bounds__(64 * kXlDiagWaves) void xl_diag16_kernel(const double* r, double* x,
+                                                                     const double* __restrict__ D, int64_t ncells,
+                                                                     int b) {
+  const int lane = threadIdx.x & 63;
+  const int64_t first = ((int64_t)blockIdx.x * kXlDiagWaves + (threadIdx.x >> 6)) * kXlDiagPerWave;
+  const int row = lane >> 2, q = lane & 3;
+  const bool on = row < b;
+  const int rr = on ? row : 0;
+  const int64_t bb = (int64_t)b * b;
+  double dm[kXlDiagPerWave][4], rv[kXlDiagPerWave][4];
+#pragma unroll
+  for (int c = 0; c < kXlDiagPerWave; ++c) {
+    const int64_t cell = first + c < ncells ? first + c : ncells - 1;   // a cell that exists
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int k = (q + 4 * m < b) ? q + 4 * m : 0;
+      dm[c][m] = D[cell * bb + (int64_t)k * b + rr];
+      rv[c][m] = r[cell * b + k];
+    }
+  }
+  double out[kXlDiagPerWave];
+#pragma unroll
+  for (int c = 0; c < kXlDiagPerWave; ++c) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (q + 4 * m < b) acc = fma(dm[c][m], rv[c][m], acc);
+    out[c] = xl_quad_sum(acc);
+  }
+#pragma unroll
+  for (int c = 0; c < kXlDiagPerWave; ++c)
+    if (q == 0 && on && first + c < ncells) x[(first + c) * b + row] = out[c];
+}
+
+// the two sweeps; x holds S_i^{-1} r_i on entry and P^{-1} r on exit
+__global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(double* x, const double* __restrict__ M,
                                                                     const double* __restrict__ U, int nx, int b) {
   __shared__ double v[16];
   const int lane = threadIdx.x;
@@ -297,23 +357,21 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(const doubl
   const int64_t bb = (int64_t)b * b;
   const int64_t c0 = (int64_t)line * nx;
   if (lane < 16) v[lane] = 0.0;
-  double p1[kXlRing][4], p2[kXlRing][4], pv[kXlRing];
-  // cell i of the line into ring slot s: rows of blocks A (and B) and the
-  // row's entry of vector w.  The loads are unconditional, so that no branch
+  double p1[kXlRing][4], pv[kXlRing];
+  // cell i of the line into a ring slot: the row of block A and the row's
+  // entry of vector w.  The loads are unconditional, so that no branch
   // stands between a load and its use and the in-order wait counts stay
   // exact; an index outside the line, the block or the rows is clamped to an
   // entry that exists, and what is read there is never used (entries k >= b
   // are skipped in prod, rows >= b and cells past the line's end are not
   // stored).
   const int rr = on ? row : 0;
-  auto fetch = [&](double (&a)[4], double (&bm)[4], double& w, const double* A, const double* B, const double* vec,
-                   int i) {
+  auto fetch = [&](double (&a)[4], double& w, const double* A, const double* vec, int i) {
     const int64_t cell = c0 + ((i >= 0 && i < nx) ? i : 0);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int k = (q + 4 * m < b) ? q + 4 * m : 0;
       a[m] = A[cell * bb + (int64_t)k * b + rr];
-      if (B) bm[m] = B[cell * bb + (int64_t)k * b + rr];
     }
     w = vec[cell * b + rr];
   };
@@ -324,30 +382,27 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(const doubl
       if (q + 4 * m < b) acc = fma(a[m], v[q + 4 * m], acc);
     return xl_quad_sum(acc);
   };
-  // forward: y_i = S_i^{-1}(r_i - L_i y_{i-1}); p1 = L rows, p2 = S^{-1} rows
+  // forward: y_i = c_i - M_i y_{i-1}; p1 = M rows, pv = c (read from x, where
+  // y_i then goes: each cell's c is read kXlRing cells before its y is stored)
 #pragma unroll
-  for (int s = 0; s < kXlRing; ++s) fetch(p1[s], p2[s], pv[s], L, D, r, s);
+  for (int s = 0; s < kXlRing; ++s) fetch(p1[s], pv[s], M, x, s);
   double prev = 0.0;
   for (int i0 = 0; i0 < nx; i0 += kXlRing) {
 #pragma unroll
     for (int s = 0; s < kXlRing; ++s) {
       const int i = i0 + s;
       if (i < nx) {
-        double t = pv[s];
+        double y = pv[s];
         if (i > 0) {
           xl_wave_sync();
           if (q == 0 && on) v[row] = prev;
           xl_wave_sync();
-          t -= prod(p1[s]);
+          y -= prod(p1[s]);
         }
-        xl_wave_sync();
-        if (q == 0 && on) v[row] = t;
-        xl_wave_sync();
-        const double y = prod(p2[s]);
         if (q == 0 && on) x[(c0 + i) * b + row] = y;
         prev = y;
       }
-      fetch(p1[s], p2[s], pv[s], L, D, r, i + kXlRing);
+      fetch(p1[s], pv[s], M, x, i + kXlRing);
     }
   }
   // backward: x_i = y_i - G_i x_{i+1}, i = nx-2 .. 0; p1 = G rows, pv = y.
@@ -357,7 +412,7 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(const doubl
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
-  for (int s = 0; s < kXlRing; ++s) fetch(p1[s], p2[s], pv[s], U, nullptr, x, nx - 2 - s);
+  for (int s = 0; s < kXlRing; ++s) fetch(p1[s], pv[s], U, x, nx - 2 - s);
   for (int j0 = 0; j0 < nx - 1; j0 += kXlRing) {
 #pragma unroll
     for (int s = 0; s < kXlRing; ++s) {
@@ -369,7 +424,7 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(const doubl
         prev = pv[s] - prod(p1[s]);
         if (q == 0 && on) x[(c0 + i) * b + row] = prev;
       }
-      fetch(p1[s], p2[s], pv[s], U, nullptr, x, i - kXlRing);
+      fetch(p1[s], pv[s], U, x, i - kXlRing);
     }
   }
 }
@@ -389,14 +444,19 @@ void xl_probe_get(const double* w, double* D, double* L, double* U, int64_t ndof
                      wrapc, color, j);
 }
 
-void xl_factor(double* D, const double* L, double* U, int nlines, int nx, int b, int* fail, hipStream_t s) {
+void xl_factor(double* D, double* L, double* U, int nlines, int nx, int b, int* fail, hipStream_t s) {
   hipLaunchKernelGGL(xl_factor_kernel, dim3(nlines), dim3(kXlThreads), 0, s, D, L, U, nx, b, fail);
 }
 
 void xl_apply(const double* r, double* x, const double* D, const double* L, const double* U, int nlines, int nx,
               int b, bool rowwise, hipStream_t s) {
-  if (b <= 16 && !rowwise)
-    hipLaunchKernelGGL(xl_apply16_kernel, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
+  if (b <= 16 && !rowwise) {
+    const int64_t ncells = (int64_t)nlines * nx;
+    constexpr int per_block = kXlDiagWaves * kXlDiagPerWave;
+    hipLaunchKernelGGL(xl_diag16_kernel, dim3((unsigned)((ncells + per_block - 1) / per_block)),
+                       dim3(64 * kXlDiagWaves), 0, s, r, x, D, ncells, b);
+    hipLaunchKernelGGL(xl_apply16_kernel, dim3(nlines), dim3(kXlApplyThreads), 0, s, x, L, U, nx, b);
+  }
   else if (b <= 16)
     hipLaunchKernelGGL(xl_apply_kernel<16>, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
   else if (b <= 32)
