@@ -315,7 +315,12 @@ def extension_timing():
       (reads the state and the table, writes rows x 64 values);
     * a 1-D line at k = 5 (8192 cells, l_max = 7) and the 512 x 64 shock on a
       linear p axis (k = 2, l_max = 3), both on the general kernels: stage
-      launches, 16 B/DoF for the first stage and 24 B/DoF for the others."""
+      launches, 16 B/DoF for the first stage and 24 B/DoF for the others;
+    * the 1024 x 128 shock with a width of 2.5 (w_frac 0.25) instead of 0.1,
+      so that U' is nonzero on every x column and the stage kernel takes the
+      momentum terms everywhere (with the benchmark's width it skips them on
+      the columns where 1 - tanh^2(x/w) rounds to 0); its bytes per launch
+      include the input fields as the benchmark line's do."""
     import math
     import numpy as np
     import torch
@@ -359,6 +364,8 @@ def extension_timing():
             p_fixed=math.sqrt(3.0), flow=W.zero_flow, magnetic=W.uniform_field((0.0, 0.0, 1.0)), nu=1.0)),
         ("shock2d_x_p_512x64_k2_lmax3", W.shock_workload("shock_p", 512, 64, 2, 3, paxis="p",
                                                          lnp=(-1.0, 2.5), init=False)),
+        ("shock2d_x_lnp_1024x128_k2_lmax3_wide_shock", W.shock_workload("shock_wide", 1024, 128, 2, 3,
+                                                                       w_frac=0.25, init=False)),
     )
     for name, wl in cases:
         op = vfp.Operator(wl)
@@ -369,6 +376,8 @@ def extension_timing():
         steps = 20
         t = timed(lambda: op.advance(u, dt, steps, work), 1) / steps
         bts = N * (16 + 3 * 24) / 4
+        if name.endswith("wide_shock"):
+            bts += 8 * wl.ncells + 8 * wl.ncells * wl.n_basis + 8 * (1024 * 3 * 4 + 1025 + 128 * 3 * 4 + 129)
         out[name] = {"ndofs": N, "dofs_per_s": N / t, "us_per_launch": t / 4 * 1e6,
                      "bytes_per_launch": bts, "achieved_GBs": bts / (t / 4) / 1e9,
                      "frac": bts / (t / 4) / 1e9 / HBM_PEAK_GBS}
