@@ -69,18 +69,25 @@ __device__ bool xl_invert(double* S, int b, int* perm, int* sh_piv, double* sh_v
   const int tid = threadIdx.x;
   bool ok = true;
   for (int k = 0; k < b; ++k) {
-    if (tid == 0) {
-      int p = k;
-      double best = fabs(S[k * b + k]);
-      for (int r = k + 1; r < b; ++r) {
-        const double a = fabs(S[k * b + r]);
-        if (a > best) {
-          best = a;
-          p = r;
+    if (tid < 64) {
+      // the first row r >= k of largest |S[r][k]|: an arg-max over the
+      // first wavefront (b <= 64 rows), ties to the smaller row
+      const int r = k + tid;
+      double a = r < b ? fabs(S[k * b + r]) : -1.0;
+      int idx = r;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const double a2 = __shfl_xor(a, off, 64);
+        const int i2 = __shfl_xor(idx, off, 64);
+        if (a2 > a || (a2 == a && i2 < idx)) {
+          a = a2;
+          idx = i2;
         }
       }
-      perm[k] = p;
-      *sh_piv = p;
+      if (tid == 0) {
+        perm[k] = idx;
+        *sh_piv = idx;
+      }
     }
     __syncthreads();
     const int p = *sh_piv;
@@ -125,12 +132,17 @@ __device__ bool xl_invert(double* S, int b, int* perm, int* sh_piv, double* sh_v
 
 // One workgroup per line: S_i = D_i - L_i G_{i-1}, D_i <- S_i^{-1},
 // U_i <- G_i = S_i^{-1} U_i, L_i <- M_i = S_i^{-1} L_i (i > 0).
-// fail[line] = 1 if a block was singular.
+// fail[line] = 1 if a block was singular.  The next cell's three blocks are
+// loaded into registers while the current cell is worked on, and staged in
+// LDS, so that the block products read no global memory.
+constexpr int kXlPer = (kXlMaxBlock * kXlMaxBlock + kXlThreads - 1) / kXlThreads;   // block entries per thread
+
 __global__ __launch_bounds__(kXlThreads) void xl_factor_kernel(double* D, double* L, double* U, int nx, int b,
                                                               int* fail) {
   __shared__ double S[kXlMaxBlock * kXlMaxBlock];
   __shared__ double G[kXlMaxBlock * kXlMaxBlock];
-  __shared__ double Mt[kXlMaxBlock * kXlMaxBlock];
+  __shared__ double Lb[kXlMaxBlock * kXlMaxBlock];
+  __shared__ double Ub[kXlMaxBlock * kXlMaxBlock];
   __shared__ int perm[kXlMaxBlock];
   __shared__ int sh_piv;
   __shared__ double sh_val;
@@ -138,45 +150,57 @@ __global__ __launch_bounds__(kXlThreads) void xl_factor_kernel(double* D, double
   const int line = blockIdx.x;
   const int64_t bb = (int64_t)b * b;
   bool ok = true;
+  double nD[kXlPer], nL[kXlPer], nU[kXlPer];
+  auto load_blocks = [&](int i) {
+    const int64_t base = ((int64_t)line * nx + i) * bb;
+#pragma unroll
+    for (int t = 0; t < kXlPer; ++t) {
+      const int e = tid + t * kXlThreads;
+      const bool in = i < nx && e < bb;
+      nD[t] = in ? D[base + e] : 0.0;
+      nL[t] = in ? L[base + e] : 0.0;
+      nU[t] = in ? U[base + e] : 0.0;
+    }
+  };
+  load_blocks(0);
   for (int i = 0; i < nx; ++i) {
     const int64_t cell = (int64_t)line * nx + i;
-    for (int e = tid; e < b * b; e += blockDim.x) {
-      double s = D[cell * bb + e];
-      if (i > 0) {
-        // (L G)[r][c] = sum_k L[r][k] G[k][c]
-        const int c = e / b, r = e - c * b;
-        const double* Lc = L + cell * bb;
-        double acc = 0.0;
-        for (int k = 0; k < b; ++k) acc = fma(Lc[k * b + r], G[c * b + k], acc);
-        s -= acc;
+#pragma unroll
+    for (int t = 0; t < kXlPer; ++t) {
+      const int e = tid + t * kXlThreads;
+      if (e < bb) {
+        S[e] = nD[t];
+        Lb[e] = nL[t];
+        Ub[e] = nU[t];
       }
-      S[e] = s;
     }
     __syncthreads();
-    ok = xl_invert(S, b, perm, &sh_piv, &sh_val) && ok;
-    for (int e = tid; e < b * b; e += blockDim.x) D[cell * bb + e] = S[e];
+    load_blocks(i + 1);   // in flight during this cell
     if (i > 0) {
-      // M_i = S_i^{-1} L_i, staged in LDS: every thread still reads L_i
-      const double* Lc = L + cell * bb;
+      // S -= L G_{i-1}: (L G)[r][c] = sum_k L[r][k] G[k][c]
       for (int e = tid; e < b * b; e += blockDim.x) {
         const int c = e / b, r = e - c * b;
         double acc = 0.0;
-        for (int k = 0; k < b; ++k) acc = fma(S[k * b + r], Lc[c * b + k], acc);
-        Mt[e] = acc;
+        for (int k = 0; k < b; ++k) acc = fma(Lb[k * b + r], G[c * b + k], acc);
+        S[e] -= acc;
       }
       __syncthreads();
-      for (int e = tid; e < b * b; e += blockDim.x) L[cell * bb + e] = Mt[e];
     }
-    if (i + 1 < nx) {
-      const double* Uc = U + cell * bb;
-      for (int e = tid; e < b * b; e += blockDim.x) {
-        const int c = e / b, r = e - c * b;
+    ok = xl_invert(S, b, perm, &sh_piv, &sh_val) && ok;
+    for (int e = tid; e < b * b; e += blockDim.x) {
+      const int c = e / b, r = e - c * b;
+      D[cell * bb + e] = S[e];
+      if (i > 0) {   // M_i = S_i^{-1} L_i
         double acc = 0.0;
-        for (int k = 0; k < b; ++k) acc = fma(S[k * b + r], Uc[c * b + k], acc);
-        G[e] = acc;
+        for (int k = 0; k < b; ++k) acc = fma(S[k * b + r], Lb[c * b + k], acc);
+        L[cell * bb + e] = acc;
       }
-      __syncthreads();
-      for (int e = tid; e < b * b; e += blockDim.x) U[cell * bb + e] = G[e];
+      if (i + 1 < nx) {   // G_i = S_i^{-1} U_i (G_{i-1} is no longer read)
+        double acc = 0.0;
+        for (int k = 0; k < b; ++k) acc = fma(S[k * b + r], Ub[c * b + k], acc);
+        G[e] = acc;
+        U[cell * bb + e] = acc;
+      }
     }
     __syncthreads();
   }
