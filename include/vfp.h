@@ -202,9 +202,12 @@ int vfp_cfl_dt(const vfp_ctx* ctx, double courant, double* dt);
 /* Choose the fastest launch shape of this context's stage kernel by timing:
  * for the specialised (x, ln p) kernel, every built workgroup shape (lanes
  * per workgroup, and so cells per tile) and both tile orders (launch order,
- * or each of the 8 XCDs taking one contiguous range of tiles), reps launches
- * each of the stage-1 form (reads u, writes work: device, ndofs doubles,
- * disjoint from u; u is unchanged).  The choice stays with the context (a
+ * or each of the 8 XCDs taking one contiguous range of tiles), each timed on
+ * reps repetitions of a Runge-Kutta step's stage forms: one stage that reads
+ * u and writes work (device, ndofs doubles, disjoint from u) and three that
+ * read work and u and write a temporary vector of ndofs doubles that the
+ * call allocates and frees (VFP_ENOMEM if it cannot); two rounds over the
+ * candidates, each keeping its faster round.  u is unchanged.  The choice stays with the context (a
  * later set-up call keeps it where the kernel exists) and changes no result:
  * every shape computes each cell with the same arithmetic.  chosen (host,
  * 3 ints, may be NULL):
