@@ -32,7 +32,9 @@ struct RecShape {
   static constexpr int kTile = kRowStep * kRecRowsPerLane;   // node rows per tile
 };
 
-template <int DIRS>
+// NREG > 0 (n <= NREG): a lane keeps its two directions' table rows in
+// registers, read from LDS once, so the inner loop reads only the tile
+template <int DIRS, int NREG>
 __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(const double* __restrict__ zeta, int64_t rows,
                                                                    int n, const double* __restrict__ Y,
                                                                    int64_t ndir, double* __restrict__ out) {
@@ -63,6 +65,15 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(const double* 
   // thread -> (directions 2 dp and 2 dp + 1, rows rr + kRowStep q)
   const int dp = threadIdx.x % S::kPairs, rr = threadIdx.x / S::kPairs;
   const bool pairs = (ndir % 2) == 0 && (reinterpret_cast<uintptr_t>(out) % 16) == 0;   // 16-byte aligned pairs
+  double y0r[NREG > 0 ? NREG : 1], y1r[NREG > 0 ? NREG : 1];
+  if constexpr (NREG > 0) {
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < NREG; ++j) {
+      y0r[j] = j < n ? ys[(2 * dp) * pitch + j] : 0.0;
+      y1r[j] = j < n ? ys[(2 * dp + 1) * pitch + j] : 0.0;
+    }
+  }
   for (int64_t r0 = (int64_t)blockIdx.x * S::kTile; r0 < rows; r0 += (int64_t)gridDim.x * S::kTile) {
     __syncthreads();   // the previous tile's reads of zs are done
     for (int e = threadIdx.x; e < S::kTile * n; e += kRecThreads) {
@@ -73,15 +84,29 @@ __global__ __launch_bounds__(kRecThreads) void reconstruct_kernel(const double* 
     double a0[kRecRowsPerLane], a1[kRecRowsPerLane];
 #pragma unroll
     for (int q = 0; q < kRecRowsPerLane; ++q) a0[q] = a1[q] = 0.0;
-    const double* y0p = ys + (2 * dp) * pitch;
-    const double* y1p = y0p + pitch;
-    for (int j = 0; j < n; ++j) {
-      const double y0 = y0p[j], y1 = y1p[j];
+    if constexpr (NREG > 0) {
 #pragma unroll
-      for (int q = 0; q < kRecRowsPerLane; ++q) {
-        const double zv = zs[(rr + S::kRowStep * q) * pitch + j];
-        a0[q] = fma(zv, y0, a0[q]);
-        a1[q] = fma(zv, y1, a1[q]);
+      for (int j = 0; j < NREG; ++j) {
+        if (j < n) {
+#pragma unroll
+          for (int q = 0; q < kRecRowsPerLane; ++q) {
+            const double zv = zs[(rr + S::kRowStep * q) * pitch + j];
+            a0[q] = fma(zv, y0r[j], a0[q]);
+            a1[q] = fma(zv, y1r[j], a1[q]);
+          }
+        }
+      }
+    } else {
+      const double* y0p = ys + (2 * dp) * pitch;
+      const double* y1p = y0p + pitch;
+      for (int j = 0; j < n; ++j) {
+        const double y0 = y0p[j], y1 = y1p[j];
+#pragma unroll
+        for (int q = 0; q < kRecRowsPerLane; ++q) {
+          const double zv = zs[(rr + S::kRowStep * q) * pitch + j];
+          a0[q] = fma(zv, y0, a0[q]);
+          a1[q] = fma(zv, y1, a1[q]);
+        }
       }
     }
     // written once and not read again here: streaming stores
@@ -115,7 +140,12 @@ void launch_t(const double* zeta, int64_t rows, int n, const double* Y, int64_t 
   const int64_t tiles = (rows + S::kTile - 1) / S::kTile;
   const dim3 grid((unsigned)(tiles < 2048 ? tiles : 2048), (unsigned)((ndir + DIRS - 1) / DIRS));
   const size_t lds = DIRS == 64 ? 0 : (size_t)(S::kTile + DIRS) * (n + 1) * sizeof(double);
-  hipLaunchKernelGGL(reconstruct_kernel<DIRS>, grid, dim3(kRecThreads), lds, s, zeta, rows, n, Y, ndir, out);
+  // the register rows only where the workgroup's LDS already limits the
+  // occupancy (64 directions: 3 workgroups per CU either way)
+  if (DIRS == 64 && n <= 16)
+    hipLaunchKernelGGL((reconstruct_kernel<DIRS, 16>), grid, dim3(kRecThreads), lds, s, zeta, rows, n, Y, ndir, out);
+  else
+    hipLaunchKernelGGL((reconstruct_kernel<DIRS, 0>), grid, dim3(kRecThreads), lds, s, zeta, rows, n, Y, ndir, out);
 }
 
 // n > 64 (l_max 8..11): one output per lane, the row and the direction's
