@@ -489,9 +489,11 @@ int vfp_batch_bind(vfp_batch* b, double* const* u, double* const* work, const do
  * it; `stream` waits for the replays. */
 int vfp_batch_advance(vfp_batch* b, int64_t nsteps, void* stream);
 
-/* Time the batched kernel of every class over the bound buffers (stage-1
- * form: reads u, writes the first work vector; u is unchanged), reps
- * launches per candidate, for each workgroup shape (lanes per workgroup:
+/* Time the batched kernel of every class over the bound buffers, on a
+ * step's mix of stage forms (the first stage, which reads u and writes the
+ * first work vector, and three that read a work vector and u and write the
+ * other; u is unchanged), reps repetitions per candidate over two rounds
+ * keeping each candidate's faster one, for each workgroup shape (lanes per workgroup:
  * 64 / 128 / 256 where n = (l_max+1)^2 divides 64, else 256 / 64 / 128;
  * cells per tile follow) and each tile order -- launch order, or each of the
  * 8 XCDs taking one contiguous range of tiles -- and keep the fastest.

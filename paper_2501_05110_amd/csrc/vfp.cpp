@@ -2562,31 +2562,44 @@ int vfp_batch_advance(vfp_batch* b, int64_t nsteps, void* stream) {
 // both tile orders of a class's batched kernel and keeps the fastest.
 static int tune_class(vfp_batch* b, vfp_batch::Class& cl, int reps, hipStream_t st, hipEvent_t e0,
                       hipEvent_t e1) {
-  float best = 1e30f;
-  int bt = cl.tile_map, bs = cl.shape;
-  for (int shape = 0; shape < kShockShapes; ++shape) {
-    BatchKernel bk = find_shock_batch_kernel(cl.k, cl.lmax, cl.nrot, shape);
-    if (!bk.launch) continue;
-    cl.bk = bk;
-    cl.shape = shape;
-    if (int e = class_tiles(b, cl)) return e;
-    for (int tm : {0, 1}) {
-      cl.tile_map = tm;
-      // stage 1 form (reads u, writes the first work vector): u is untouched
-      if (int e = batch_launch_stage(b, cl, 0, st)) return e;
+  // every (shape, tile order) runs a step's mix of stage forms: the first
+  // stage (reads u) and three that read a work vector and u (stages 2, 3
+  // and 2 again: the last stage, which writes u, is left out so u stays
+  // untouched), reps times, over two rounds keeping each candidate's faster
+  // one
+  struct Cand {
+    int shape, tm;
+    float best;
+  };
+  std::vector<Cand> cand;
+  for (int shape = 0; shape < kShockShapes; ++shape)
+    if (find_shock_batch_kernel(cl.k, cl.lmax, cl.nrot, shape).launch)
+      for (int tm : {0, 1}) cand.push_back({shape, tm, 1e30f});
+  for (int round = 0; round < 2; ++round)
+    for (Cand& cd : cand) {
+      cl.bk = find_shock_batch_kernel(cl.k, cl.lmax, cl.nrot, cd.shape);
+      cl.shape = cd.shape;
+      if (int e = class_tiles(b, cl)) return e;
+      cl.tile_map = cd.tm;
+      for (int s : {0, 1, 2})
+        if (int e = batch_launch_stage(b, cl, s, st)) return e;
       HIP_TRY(hipEventRecord(e0, st));
       for (int i = 0; i < reps; ++i)
-        if (int e = batch_launch_stage(b, cl, 0, st)) return e;
+        for (int s : {0, 1, 2, 1})
+          if (int e = batch_launch_stage(b, cl, s, st)) return e;
       HIP_TRY(hipEventRecord(e1, st));
       HIP_TRY(hipEventSynchronize(e1));
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < best) {
-        best = ms;
-        bt = tm;
-        bs = shape;
-      }
+      cd.best = std::min(cd.best, ms);
     }
+  int bt = cl.tile_map, bs = cl.shape;
+  if (!cand.empty()) {
+    const Cand* w = &cand[0];
+    for (const Cand& cd : cand)
+      if (cd.best < w->best) w = &cd;
+    bt = w->tm;
+    bs = w->shape;
   }
   cl.tile_map = bt;
   cl.shape = bs;
