@@ -322,14 +322,15 @@ def test_support_keeps_profile_gradient(lib, cuda):
     op.close()
 
 
-@pytest.mark.parametrize("nx,npc,k,lmax", [(40, 6, 2, 3), (37, 5, 2, 3), (29, 4, 1, 1)])
+@pytest.mark.parametrize("nx,npc,k,lmax", [(40, 6, 2, 3), (37, 5, 2, 3), (29, 4, 1, 1), (31, 3, 2, 2)])
 def test_support_tiles_bit_identical(lib, cuda, nx, npc, k, lmax):
     """With a support set, only the tiles that hold a support cell run the
     U'/dU/dt part: every slot of a support cell and every U / U_face slot is
     bit-identical to the run without a support; the U'/dU/dt slots of the
     other cells are either that same value (a tile shared with a support
     cell) or untouched (zero), and some are untouched.  Odd nx puts tiles
-    across p rows and leaves a partial last tile."""
+    across p rows and leaves a partial last tile; l_max = 2 gives tiles of
+    7 cells."""
     import torch
     from paper_2501_05110_amd import vfp
     wl = W.shock_workload("tiles", nx, npc, k, lmax, w_frac=0.02, seed=9)
