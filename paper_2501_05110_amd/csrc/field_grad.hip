@@ -353,19 +353,33 @@ __device__ __forceinline__ void fgrad_body(const KernelArgs& A, const double* __
     wave_sync();
   }
 
-  // ---- one reduction over the cell's lanes for this part's slots
-  if (in_grp)
+  // ---- one reduction over the cell's lanes for this part's slots; each
+  // slot gets one add per launch, in stream order across launches (so the
+  // sum is reproducible), with no returned value, so nothing waits for it
+  if constexpr (N == 16) {
+    // the cell's 16 lanes are one DPP row: register reductions, lane r
+    // adding slot r (and r + 16)
+    double mine = 0.0, mine2 = 0.0;
 #pragma unroll
-    for (int i = 0; i < FR::NRED; ++i) X[i * N + r] = red[i];
-  wave_sync();
-  if (act)
-    for (int j = r; j < FR::NRED; j += N) {
-      double sum = 0.0;
-      for (int l = 0; l < N; ++l) sum += X[j * N + l];
-      // one add per slot and launch, in stream order across launches (so the
-      // sum is reproducible); no returned value, so nothing waits for it
-      atomicAdd(&slots[(size_t)cell * NS + FR::slot(j)], cdt * sum);
+    for (int i = 0; i < FR::NRED; ++i) {
+      const double sum = row16_sum(red[i]);
+      if (i == r) mine = sum;
+      if (i == r + 16) mine2 = sum;
     }
+    if (act && r < FR::NRED) atomicAdd(&slots[(size_t)cell * NS + FR::slot(r)], cdt * mine);
+    if (act && r + 16 < FR::NRED) atomicAdd(&slots[(size_t)cell * NS + FR::slot(r + 16)], cdt * mine2);
+  } else {
+    if (in_grp)
+#pragma unroll
+      for (int i = 0; i < FR::NRED; ++i) X[i * N + r] = red[i];
+    wave_sync();
+    if (act)
+      for (int j = r; j < FR::NRED; j += N) {
+        double sum = 0.0;
+        for (int l = 0; l < N; ++l) sum += X[j * N + l];
+        atomicAdd(&slots[(size_t)cell * NS + FR::slot(j)], cdt * sum);
+      }
+  }
 }
 
 // Both parts in one launch, spread evenly over the grid so that the two

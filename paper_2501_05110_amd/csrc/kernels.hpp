@@ -36,6 +36,27 @@ __device__ __forceinline__ global_ptr<T> gp(T* p) {
   return (global_ptr<T>)p;
 }
 
+// Moves within a row of 16 lanes (DPP), on the two
+// 32-bit halves of a double.  CTRL: 0xB1 / 0x4E quad permutes (lane ^ 1,
+// lane ^ 2), 0x124 / 0x128 rotations of the row by 4 / 8 lanes.  Every lane
+// of the row must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long bits = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(bits & 0xffffffffLL), CTRL, 0xf, 0xf, true);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(bits >> 32), CTRL, 0xf, 0xf, true);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The sum of v over the 16 lanes of this lane's DPP row, in every lane of it
+// (a fixed order: pairs, quads, quad pairs, then the two halves).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1>(v);
+  v += dpp_move<0x4E>(v);
+  v += dpp_move<0x124>(v);
+  return v + dpp_move<0x128>(v);
+}
+
 template <int B, int E>
 struct IPow { static constexpr int v = B * IPow<B, E - 1>::v; };
 template <int B>

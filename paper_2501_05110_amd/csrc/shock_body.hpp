@@ -697,14 +697,20 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) part = fma(w[b], ff[b], part);
       part *= gp(T.c_val)[r] * jac;
-      if (in_grp) X[r] = part;
-      cell_sync<N, TPB>();
-      if (act && r == 0) {
-        double sum = 0.0;
-        for (int j = 0; j < N; ++j) sum += X[j];
-        // one add per cell and launch, so stream order keeps the sum
-        // reproducible; nothing waits for the old value
-        atomicAdd(&A.adj.grad_nu[cell], -A.st.beta * F.t_col * sum);
+      // one add per cell and launch, so stream order keeps the sum
+      // reproducible; nothing waits for the old value
+      if constexpr (N == 16 && LS::kThreads == 64) {
+        // the cell's 16 lanes are one DPP row: a register reduction
+        const double sum = row16_sum(part);
+        if (act && r == 0) atomicAdd(&A.adj.grad_nu[cell], -A.st.beta * F.t_col * sum);
+      } else {
+        if (in_grp) X[r] = part;
+        cell_sync<N, TPB>();
+        if (act && r == 0) {
+          double sum = 0.0;
+          for (int j = 0; j < N; ++j) sum += X[j];
+          atomicAdd(&A.adj.grad_nu[cell], -A.st.beta * F.t_col * sum);
+        }
       }
     }
     if (act && gp(A.adj.t_out)) {
