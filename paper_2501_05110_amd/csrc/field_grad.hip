@@ -160,6 +160,15 @@ __device__ __forceinline__ void fgrad_body(const KernelArgs& A, const double* __
       nm[side][j] = mu[nb0 + (size_t)node * N];
     }
   }
+  // the ln p face codes are loaded with the state, so that the derivative
+  // table rows they select cost one round trip later, not two
+  int pcode[2][K1];
+  if constexpr (PART == 1) {
+#pragma unroll
+    for (int side = 0; side < 2; ++side)
+#pragma unroll
+      for (int q = 0; q < K1; ++q) pcode[side][q] = F.pf_code[(size_t)(ip + side) * (nx * K1) + ix * K1 + q];
+  }
   const double* xr = F.xrec + (size_t)ix * kRec;
   const double* pr = F.prec + (size_t)ip * kRec;
   const double s2hx = xr[11], s2hp = pr[14];
@@ -328,7 +337,7 @@ __device__ __forceinline__ void fgrad_body(const KernelArgs& A, const double* __
       const double tmv = pr[12 + side];     // t_mom / V at this face
 #pragma unroll
       for (int q = 0; q < K1; ++q) {
-        const int code = F.pf_code[(size_t)(ip + side) * (nx * K1) + ix * K1 + q];
+        const int code = pcode[side][q];
         const double* Pu = (code == -1) ? R1 + q * N : R2 + q * N;
         double ja = -t_mom * tmv * fma(axv0, Pu[axc0], axv1 * Pu[axc1]);
         double ju = -t_mom * fma(axxv0, Pu[axxc0], fma(axxv1, Pu[r], axxv2 * Pu[axxc1]));
