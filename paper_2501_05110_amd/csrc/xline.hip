@@ -453,6 +453,146 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(double* x, 
   }
 }
 
+// The factorisation for b <= 16 by one wavefront per line: the same
+// operations in the same order as xl_factor_kernel (so the same blocks, bit
+// for bit), ordered by wavefront-level fences instead of workgroup barriers,
+// each lane holding 4 of the 256 entries of a block, and the pivot found by
+// a DPP arg-max within the first 16-lane row.
+template <int CTRL>
+__device__ __forceinline__ int xl_dpp_int(int v) {
+  return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+
+// arg-max of a over the lanes of each 16-lane row (ties to the smaller
+// index), in every lane of the row
+__device__ __forceinline__ void xl_row16_argmax(double& a, int& idx) {
+#define XL_ARGMAX_STEP(CTRL)                                          \
+  {                                                                   \
+    const double a2 = xl_quad_swap<CTRL>(a);                          \
+    const int i2 = xl_dpp_int<CTRL>(idx);                             \
+    if (a2 > a || (a2 == a && i2 < idx)) {                            \
+      a = a2;                                                         \
+      idx = i2;                                                       \
+    }                                                                 \
+  }
+  XL_ARGMAX_STEP(0x121)   // row_ror:1
+  XL_ARGMAX_STEP(0x122)   // row_ror:2
+  XL_ARGMAX_STEP(0x124)   // row_ror:4
+  XL_ARGMAX_STEP(0x128)   // row_ror:8
+#undef XL_ARGMAX_STEP
+}
+
+__global__ __launch_bounds__(64) void xl_factor16_kernel(double* D, double* L, double* U, int nx, int b,
+                                                        int* fail) {
+  __shared__ double S[256], G[256], Lb[256], Ub[256];
+  __shared__ int perm[16];
+  const int lane = threadIdx.x;
+  const int line = blockIdx.x;
+  const int bb = b * b;
+  bool ok = true;
+  double nD[4], nL[4], nU[4];
+  auto load_blocks = [&](int i) {
+    const int64_t base = ((int64_t)line * nx + i) * bb;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = lane + 64 * t;
+      const bool in = i < nx && e < bb;
+      nD[t] = in ? D[base + e] : 0.0;
+      nL[t] = in ? L[base + e] : 0.0;
+      nU[t] = in ? U[base + e] : 0.0;
+    }
+  };
+  load_blocks(0);
+  for (int i = 0; i < nx; ++i) {
+    const int64_t cell = (int64_t)line * nx + i;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = lane + 64 * t;
+      if (e < bb) {
+        S[e] = nD[t];
+        Lb[e] = nL[t];
+        Ub[e] = nU[t];
+      }
+    }
+    xl_wave_sync();
+    load_blocks(i + 1);
+    if (i > 0) {
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int e = lane + 64 * t;
+        if (e < bb) {
+          const int c = e / b, r = e - c * b;
+          double acc = 0.0;
+          for (int k = 0; k < b; ++k) acc = fma(Lb[k * b + r], G[c * b + k], acc);
+          S[e] -= acc;
+        }
+      }
+      xl_wave_sync();
+    }
+    // Gauss-Jordan with partial pivoting (as xl_invert)
+    for (int k = 0; k < b; ++k) {
+      double a = (lane >= k && lane < b) ? fabs(S[k * b + lane]) : -1.0;
+      int idx = lane;
+      xl_row16_argmax(a, idx);
+      const int p = __builtin_amdgcn_readfirstlane(idx);
+      if (lane == 0) perm[k] = p;
+      if (p != k && lane < b) {
+        const double t0 = S[lane * b + k];
+        S[lane * b + k] = S[lane * b + p];
+        S[lane * b + p] = t0;
+      }
+      xl_wave_sync();
+      const double pv = S[k * b + k];
+      if (pv == 0.0) ok = false;
+      const double ipv = 1.0 / pv;
+      xl_wave_sync();
+      if (lane < b) S[lane * b + k] = (lane == k) ? ipv : S[lane * b + k] * ipv;
+      xl_wave_sync();
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int e = lane + 64 * t;
+        if (e < bb) {
+          const int c = e / b, r = e - c * b;
+          if (r != k && c != k) S[e] = fma(-S[k * b + r], S[c * b + k], S[e]);
+        }
+      }
+      xl_wave_sync();
+      if (lane < b && lane != k) S[k * b + lane] = -S[k * b + lane] * ipv;
+      xl_wave_sync();
+    }
+    for (int k = b - 1; k >= 0; --k) {
+      const int p = perm[k];
+      if (p != k && lane < b) {
+        const double t0 = S[k * b + lane];
+        S[k * b + lane] = S[p * b + lane];
+        S[p * b + lane] = t0;
+      }
+      xl_wave_sync();
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int e = lane + 64 * t;
+      if (e < bb) {
+        const int c = e / b, r = e - c * b;
+        D[cell * bb + e] = S[e];
+        if (i > 0) {
+          double acc = 0.0;
+          for (int k = 0; k < b; ++k) acc = fma(S[k * b + r], Lb[c * b + k], acc);
+          L[cell * bb + e] = acc;
+        }
+        if (i + 1 < nx) {
+          double acc = 0.0;
+          for (int k = 0; k < b; ++k) acc = fma(S[k * b + r], Ub[c * b + k], acc);
+          G[e] = acc;
+          U[cell * bb + e] = acc;
+        }
+      }
+    }
+    xl_wave_sync();
+  }
+  if (lane == 0) fail[line] = ok ? 0 : 1;
+}
+
 }  // namespace
 
 void xl_probe_set(double* v, int64_t ndofs, int nx, int b, int wrapc, int color, int j, hipStream_t s) {
@@ -469,7 +609,10 @@ void xl_probe_get(const double* w, double* D, double* L, double* U, int64_t ndof
 }
 
 void xl_factor(double* D, double* L, double* U, int nlines, int nx, int b, int* fail, hipStream_t s) {
-  hipLaunchKernelGGL(xl_factor_kernel, dim3(nlines), dim3(kXlThreads), 0, s, D, L, U, nx, b, fail);
+  if (b <= 16)
+    hipLaunchKernelGGL(xl_factor16_kernel, dim3(nlines), dim3(64), 0, s, D, L, U, nx, b, fail);
+  else
+    hipLaunchKernelGGL(xl_factor_kernel, dim3(nlines), dim3(kXlThreads), 0, s, D, L, U, nx, b, fail);
 }
 
 void xl_apply(const double* r, double* x, const double* D, const double* L, const double* U, int nlines, int nx,
