@@ -317,6 +317,7 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply_kernel(const double*
 #endif
 constexpr int kXlRing = VFP_XL_RING;
 constexpr int kXlDiagWaves = 4;     // wavefronts per workgroup of xl_diag16_kernel
+constexpr size_t kXlLineLds = 60 * 1024;   // dynamic LDS for a line's rows (under the 64 KB default)
 constexpr int kXlDiagPerWave = 4;   // cells per wavefront
 
 // v from lane (lane ^ 1) and (lane ^ 2) of the same quad (DPP quad_perm)
@@ -370,10 +371,15 @@ __global__ __launch_bounds__(64 * kXlDiagWaves) void xl_diag16_kernel(const doub
     if (q == 0 && on && first + c < ncells) x[(first + c) * b + row] = out[c];
 }
 
-// the two sweeps; x holds S_i^{-1} r_i on entry and P^{-1} r on exit
+// the two sweeps; x holds S_i^{-1} r_i on entry and P^{-1} r on exit.
+// LY: the line's y (then x) rows stay in LDS (nx b doubles of dynamic LDS)
+// and go to x in one coalesced pass at the end, so the recurrences issue no
+// global stores and the backward ring holds only the rows of G.
+template <bool LY>
 __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(double* x, const double* __restrict__ M,
                                                                     const double* __restrict__ U, int nx, int b) {
   __shared__ double v[16];
+  extern __shared__ double ys[];
   const int lane = threadIdx.x;
   const int row = lane >> 2, q = lane & 3;
   const bool on = row < b;
@@ -390,14 +396,17 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(double* x, 
   // are skipped in prod, rows >= b and cells past the line's end are not
   // stored).
   const int rr = on ? row : 0;
-  auto fetch = [&](double (&a)[4], double& w, const double* A, const double* vec, int i) {
+  auto fetch_rows = [&](double (&a)[4], const double* A, int i) {
     const int64_t cell = c0 + ((i >= 0 && i < nx) ? i : 0);
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       const int k = (q + 4 * m < b) ? q + 4 * m : 0;
       a[m] = A[cell * bb + (int64_t)k * b + rr];
     }
-    w = vec[cell * b + rr];
+  };
+  auto fetch = [&](double (&a)[4], double& w, const double* A, const double* vec, int i) {
+    fetch_rows(a, A, i);
+    w = vec[(c0 + ((i >= 0 && i < nx) ? i : 0)) * b + rr];
   };
   auto prod = [&](const double (&a)[4]) {
     double acc = 0.0;
@@ -407,7 +416,8 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(double* x, 
     return xl_quad_sum(acc);
   };
   // forward: y_i = c_i - M_i y_{i-1}; p1 = M rows, pv = c (read from x, where
-  // y_i then goes: each cell's c is read kXlRing cells before its y is stored)
+  // y_i may then go: each cell's c is read kXlRing cells before its y is
+  // stored)
 #pragma unroll
   for (int s = 0; s < kXlRing; ++s) fetch(p1[s], pv[s], M, x, s);
   double prev = 0.0;
@@ -423,20 +433,31 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(double* x, 
           xl_wave_sync();
           y -= prod(p1[s]);
         }
-        if (q == 0 && on) x[(c0 + i) * b + row] = y;
+        if (q == 0 && on) {
+          if constexpr (LY)
+            ys[i * b + row] = y;
+          else
+            x[(c0 + i) * b + row] = y;
+        }
         prev = y;
       }
       fetch(p1[s], pv[s], M, x, i + kXlRing);
     }
   }
-  // backward: x_i = y_i - G_i x_{i+1}, i = nx-2 .. 0; p1 = G rows, pv = y.
-  // The y rows were stored above by the quad's lane 0 and are read back by
-  // all four lanes: order those stores before these loads
+  // backward: x_i = y_i - G_i x_{i+1}, i = nx-2 .. 0; p1 = G rows (and pv =
+  // y from x without LY).  The y rows were stored above by the quad's lane 0
+  // and are read back by all four lanes: order those stores before these
+  // loads
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 #pragma unroll
-  for (int s = 0; s < kXlRing; ++s) fetch(p1[s], pv[s], U, x, nx - 2 - s);
+  for (int s = 0; s < kXlRing; ++s) {
+    if constexpr (LY)
+      fetch_rows(p1[s], U, nx - 2 - s);
+    else
+      fetch(p1[s], pv[s], U, x, nx - 2 - s);
+  }
   for (int j0 = 0; j0 < nx - 1; j0 += kXlRing) {
 #pragma unroll
     for (int s = 0; s < kXlRing; ++s) {
@@ -445,11 +466,23 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply16_kernel(double* x, 
         xl_wave_sync();
         if (q == 0 && on) v[row] = prev;
         xl_wave_sync();
-        prev = pv[s] - prod(p1[s]);
-        if (q == 0 && on) x[(c0 + i) * b + row] = prev;
+        if constexpr (LY) {
+          prev = ys[i * b + rr] - prod(p1[s]);
+          if (q == 0 && on) ys[i * b + row] = prev;
+        } else {
+          prev = pv[s] - prod(p1[s]);
+          if (q == 0 && on) x[(c0 + i) * b + row] = prev;
+        }
       }
-      fetch(p1[s], pv[s], U, x, i - kXlRing);
+      if constexpr (LY)
+        fetch_rows(p1[s], U, i - kXlRing);
+      else
+        fetch(p1[s], pv[s], U, x, i - kXlRing);
     }
+  }
+  if constexpr (LY) {
+    xl_wave_sync();
+    for (int e = lane; e < nx * b; e += kXlApplyThreads) x[c0 * b + e] = ys[e];
   }
 }
 
@@ -622,7 +655,12 @@ void xl_apply(const double* r, double* x, const double* D, const double* L, cons
     constexpr int per_block = kXlDiagWaves * kXlDiagPerWave;
     hipLaunchKernelGGL(xl_diag16_kernel, dim3((unsigned)((ncells + per_block - 1) / per_block)),
                        dim3(64 * kXlDiagWaves), 0, s, r, x, D, ncells, b);
-    hipLaunchKernelGGL(xl_apply16_kernel, dim3(nlines), dim3(kXlApplyThreads), 0, s, x, L, U, nx, b);
+    // the line's rows in LDS where they fit the default dynamic LDS limit
+    const size_t ly = (size_t)nx * b * sizeof(double);
+    if (ly <= kXlLineLds)
+      hipLaunchKernelGGL(xl_apply16_kernel<true>, dim3(nlines), dim3(kXlApplyThreads), ly, s, x, L, U, nx, b);
+    else
+      hipLaunchKernelGGL(xl_apply16_kernel<false>, dim3(nlines), dim3(kXlApplyThreads), 0, s, x, L, U, nx, b);
   }
   else if (b <= 16)
     hipLaunchKernelGGL(xl_apply_kernel<16>, dim3(nlines), dim3(kXlApplyThreads), 0, s, r, x, D, L, U, nx, b);
