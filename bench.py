@@ -24,9 +24,11 @@ per class) against one run per launch sequence on the same GPU
 (--batch-small: 512 small runs), and the stage throughput of the 3-D box
 (48^3, k=2, l_max=5) and the 1-D line (64 cells, k=1, l_max=3), and
 Theta-method steps (Crank-Nicolson, backward Euler) of the 512 x 64 shock at
-10 times the explicit time step, and (with the other configurations) the
-reconstruction of f in 64 directions, a k = 5 line and the shock on a linear
-p axis.
+10 times the explicit time step and the Sec. 4.4 run on its 410 x 256 grid
+by implicit steps with the x-line preconditioner, and (with the other
+configurations) the reconstruction of f in 64 directions, a k = 5 line, the
+shock on a linear p axis and the 1024 x 128 stage with a shock wide enough
+that the flow gradient is nonzero on every x column.
 """
 
 from __future__ import annotations
