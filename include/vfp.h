@@ -55,7 +55,7 @@ extern "C" {
 #define VFP_ENOMEM       -2   /* allocation failed */
 #define VFP_EDEVICE      -3   /* HIP runtime error */
 #define VFP_ESTATE       -4   /* call out of order (e.g. apply before set_mesh) */
-#define VFP_EUNSUPPORTED -5   /* valid request this build does not handle */
+#define VFP_EUNSUPPORTED -5   /* valid request the library does not handle */
 
 /* axis kinds (reduced phase space xi, Sec. 2.2) */
 #define VFP_AXIS_X   0
