@@ -71,7 +71,8 @@ __device__ __forceinline__ void mdot_rows(const double* __restrict__ V, int64_t 
 __global__ __launch_bounds__(kKryThreads) void mdot_partial_kernel(const double* __restrict__ V, int64_t ldv,
                                                                     int k, const double* __restrict__ w,
                                                                     int64_t n, double* __restrict__ partial,
-                                                                    int self) {
+                                                                    int self, const double* __restrict__ enable) {
+  if (enable && *enable == 0.0) return;   // a pass the device decided to skip
   const int j0 = blockIdx.y * kDotChunk;
   const bool do_self = self && blockIdx.y == 0;
   double acc[kDotChunk], ws = 0.0;
@@ -115,7 +116,9 @@ __global__ __launch_bounds__(kKryThreads) void mdot_partial_kernel(const double*
 
 // out[j] = sum_b partial[j][b]  (one block per j)
 __global__ __launch_bounds__(kKryThreads) void mdot_final_kernel(const double* __restrict__ partial, int nblk,
-                                                                  double* __restrict__ out) {
+                                                                  double* __restrict__ out,
+                                                                  const double* __restrict__ enable) {
+  if (enable && *enable == 0.0) return;
   const int j = blockIdx.x;
   double s = 0.0;
   for (int b = threadIdx.x; b < nblk; b += kKryThreads) s += partial[(int64_t)j * nblk + b];
@@ -135,7 +138,9 @@ __global__ __launch_bounds__(kKryThreads) void mdot_final_kernel(const double* _
 // partial[blockIdx.x] = sum over this block's elements of the new w . w
 __global__ __launch_bounds__(kKryThreads) void maxpy_kernel(double* __restrict__ w, const double* __restrict__ V,
                                                              int64_t ldv, int k, const double* __restrict__ coef,
-                                                             double sign, int64_t n, double* __restrict__ partial) {
+                                                             double sign, int64_t n, double* __restrict__ partial,
+                                                             const double* __restrict__ enable) {
+  if (enable && *enable == 0.0) return;
   __shared__ double cs[kKryMaxVectors];
   for (int j = threadIdx.x; j < k; j += kKryThreads) cs[j] = sign * coef[j];
   __syncthreads();
@@ -177,6 +182,27 @@ __global__ __launch_bounds__(kKryThreads) void coll_precond_kernel(double* out, 
   }
 }
 
+// The classical Gram-Schmidt step's decision on the device: a second pass
+// where the first removed more than half of |w|^2 (d3[1] = |w_new|^2,
+// d1[j + 1] = |w_old|^2); d3[4] = 1 or 0.
+__global__ void decide_kernel(const double* __restrict__ d1, int j, double* __restrict__ d3) {
+  if (threadIdx.x == 0) d3[4] = d3[1] < 0.5 * d1[j + 1] ? 1.0 : 0.0;
+}
+
+// hn = |w| after the Gram-Schmidt passes (d3[2] after a second pass, else
+// d3[1]) into d3[3], and out = w / hn (out may be null)
+__global__ __launch_bounds__(kKryThreads) void norm_scale_kernel(double* __restrict__ out,
+                                                                  const double* __restrict__ w, int64_t n,
+                                                                  double* __restrict__ d3) {
+  const double hn2 = d3[4] != 0.0 ? d3[2] : d3[1];
+  const double hn = sqrt(hn2 > 0.0 ? hn2 : 0.0);
+  if (blockIdx.x == 0 && threadIdx.x == 0) d3[3] = hn;
+  if (!out) return;
+  const double a = 1.0 / hn;
+  const int64_t stride = (int64_t)gridDim.x * kKryThreads;
+  for (int64_t i = (int64_t)blockIdx.x * kKryThreads + threadIdx.x; i < n; i += stride) out[i] = a * w[i];
+}
+
 int grid_for(int64_t n) {
   const int64_t g = (n + kKryThreads - 1) / kKryThreads;
   return (int)(g < 1 ? 1 : (g > kKryBlocks ? kKryBlocks : g));
@@ -185,21 +211,30 @@ int grid_for(int64_t n) {
 }  // namespace
 
 void kry_mdot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial, double* out,
-              hipStream_t s, bool self) {
+              hipStream_t s, bool self, const double* enable) {
   if (k <= 0) return;
   const dim3 grid(kKryBlocks, (k + kDotChunk - 1) / kDotChunk);
-  hipLaunchKernelGGL(mdot_partial_kernel, grid, dim3(kKryThreads), 0, s, V, ldv, k, w, n, partial, self ? 1 : 0);
+  hipLaunchKernelGGL(mdot_partial_kernel, grid, dim3(kKryThreads), 0, s, V, ldv, k, w, n, partial, self ? 1 : 0,
+                     enable);
   hipLaunchKernelGGL(mdot_final_kernel, dim3(k + (self ? 1 : 0)), dim3(kKryThreads), 0, s, partial, kKryBlocks,
-                     out);
+                     out, enable);
 }
 
 void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coef, double sign, int64_t n,
-               hipStream_t s, double* partial, double* norm2) {
+               hipStream_t s, double* partial, double* norm2, const double* enable) {
   if (k <= 0) return;
   const int g = grid_for(n);
   hipLaunchKernelGGL(maxpy_kernel, dim3(g), dim3(kKryThreads), 0, s, w, V, ldv, k, coef, sign, n,
-                     norm2 ? partial : nullptr);
-  if (norm2) hipLaunchKernelGGL(mdot_final_kernel, dim3(1), dim3(kKryThreads), 0, s, partial, g, norm2);
+                     norm2 ? partial : nullptr, enable);
+  if (norm2) hipLaunchKernelGGL(mdot_final_kernel, dim3(1), dim3(kKryThreads), 0, s, partial, g, norm2, enable);
+}
+
+void kry_decide(const double* d1, int j, double* d3, hipStream_t s) {
+  hipLaunchKernelGGL(decide_kernel, dim3(1), dim3(64), 0, s, d1, j, d3);
+}
+
+void kry_norm_scale(double* out, const double* w, int64_t n, double* d3, hipStream_t s) {
+  hipLaunchKernelGGL(norm_scale_kernel, dim3(out ? grid_for(n) : 1), dim3(kKryThreads), 0, s, out, w, n, d3);
 }
 
 void kry_coll_precond(double* out, const double* in, const double* nu, double nu0, const double* cval, double s,

@@ -73,10 +73,17 @@ int field_grad_tiles(int ncells, int lmax);
 // kry_lincomb: out = a x + b y.
 constexpr int kKryMaxVectors = 72;
 constexpr int kKryBlocks = 1024;
+// enable (device, may be null): the pass is skipped where *enable == 0.
 void kry_mdot(const double* V, int64_t ldv, int k, const double* w, int64_t n, double* partial, double* out,
-              hipStream_t s, bool self = false);
+              hipStream_t s, bool self = false, const double* enable = nullptr);
 void kry_maxpy(double* w, const double* V, int64_t ldv, int k, const double* coef, double sign, int64_t n,
-               hipStream_t s, double* partial = nullptr, double* norm2 = nullptr);
+               hipStream_t s, double* partial = nullptr, double* norm2 = nullptr, const double* enable = nullptr);
+// d3[4] = 1 where the first Gram-Schmidt pass left less than half of |w|^2
+// (d3[1] against d1[j + 1]), else 0
+void kry_decide(const double* d1, int j, double* d3, hipStream_t s);
+// d3[3] = hn = |w| after the passes (d3[2] if d3[4], else d3[1]); out = w / hn
+// unless out is null
+void kry_norm_scale(double* out, const double* w, int64_t n, double* d3, hipStream_t s);
 void kry_lincomb(double* out, double a, const double* x, double b, const double* y, int64_t n, hipStream_t s);
 // flag[0] = 1 if x (n doubles) holds a NaN or an infinity (flag left as is otherwise)
 void kry_nonfinite(const double* x, int64_t n, int* flag, hipStream_t s);

@@ -2052,6 +2052,12 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
   }
   std::vector<double> H((size_t)(m + 1) * m, 0.0), g(m + 1), cs(m), sn(m), y(m), hb(3 * kKryMaxVectors);
   int64_t used = 0;
+  hipEvent_t ev;
+  HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  struct EvGuard {
+    hipEvent_t e;
+    ~EvGuard() { (void)hipEventDestroy(e); }
+  } ev_guard{ev};
   for (;;) {
     // true residual r = b - A u into V_0
     if (int e = theta_op(c, u, t.w, dt, th, stream)) return e;
@@ -2071,32 +2077,51 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int j = 0;
-    while (j < m && used < o.max_iters) {
-      // w = A P^{-1} V_j, orthogonalised against V_0..V_j by classical
-      // Gram-Schmidt; a second pass only where the first removed most of w
-      // (the criterion of Daniel, Gragg, Kaufman and Stewart:
-      // |w_new| < |w_old| / sqrt 2)
-      const double* vin = t.V + (int64_t)j * N;
+    // w = A P^{-1} V_j, orthogonalised against V_0..V_j by classical
+    // Gram-Schmidt; a second pass only where the first removed most of w
+    // (the criterion of Daniel, Gragg, Kaufman and Stewart:
+    // |w_new| < |w_old| / sqrt 2).  The decision, the second pass and the
+    // normalisation V_{j+1} = w / |w| run on the device (d3[4] the decision,
+    // d3[3] = |w|), so that iteration j + 1's launches can be queued before
+    // the host has read iteration j's Hessenberg column: the host's round
+    // trip then overlaps the next iteration's kernels.  Where the column
+    // shows convergence, that queued iteration's results are not used.
+    auto front = [&](int jj) -> int {
+      const double* vin = t.V + (int64_t)jj * N;
       if (pre) {
         precond(t.z, vin);
         vin = t.z;
       }
       if (int e = theta_op(c, vin, t.w, dt, th, stream)) return e;
-      // d1[0..j] = V^T w and d1[j+1] = |w|^2 in one pass over w; the update
-      // leaves |w_new|^2 in d3[1]
-      kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d1, st, true);
-      kry_maxpy(t.w, t.V, N, j + 1, t.d1, -1.0, N, st, t.partial, t.d3 + 1);
-      if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st, c->h_kry.p)) return e;
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hb[i];
-      double hn2 = hb[2 * kKryMaxVectors + 1];
-      if (hn2 < 0.5 * hb[j + 1]) {
-        kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d2, st);
-        kry_maxpy(t.w, t.V, N, j + 1, t.d2, -1.0, N, st, t.partial, t.d3 + 2);
-        if (int e = fetch(hb.data(), t.d1, 3 * kKryMaxVectors, st, c->h_kry.p)) return e;
-        for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] += hb[kKryMaxVectors + i];
-        hn2 = hb[2 * kKryMaxVectors + 2];
-      }
-      const double hn = std::sqrt(std::max(hn2, 0.0));
+      // d1[0..jj] = V^T w and d1[jj+1] = |w|^2 in one pass over w; the
+      // update leaves |w_new|^2 in d3[1]
+      kry_mdot(t.V, N, jj + 1, t.w, N, t.partial, t.d1, st, true);
+      kry_maxpy(t.w, t.V, N, jj + 1, t.d1, -1.0, N, st, t.partial, t.d3 + 1);
+      return VFP_OK;
+    };
+    if (int e = front(0)) return e;
+    bool queued = true;   // front(j) is in the stream
+    while (j < m && used < o.max_iters) {
+      if (!queued)
+        if (int e = front(j)) return e;
+      kry_decide(t.d1, j, t.d3, st);
+      kry_mdot(t.V, N, j + 1, t.w, N, t.partial, t.d2, st, false, t.d3 + 4);
+      kry_maxpy(t.w, t.V, N, j + 1, t.d2, -1.0, N, st, t.partial, t.d3 + 2, t.d3 + 4);
+      kry_norm_scale(j + 1 < m ? t.V + (int64_t)(j + 1) * N : nullptr, t.w, N, t.d3, st);
+      HIP_TRY(hipMemcpyAsync(c->h_kry.p, t.d1, 3 * kKryMaxVectors * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipEventRecord(ev, st));
+      // queue the next iteration unless the residual estimate so far is
+      // within a factor 100 of the tolerance (then this one may well be the
+      // last, and a queued iteration would be wasted work)
+      queued = j + 1 < m && used + 1 < o.max_iters && std::fabs(g[j]) > 100.0 * o.tol * bn;
+      if (queued)
+        if (int e = front(j + 1)) return e;
+      HIP_TRY(hipEventSynchronize(ev));
+      std::memcpy(hb.data(), c->h_kry.p, 3 * kKryMaxVectors * sizeof(double));
+      const bool second = hb[2 * kKryMaxVectors + 4] != 0.0;
+      for (int i = 0; i <= j; ++i)
+        H[(size_t)i * m + j] = second ? hb[i] + hb[kKryMaxVectors + i] : hb[i];
+      const double hn = hb[2 * kKryMaxVectors + 3];
       H[(size_t)(j + 1) * m + j] = hn;
       ++used;
       // previous Givens rotations, then the one that removes H[j+1][j]
@@ -2115,7 +2140,6 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
       g[j] = cs[j] * g[j];
       ++j;
       if (std::fabs(g[j]) <= o.tol * bn || hn == 0.0) break;
-      if (j < m) kry_lincomb(t.V + (int64_t)j * N, 1.0 / hn, t.w, 0.0, nullptr, N, st);
     }
     // y = H^{-1} g (upper triangular), u += V y
     for (int i = j - 1; i >= 0; --i) {
@@ -2126,8 +2150,9 @@ int theta_step(vfp_ctx* c, double* u, double dt, const vfp_theta_opts& o, const 
     }
     HIP_TRY(hipMemcpyAsync(t.d1, y.data(), j * sizeof(double), hipMemcpyHostToDevice, st));
     if (pre) {
-      // u += P^{-1} V y
-      kry_lincomb(t.z, 0.0, t.z, 0.0, nullptr, N, st);
+      // u += P^{-1} V y (z is cleared from V_0, which is finite: z may hold
+      // the unused results of a queued iteration)
+      kry_lincomb(t.z, 0.0, t.V, 0.0, nullptr, N, st);
       kry_maxpy(t.z, t.V, N, j, t.d1, 1.0, N, st);
       precond(t.z, t.z);
       kry_lincomb(u, 1.0, u, 1.0, t.z, N, st);
