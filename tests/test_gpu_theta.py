@@ -126,6 +126,27 @@ def test_theta_collision_preconditioner(lib, cuda):
     assert st["converged"] and st["iterations"] <= 3
 
 
+def test_theta_short_restarts_and_iteration_cap(lib, cuda):
+    """Restarts every 4 Krylov vectors (so the next iteration is often queued
+    across a restart boundary) still give the oracle's step, and an
+    iteration cap stops the solve after exactly that many iterations with a
+    finite state (a queued iteration that is not used is not counted)."""
+    from paper_2501_05110_amd.vfp import Operator
+    wl = shock(16, 6, 2, 3)
+    op = Operator(wl)
+    dt = 10.0 * op.cfl_dt(0.2)
+    z = W.random_state(wl, 53)
+    want = dg.theta_step(dg.assemble(wl), z, dt, 0.5, 2)
+    got, st = _gpu_theta(op, z, dt, 0.5, 2, tol=1e-12, restart=4, max_iters=5000)
+    err = rel_inf(got, want)
+    _say(f"[theta restarts] restart=4: iterations={st['iterations']} residual={st['residual']:.2e} rel_inf={err:.3e}")
+    assert st["converged"] and err <= THETA_TOL
+    capped, st2 = _gpu_theta(op, z, dt, 0.5, 1, tol=1e-14, restart=4, max_iters=7)
+    _say(f"   capped: iterations={st2['iterations']} converged={st2['converged']} residual={st2['residual']:.2e}")
+    assert st2["iterations"] == 7 and not st2["converged"]
+    assert np.isfinite(capped).all()
+
+
 def _x_transport(nx=40, k=2, lmax=3, U=(0.3, 0.0, 0.0)):
     """Advection along one axis only (fixed p, uniform flow, zero inflow /
     continuous ends): the system is block-tridiagonal along x."""
