@@ -310,8 +310,11 @@ __global__ __launch_bounds__(kXlApplyThreads) void xl_apply_kernel(const double*
 // at once (xl_diag16_kernel, into x); the sweep then keeps the rows of the
 // next kXlRing cells in a ring of registers (a loop unrolled by kXlRing, so
 // every slot index is a constant): the loads of cell i + kXlRing are issued
-// as cell i is done, so about kXlRing steps of the recurrence hide each
-// load's latency.
+// as cell i is done, to hide their latency behind the next steps (the
+// compiler's wait counts for loads in flight across the loop's back edge
+// are conservative, so the lookahead it keeps is shorter; the steps
+// themselves, an LDS exchange, four dependent FMAs and two DPP exchanges,
+// bound the sweep).
 #ifndef VFP_XL_RING
 #define VFP_XL_RING 12
 #endif
