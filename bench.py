@@ -197,7 +197,8 @@ def adjoint_timing(steps=1000):
             "full_tape": taped,
             "note": "reverse = replay of each segment into a stage tape + adjoint stages with the "
                     "fused dJ/dnu accumulation (dJ/du0, dJ/dnu for 32768 cells); with_flow adds the "
-                    "planar-flow sensitivities that give dJ/d(r, w)"}
+                    "planar-flow sensitivities that give dJ/d(r, w), whose launches then also form dJ/dnu (the adjoint "
+                    "stages skip the forward state)"}
 
 
 def batch_timing(full=False, steps=None):

@@ -307,7 +307,11 @@ int vfp_advance_tape(vfp_ctx* ctx, const double* u0, double dt, int64_t nsteps, 
  * linear autonomous system, each step maps mu to P(dt K) mu.
  * grad_nu (ncells doubles, may be NULL) accumulates dJ/dnu_c; field_slots
  * (vfp_field_grad_size doubles, may be NULL) accumulates the planar-flow
- * sensitivities (see vfp_field_grad_stage).  work: 3 ndofs doubles. */
+ * sensitivities (see vfp_field_grad_stage).  With both, the dJ/dnu term of
+ * each stage is added by the flow-sensitivity launch, which reads the same
+ * stage inputs, and the adjoint stages skip the forward state: the per-cell
+ * terms are those of vfp_adjoint_stage, added in the same order.
+ * work: 3 ndofs doubles. */
 int vfp_adjoint_steps(vfp_ctx* ctx, const double* u0, const double* tape, double dt, int64_t nsteps,
                       double* mu, double* grad_nu, double* field_slots, double* work, void* stream);
 

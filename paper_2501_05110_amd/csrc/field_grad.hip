@@ -32,7 +32,10 @@
 // their shares of the slots through the same rows, and one lane adds each
 // slot's sum with an atomic add that nothing waits for (a slot receives one
 // add per launch, so launches in stream order give a reproducible sum).
-// fgrad_reduce sums the slots per x point.
+// fgrad_reduce sums the slots per x point.  Given a grad_nu array, the U part
+// also adds the stage's dJ/dnu term per cell (the collision pairing of the
+// same mu and forward state), so that a reverse sweep with both gradients
+// need not read the forward state in its adjoint stages.
 #include <type_traits>
 
 #include "basis.hpp"
@@ -97,7 +100,7 @@ template <int K, int LMAX, int PART>
 __device__ __forceinline__ void fgrad_body(const KernelArgs& A, const double* __restrict__ mu,
                                            const double* __restrict__ fwd, double cdt,
                                            double* __restrict__ slots, const unsigned char* __restrict__ support,
-                                           double* lds, int blk) {
+                                           double* __restrict__ grad_nu, double* lds, int blk) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int K1 = K + 1;
   constexpr int NB = K1 * K1;
@@ -389,6 +392,53 @@ __device__ __forceinline__ void fgrad_body(const KernelArgs& A, const double* __
         atomicAdd(&slots[(size_t)cell * NS + FR::slot(j)], cdt * sum);
       }
   }
+
+  // ---- dJ/dnu of the cell from the same pair (the U part runs on every
+  // cell): the collision term's pairing -cdt t_col sum_r c_r (M mu)_r . f_r,
+  // with (M mu) the reference mass (M1 x M1) applied to the lane's row and
+  // scaled by the cell's Jacobian; the products and their order are those
+  // of the adjoint stage's own accumulation, so either place gives the same
+  // per-cell term
+  if constexpr (PART == 0) {
+    if (grad_nu) {
+      double tm[NB], mm[NB];
+#pragma unroll
+      for (int i1 = 0; i1 < K1; ++i1)
+#pragma unroll
+        for (int i0 = 0; i0 < K1; ++i0) {
+          double a = 0.0;
+#pragma unroll
+          for (int j0 = 0; j0 < K1; ++j0) a = fma(CB::mass[i0][j0], m[j0 + K1 * i1], a);
+          tm[i0 + K1 * i1] = a;
+        }
+#pragma unroll
+      for (int i1 = 0; i1 < K1; ++i1)
+#pragma unroll
+        for (int i0 = 0; i0 < K1; ++i0) {
+          double a = 0.0;
+#pragma unroll
+          for (int j1 = 0; j1 < K1; ++j1) a = fma(CB::mass[i1][j1], tm[i0 + K1 * j1], a);
+          mm[i0 + K1 * i1] = a;
+        }
+      double part = 0.0;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) part = fma(mm[b], w[b], part);
+      part *= T.c_val[r] * jac;
+      if constexpr (N == 16) {
+        const double sum = row16_sum(part);
+        if (act && r == 0) atomicAdd(&grad_nu[cell], -cdt * F.t_col * sum);
+      } else {
+        wave_sync();
+        if (in_grp) X[r] = part;
+        wave_sync();
+        if (act && r == 0) {
+          double sum = 0.0;
+          for (int j = 0; j < N; ++j) sum += X[j];
+          atomicAdd(&grad_nu[cell], -cdt * F.t_col * sum);
+        }
+      }
+    }
+  }
 }
 
 // Both parts in one launch, spread evenly over the grid so that the two
@@ -403,7 +453,7 @@ template <int K, int LMAX>
 __global__ __launch_bounds__(kFgThreads) __attribute__((amdgpu_waves_per_eu(VFP_FG_WAVES)))
 void fgrad_kernel(KernelArgs A, const double* __restrict__ mu, const double* __restrict__ fwd, double cdt,
                   double* __restrict__ slots, const unsigned char* __restrict__ support,
-                  const int* __restrict__ p1_blocks, int nblk, int np1) {
+                  const int* __restrict__ p1_blocks, int nblk, int np1, double* __restrict__ grad_nu) {
   constexpr int N = (LMAX + 1) * (LMAX + 1);
   constexpr int CPB = (kFgThreads / N) > 0 ? kFgThreads / N : 1;
   constexpr int X0 = FgRows<K, 0>::XRW, X1 = FgRows<K, 1>::XRW;
@@ -411,10 +461,10 @@ void fgrad_kernel(KernelArgs A, const double* __restrict__ mu, const double* __r
   const long long total = (long long)nblk + np1, i = blockIdx.x;
   const int c0 = (int)(i * np1 / total), c1 = (int)((i + 1) * np1 / total);
   if (c1 > c0)
-    fgrad_body<K, LMAX, 1>(A, mu, fwd, cdt, slots, p1_blocks ? nullptr : support, lds,
+    fgrad_body<K, LMAX, 1>(A, mu, fwd, cdt, slots, p1_blocks ? nullptr : support, nullptr, lds,
                            p1_blocks ? p1_blocks[c0] : c0);
   else
-    fgrad_body<K, LMAX, 0>(A, mu, fwd, cdt, slots, support, lds, (int)i - c0);
+    fgrad_body<K, LMAX, 0>(A, mu, fwd, cdt, slots, support, grad_nu, lds, (int)i - c0);
 }
 
 // g_u, g_dudx, g_dudt at the nx (k+1) x Gauss points and g_uface at the nx+1
@@ -453,12 +503,12 @@ __global__ void fgrad_reduce_kernel(MeshArgs M, const double* __restrict__ slots
 
 template <int K, int LMAX>
 void launch_fg_t(const KernelArgs& a, const double* mu, const double* fwd, double cdt, double* slots,
-                 const unsigned char* support, const int* p1_blocks, int np1, hipStream_t s) {
+                 const unsigned char* support, const int* p1_blocks, int np1, double* grad_nu, hipStream_t s) {
   const int blocks = field_grad_tiles(a.mesh.ncells, LMAX);
   if (!p1_blocks) np1 = blocks;
   if (blocks + np1 == 0) return;
   hipLaunchKernelGGL((fgrad_kernel<K, LMAX>), dim3(blocks + np1), dim3(kFgThreads), 0, s, a, mu, fwd, cdt, slots,
-                     support, p1_blocks, blocks, np1);
+                     support, p1_blocks, blocks, np1, grad_nu);
 }
 
 template <int K>

@@ -51,10 +51,12 @@ int shock_cells_per_tile(int lmax);
 // x faces.
 // support: per x cell, 0 where the U' and dU/dt sensitivities are not
 // wanted (null: everywhere).  p1_blocks: the np1 tiles (field_grad_tiles
-// numbering) that hold a support cell, or null for every tile.
+// numbering) that hold a support cell, or null for every tile.  grad_nu:
+// per cell, receives the same dJ/dnu term the adjoint stage would add for
+// this (mu, fwd, cdt), or null.
 using FieldGradLauncher = void (*)(const KernelArgs&, const double* mu, const double* fwd, double cdt,
                                    double* slots, const unsigned char* support, const int* p1_blocks, int np1,
-                                   hipStream_t);
+                                   double* grad_nu, hipStream_t);
 using FieldGradReduce = void (*)(const MeshArgs&, const double* slots, double* g_u, double* g_du, double* g_a,
                                  double* g_uf, hipStream_t);
 FieldGradLauncher find_field_grad_launcher(int k, int lmax);

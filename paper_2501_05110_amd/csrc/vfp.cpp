@@ -1736,7 +1736,8 @@ static int ensure_pf_dk(vfp_ctx* c) {
   return VFP_OK;
 }
 
-static int launch_fg(vfp_ctx* c, const double* mu, const double* fwd, double cdt, double* slots, void* stream) {
+static int launch_fg(vfp_ctx* c, const double* mu, const double* fwd, double cdt, double* slots, double* grad_nu,
+                     void* stream) {
   FieldGradLauncher fl = find_field_grad_launcher(c->k, c->lmax);
   if (!fl) return fail(VFP_EUNSUPPORTED, "no field-gradient kernel for k=%d lmax=%d", c->k, c->lmax);
   if (int e = ensure_pf_dk(c)) return e;
@@ -1746,7 +1747,7 @@ static int launch_fg(vfp_ctx* c, const double* mu, const double* fwd, double cdt
   a.tab = c->tab;
   const bool listed = c->d_fg_support.as<unsigned char>() != nullptr;
   fl(a, mu, fwd, cdt, slots, c->d_fg_support.as<unsigned char>(), listed ? c->d_fg_blocks.as<int>() : nullptr,
-     listed ? c->fg_nblocks : 0, (hipStream_t)stream);
+     listed ? c->fg_nblocks : 0, grad_nu, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
   return VFP_OK;
 }
@@ -1800,7 +1801,7 @@ int vfp_field_grad_stage(vfp_ctx* c, const double* mu, const double* fwd, double
   vfp_ndofs(c, &N);
   vfp_field_grad_size(c, &ns);
   if (overlaps(slots, ns, mu, N) || overlaps(slots, ns, fwd, N)) return fail(VFP_EINVAL, "slots overlap an input");
-  return launch_fg(c, mu, fwd, cdt, slots, stream);
+  return launch_fg(c, mu, fwd, cdt, slots, nullptr, stream);
 }
 
 int vfp_field_grad_reduce(vfp_ctx* c, const double* slots, double* g_u, double* g_dudx, double* g_dudt,
@@ -1839,27 +1840,30 @@ int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double d
   double* acc = work;
   double* b1 = work + N;
   double* b2 = work + 2 * N;
+  // with the flow sensitivities the dJ/dnu term rides on their launch, which
+  // reads the same (adjoint, forward) pair anyway; the adjoint stages then
+  // do not read the forward state at all
+  double* gnu_fg = field_slots ? grad_nu : nullptr;
+  double* gnu_adj = field_slots ? nullptr : grad_nu;
+  // each flow-sensitivity launch pairs an adjoint stage input with its
+  // forward stage input, before the adjoint stage may overwrite it
+  auto stage = [&](const double* m_in, const double* a_in, double* a_out, double* t_out, const double* fw,
+                   const double* f_nu, double cdt) -> int {
+    if (field_slots)
+      if (int e = launch_fg(c, m_in, fw, cdt, field_slots, gnu_fg, stream)) return e;
+    return launch_adj(c, m_in, a_in, a_out, 1.0, cdt, t_out, f_nu, gnu_adj, 0, stream);
+  };
   for (int64_t s = nsteps - 1; s >= 0; --s) {
     const double* un = s == 0 ? u0 : tape + (4 * s - 1) * N;
     const double* w = tape + 4 * s * N;
-    const double* f3 = grad_nu ? w + 2 * N : nullptr;
-    const double* f2 = grad_nu ? w + N : nullptr;
-    const double* f1 = grad_nu ? w : nullptr;
-    const double* f0 = grad_nu ? un : nullptr;
-    // each field-gradient launch pairs an adjoint stage input with its
-    // forward stage input, before the adjoint stage may overwrite it
-    if (field_slots)
-      if (int e = launch_fg(c, mu, w + 2 * N, stage_cdt(3, dt), field_slots, stream)) return e;
-    if (int e = launch_adj(c, mu, mu, acc, 1.0, stage_cdt(3, dt), b1, f3, grad_nu, 0, stream)) return e;
-    if (field_slots)
-      if (int e = launch_fg(c, b1, w + N, stage_cdt(2, dt), field_slots, stream)) return e;
-    if (int e = launch_adj(c, b1, acc, acc, 1.0, stage_cdt(2, dt), b2, f2, grad_nu, 0, stream)) return e;
-    if (field_slots)
-      if (int e = launch_fg(c, b2, w, stage_cdt(1, dt), field_slots, stream)) return e;
-    if (int e = launch_adj(c, b2, acc, acc, 1.0, stage_cdt(1, dt), b1, f1, grad_nu, 0, stream)) return e;
-    if (field_slots)
-      if (int e = launch_fg(c, b1, un, stage_cdt(0, dt), field_slots, stream)) return e;
-    if (int e = launch_adj(c, b1, acc, mu, 1.0, stage_cdt(0, dt), nullptr, f0, grad_nu, 0, stream)) return e;
+    const double* f3 = gnu_adj ? w + 2 * N : nullptr;
+    const double* f2 = gnu_adj ? w + N : nullptr;
+    const double* f1 = gnu_adj ? w : nullptr;
+    const double* f0 = gnu_adj ? un : nullptr;
+    if (int e = stage(mu, mu, acc, b1, w + 2 * N, f3, stage_cdt(3, dt))) return e;
+    if (int e = stage(b1, acc, acc, b2, w + N, f2, stage_cdt(2, dt))) return e;
+    if (int e = stage(b2, acc, acc, b1, w, f1, stage_cdt(1, dt))) return e;
+    if (int e = stage(b1, acc, mu, nullptr, un, f0, stage_cdt(0, dt))) return e;
   }
   return VFP_OK;
 }

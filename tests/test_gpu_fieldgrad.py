@@ -365,3 +365,45 @@ def test_support_tiles_bit_identical(lib, cuda, nx, npc, k, lmax):
     assert np.any((rest == 0) & (ref != 0))
     assert np.abs(full[on][:, p1]).max() > 0
     op.close()
+
+
+@pytest.mark.parametrize("nx,npc,k,lmax", [(14, 5, 2, 3), (11, 4, 1, 2), (9, 3, 2, 1)])
+def test_nu_gradient_same_with_flow(lib, cuda, nx, npc, k, lmax):
+    """With the flow sensitivities requested, dJ/dnu per cell is formed in
+    their launch (which reads the same adjoint and forward stage inputs)
+    instead of in the adjoint stages: the adjoint state must come out
+    bit-identical and dJ/dnu equal to rounding (the per-cell products are the
+    same; only the order of the 16-lane sum may differ with the adjoint's
+    launch shape)."""
+    import torch
+    from paper_2501_05110_amd.vfp import Operator
+    wl = shock(nx, npc, k, lmax, seed=12, w_frac=0.05)
+    op = Operator(wl)
+    dt = op.cfl_dt(0.2)
+    n = 5
+    rng = np.random.default_rng(31)
+    N = op.ndofs
+    tz0 = torch.from_numpy(rng.standard_normal(N)).cuda()
+    g = torch.from_numpy(rng.standard_normal(N)).cuda()
+    tape = torch.empty(4 * n * N, dtype=torch.float64, device="cuda")
+    op.advance_tape(tz0, dt, n, tape)
+    out = {}
+    for mode in ("no_flow", "flow"):
+        _say(f"[nu/flow] {nx}x{npc} k={k} lmax={lmax} {mode}")
+        mu = g.clone()
+        op.mass(mu, mu, inverse=True)
+        work = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+        gnu = torch.zeros(op.ncells, dtype=torch.float64, device="cuda")
+        slots = torch.zeros(op.field_grad_size(), dtype=torch.float64, device="cuda") \
+            if mode != "no_flow" else torch.zeros(1, dtype=torch.float64, device="cuda")
+        op.adjoint_steps(tz0, tape, dt, n, mu, gnu, work, field_slots=slots if mode != "no_flow" else None)
+        torch.cuda.synchronize()
+        out[mode] = (mu.cpu().numpy(), gnu.cpu().numpy(), slots.cpu().numpy())
+    (m0, g0, _), (m1, g1, s1) = out["no_flow"], out["flow"]
+    assert np.array_equal(m0, m1)
+    assert np.abs(s1).max() > 0
+    scale = np.abs(g0).max()
+    assert scale > 0
+    err = np.abs(g1 - g0).max() / scale
+    _say(f"   max |dJ/dnu| {scale:.3e}, rel diff {err:.1e}")
+    assert err <= 1e-13
