@@ -262,7 +262,10 @@ class Grid:
         """Reference values at the (k+1)^d Gauss points: phi (Q, nb), dphi_ref
         (d, Q, nb), eta (d, Q), weights (Q,)."""
         bm = self.basis_multi()
-        qm = self.basis_multi()            # same multi-index shape for points
+        # point multi-indices of the rule (len(gq) points per axis, axis 0
+        # fastest, as the basis); the method's rule has k+1 points
+        nq = len(self.gq)
+        qm = np.indices((nq,) * self.d).reshape(self.d, -1)[::-1].T
         Q = len(qm)
         phi = np.ones((Q, self.nb))
         dphi = np.ones((self.d, Q, self.nb))
@@ -284,7 +287,7 @@ class Grid:
         (d, Qf) in this cell, weights (Qf,)."""
         bm = self.basis_multi()
         other = [a for a in range(self.d) if a != axis]
-        qm = (np.indices((self.K1,) * len(other)).reshape(len(other), -1)[::-1].T
+        qm = (np.indices((len(self.gq),) * len(other)).reshape(len(other), -1)[::-1].T
               if other else np.zeros((1, 0), int))
         Qf = qm.shape[0]
         phi_in = np.ones((Qf, self.nb))

@@ -633,3 +633,59 @@ def test_dsa_paper_setup_reduced():
     a, N = dsa_paper.index_and_normalisation(p, f)
     assert abs(a - 4) < 1e-2, a
     assert abs(N / 12 - 1) < 0.02, N
+
+
+def _poly_flow(c3):
+    """U = (0.15 + 0.02 x + c3 x^3, 0.1 + 0.015 y, 0.05): on [-2, 2]^2 both
+    in-plane components stay positive, and below the smallest nonzero
+    |lambda| V of the l_max = 2 systems at p = 1.3, so no upwind speed
+    changes sign inside a face."""
+    def flow(X):
+        x, y = X[0], X[1]
+        N = X.shape[1]
+        U = np.zeros((3, N))
+        dU = np.zeros((3, 3, N))
+        U[0] = 0.15 + 0.02 * x + c3 * x ** 3
+        U[1] = 0.1 + 0.015 * y
+        U[2] = 0.05
+        dU[0, 0] = 0.02 + 3 * c3 * x ** 2
+        dU[1, 1] = 0.015
+        a = np.einsum("an,abn->bn", U, dU)
+        return U, dU, a
+    flow.kind = ("points",)
+    return flow
+
+
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_gauss_rule_exact_for_polynomial_coefficients(k, monkeypatch):
+    """The quadrature of Sec. 3.2 (k+1 Gauss points per axis) integrates the
+    volume and face terms exactly when the coefficients are polynomials of
+    low degree: with a flow linear in x and y (and uniform B, constant nu)
+    every integrand has degree <= 2k+1 along each axis, so the assembled
+    operator must equal one assembled with a 12-point-richer rule.  A k-point
+    or a Gauss-Lobatto rule (exact to degree 2k-1) fails this.  With a cubic
+    term in U_x the volume integrand reaches degree 2k+2 and the two differ,
+    which shows the comparison sees the rule at all."""
+    terms = frozenset({W.ADVECTION, W.ROTATION, W.COLLISION})
+
+    def wl_for(flow):
+        return W.Workload(name="poly", lmax=2, k=k, axes=("x", "y"),
+                          nodes=(W.uniform_nodes(-2.0, 2.0, 5), W.uniform_nodes(-2.0, 2.0, 4)),
+                          bc=((W.ZERO_INFLOW, W.ZERO_INFLOW), (W.ZERO_INFLOW, W.ZERO_INFLOW)),
+                          terms=terms, p_fixed=1.3, flow=flow,
+                          magnetic=W.uniform_field((0.3, -0.2, 0.6)), nu=0.6)
+
+    orig = dg.gauss_rule
+    out = {}
+    for name, flow in (("linear", _poly_flow(0.0)), ("cubic", _poly_flow(0.004))):
+        wl = wl_for(flow)
+        monkeypatch.setattr(dg, "gauss_rule", orig)
+        S1 = dg.assemble(wl)
+        monkeypatch.setattr(dg, "gauss_rule", lambda q: orig(q + 12))
+        S2 = dg.assemble(wl)
+        scale = abs(S2.D).max()
+        out[name] = (abs(S1.D - S2.D).max() / scale, abs(S1.M - S2.M).max() / abs(S2.M).max())
+    monkeypatch.setattr(dg, "gauss_rule", orig)
+    assert out["linear"][0] <= 1e-13, out
+    assert out["linear"][1] <= 1e-14 and out["cubic"][1] <= 1e-14, out
+    assert out["cubic"][0] > 1e-8, out
