@@ -145,6 +145,9 @@ struct AdjArgs {
   const double* fwd;      // forward stage input paired with w_in for d/dnu, or null
   double* grad_nu;        // [cell] accumulated: -beta t_col sum C (M fwd) . w_in
   int mass_out;           // 1: multiply the result by the cell mass matrix
+  // (x, ln p) kernels only: a state added to w_out (null: none), and w_out
+  // may then be null to skip that output
+  const double* add_in;
 };
 
 struct KernelArgs {

@@ -730,11 +730,23 @@ __device__ __forceinline__ void shock_body(const KernelArgs& A, int blk) {
 #pragma unroll
     for (int b = 0; b < NB; ++b) uu[b] = use_u ? gp(A.st.u)[cbase + (size_t)b * N] : 0.0;
   }
-  if (act) {
+  // the adjoint may add one more state to its output (the reverse sweep's
+  // running sum, carried one stage late)
+  double ad[ADJ ? NB : 1];
+  bool use_ad = false;
+  if constexpr (ADJ) {
+    use_ad = gp(A.adj.add_in) != nullptr;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) ad[b] = use_ad ? gp(A.adj.add_in)[cbase + (size_t)b * N] : 0.0;
+  }
+  if (act && (!ADJ || gp(A.st.w_out))) {
     const double al = A.st.alpha, be = A.st.beta;
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
-      const double v = fma(be, res[b], al * uu[b]);
+      double v = fma(be, res[b], al * uu[b]);
+      if constexpr (ADJ) {
+        if (use_ad) v += ad[b];
+      }
 #if VFP_NT_STORE
       // the stage output is not read again in this launch: streaming stores
       // keep it from displacing the neighbour traces in L2

@@ -278,6 +278,7 @@ struct vfp_ctx {
   MeshArgs meshargs{};
   StageLauncher launcher = nullptr;
   StageLauncher adj_launcher = nullptr;
+  bool adj_shock = false;   // adj_launcher is the (x, ln p) kernel (AdjArgs::add_in available)
   MassLauncher mass_launcher = nullptr;
   HostPin h_kry;            // 3 kKryMaxVectors doubles: the Theta-method's per-iteration read-backs
   double beta_pmax = 0.0;   // spectral-radius bound of beta^{ln p} over p faces
@@ -985,6 +986,7 @@ int refresh(vfp_ctx* c, unsigned what) {
   if (!c->launcher) c->launcher = find_stage_launcher(c->naxes, c->k, c->lmax, c->mom, flow);
   c->adj_launcher = nullptr;
   if (shock_ok) c->adj_launcher = find_shock_adjoint_launcher(c->k, c->lmax, c->tab.nrot, c->linp);
+  c->adj_shock = c->adj_launcher != nullptr;
   if (!c->adj_launcher) c->adj_launcher = find_adjoint_launcher(c->naxes, c->k, c->lmax, c->mom, flow);
   c->mass_launcher = find_mass_launcher(c->naxes, c->k);
   // a small run on one axis with constant coefficients (uniform flow, fixed
@@ -1628,7 +1630,7 @@ int vfp_advance(vfp_ctx* c, double* u, double dt, int64_t nsteps, double* work, 
 
 static int launch_adj(vfp_ctx* c, const double* mu_in, const double* acc_in, double* acc_out, double alpha,
                       double beta, double* t_out, const double* fwd, double* grad_nu, int mass_out,
-                      void* stream) {
+                      void* stream, const double* add_in = nullptr) {
   if (!c->adj_launcher) return fail(VFP_EUNSUPPORTED, "no adjoint kernel for this configuration");
   KernelArgs a{};
   a.mesh = c->meshargs;
@@ -1644,6 +1646,7 @@ static int launch_adj(vfp_ctx* c, const double* mu_in, const double* acc_in, dou
   a.adj.fwd = fwd;
   a.adj.grad_nu = grad_nu;
   a.adj.mass_out = mass_out;
+  a.adj.add_in = add_in;
   a.tile_map = c->tile_map;
   c->adj_launcher(a, (hipStream_t)stream);
   HIP_TRY(hipGetLastError());
@@ -1848,11 +1851,17 @@ int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double d
   // each flow-sensitivity launch pairs an adjoint stage input with its
   // forward stage input, before the adjoint stage may overwrite it
   auto stage = [&](const double* m_in, const double* a_in, double* a_out, double* t_out, const double* fw,
-                   const double* f_nu, double cdt) -> int {
+                   const double* f_nu, double cdt, double alpha, const double* add_in) -> int {
     if (field_slots)
       if (int e = launch_fg(c, m_in, fw, cdt, field_slots, gnu_fg, stream)) return e;
-    return launch_adj(c, m_in, a_in, a_out, 1.0, cdt, t_out, f_nu, gnu_adj, 0, stream);
+    return launch_adj(c, m_in, a_in, a_out, alpha, cdt, t_out, f_nu, gnu_adj, 0, stream, add_in);
   };
+  // The running sum acc = lambda + t_4 + t_3 + ... starts one stage late
+  // where the kernel can add a state to its output: the last stage writes
+  // only t_4, and the next one forms lambda + t_4 + t_3 from lambda, its own
+  // input t_4 and its result (8 bytes per DoF less than writing lambda + t_4
+  // and reading it back).
+  const bool late = c->adj_shock;
   for (int64_t s = nsteps - 1; s >= 0; --s) {
     const double* un = s == 0 ? u0 : tape + (4 * s - 1) * N;
     const double* w = tape + 4 * s * N;
@@ -1860,10 +1869,15 @@ int vfp_adjoint_steps(vfp_ctx* c, const double* u0, const double* tape, double d
     const double* f2 = gnu_adj ? w + N : nullptr;
     const double* f1 = gnu_adj ? w : nullptr;
     const double* f0 = gnu_adj ? un : nullptr;
-    if (int e = stage(mu, mu, acc, b1, w + 2 * N, f3, stage_cdt(3, dt))) return e;
-    if (int e = stage(b1, acc, acc, b2, w + N, f2, stage_cdt(2, dt))) return e;
-    if (int e = stage(b2, acc, acc, b1, w, f1, stage_cdt(1, dt))) return e;
-    if (int e = stage(b1, acc, mu, nullptr, un, f0, stage_cdt(0, dt))) return e;
+    if (late) {
+      if (int e = stage(mu, nullptr, nullptr, b1, w + 2 * N, f3, stage_cdt(3, dt), 0.0, nullptr)) return e;
+      if (int e = stage(b1, mu, acc, b2, w + N, f2, stage_cdt(2, dt), 1.0, b1)) return e;
+    } else {
+      if (int e = stage(mu, mu, acc, b1, w + 2 * N, f3, stage_cdt(3, dt), 1.0, nullptr)) return e;
+      if (int e = stage(b1, acc, acc, b2, w + N, f2, stage_cdt(2, dt), 1.0, nullptr)) return e;
+    }
+    if (int e = stage(b2, acc, acc, b1, w, f1, stage_cdt(1, dt), 1.0, nullptr)) return e;
+    if (int e = stage(b1, acc, mu, nullptr, un, f0, stage_cdt(0, dt), 1.0, nullptr)) return e;
   }
   return VFP_OK;
 }
