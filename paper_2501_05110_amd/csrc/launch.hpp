@@ -119,6 +119,15 @@ hipError_t upload_basis(const Basis1D* b);
 // launch of one workgroup holding the state in LDS; u in place.
 using ResidentLauncher = void (*)(const KernelArgs&, double dt, long long nsteps, double* u, hipStream_t);
 ResidentLauncher find_resident_launcher(int k, int lmax);
+// The resident kernel keeps one item (cell, lms row) per thread, with the
+// item's rows in registers; it serves runs of at most kResidentItems items
+// whose face rows have at most kResFbCap (B) and kResFaCap<l_max> (|B|)
+// entries and whose rotation row at most kResRotCap.
+constexpr int kResidentItems = 1024;
+constexpr int kResFbCap = 4;
+template <int LMAX>
+constexpr int kResFaCap = LMAX + 2;
+constexpr int kResRotCap = 5;
 size_t resident_max_lds();
 hipError_t upload_basis_resident(const Basis1D* b);
 

@@ -997,7 +997,9 @@ int refresh(vfp_ctx* c, unsigned what) {
     const char* rv = std::getenv("VFP_RESIDENT");
     const bool allow = !(rv && std::atoi(rv) == 0);
     const size_t lds = (size_t)3 * c->ncells * c->nb * c->n * sizeof(double);
-    if (allow && c->naxes == 1 && !c->mom && !c->planar && !c->pflow && !c->have_Bpts && !c->have_nu_pts &&
+    const bool fits = (int64_t)c->ncells * c->n <= kResidentItems && c->tab.nfb[0] <= kResFbCap &&
+                      c->tab.nfa[0] <= c->lmax + 2 && c->tab.nrot <= kResRotCap;
+    if (allow && fits && c->naxes == 1 && !c->mom && !c->planar && !c->pflow && !c->have_Bpts && !c->have_nu_pts &&
         c->lmax <= kShFullMaxLmax && lds <= resident_max_lds())
       c->resident = find_resident_launcher(c->k, c->lmax);
   }
